@@ -1,0 +1,124 @@
+"""Method vs truth: the oracle's point-charge sums (Sec. 4, Eq. 4.1) against the
+double-Gauss-Legendre reference (GL2, Sec. 2) on random elements, the procedure of
+Sec. 2/Sec. 4: corners random in the unit cube, field point at a fixed distance ratio in
+a random direction from the centroid, errors averaged over many elements.
+
+Pins: the distance-ratio limits the paper gives for a 2e-15 triangle-potential
+accuracy (tests/golden/dr_limits_sec4.json), and the error decay with DR that a rule of
+degree d must show (the multipole moments up to order d are exact, so the error falls
+like DR^-(d+2) for the potential).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import ref_integrals as R
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "dr_limits_sec4.json")))
+
+
+def random_triangle(rng):
+    return rng.random(9)
+
+
+def random_rectangle(rng):
+    P0 = rng.random(3)
+    e1 = rng.standard_normal(3)
+    e1 *= rng.uniform(0.2, 1.0) / np.linalg.norm(e1)
+    t = rng.standard_normal(3)
+    e2 = t - np.dot(t, e1) / np.dot(e1, e1) * e1
+    e2 *= rng.uniform(0.2, 1.0) / np.linalg.norm(e2)
+    return np.concatenate([P0, e1, e2])
+
+
+def point_at_dr(orc, kind, g, dr, rng):
+    c, _, L = orc.element_geometry(kind, g)
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    return c + dr * L * d
+
+
+def mean_errors(orc, kind, rule_prm, dr, n_el, seed):
+    rng = np.random.default_rng(seed)
+    ep, ee = [], []
+    for _ in range(n_el):
+        g = random_triangle(rng) if kind == 0 else random_rectangle(rng)
+        P = point_at_dr(orc, kind, g, dr, rng)
+        got, _ = orc.element(kind, g, P, rule_prm, mode=0)
+        ref = R.gl2(kind, g, P, n=40)
+        ep.append(R.rel_err_phi(got, ref))
+        ee.append(R.rel_err_E(got, ref))
+    return float(np.mean(ep)), float(np.mean(ee))
+
+
+@pytest.mark.parametrize("n", [4, 7, 12, 19, 33])
+def test_triangle_rules_reach_paper_accuracy_at_their_dr_limit(orc, n):
+    """Sec. 4: rule N reaches ~2e-15 for the triangle potential above its DR limit.
+    Random elements differ from the paper's sample, so allow a factor 3."""
+    dr = GOLD["triangle_potential_lower_dr"][str(n)]
+    prm = orc.params(tri_rule=n)
+    ep, ee = mean_errors(orc, 0, prm, dr, 60, 100 + n)
+    assert ep < 3.0 * GOLD["level"], ep
+    # the field limits are "slightly higher": at twice the potential's limit the field
+    # error is at the few-1e-15 level as well
+    _, ee2 = mean_errors(orc, 0, prm, 2 * dr, 60, 200 + n)
+    assert ee2 < 1e-14, ee2
+
+
+@pytest.mark.parametrize("n,d", [(7, 5), (12, 7), (19, 9), (33, 12)])
+def test_triangle_error_decays_with_degree(orc, n, d):
+    """Halving DR well above the rounding floor raises the potential error by about
+    2^(d+2); require at least 2^(d+0.5) so that a rule of lower degree fails."""
+    prm = orc.params(tri_rule=n)
+    lim = GOLD["triangle_potential_lower_dr"][str(n)]
+    dr_hi = max(2.0, lim / 8.0)
+    e_hi, _ = mean_errors(orc, 0, prm, dr_hi, 40, 300 + n)
+    e_lo, _ = mean_errors(orc, 0, prm, dr_hi / 2.0, 40, 300 + n)
+    assert e_lo / e_hi > 2.0 ** (d + 0.5), (e_lo, e_hi)
+
+
+def test_rectangle_gauss_7x7_accuracy(orc):
+    """Tensor Gauss-Legendre 7x7 (degree 13 per axis): near the double-precision floor
+    from DR 8 on, and below 1e-12 at the near-field threshold DR 3."""
+    prm = orc.params(rect_gl_n=7)
+    ep3, ee3 = mean_errors(orc, 1, prm, 3.0, 60, 7)
+    ep8, ee8 = mean_errors(orc, 1, prm, 8.0, 60, 8)
+    assert ep3 < 1e-12 and ee3 < 3e-11, (ep3, ee3)
+    assert ep8 < 2e-15 and ee8 < 1e-14, (ep8, ee8)
+
+
+@pytest.mark.parametrize("n", [7, 12, 17, 33])
+def test_rectangle_tables_converge(orc, n):
+    """The App. B rules reach the rounding floor at large DR (Sec. 4, rectangle figures)."""
+    prm = orc.params(rect_gl_n=0, rect_table_n=n)
+    ep, ee = mean_errors(orc, 1, prm, 2000.0, 40, 50 + n)
+    assert ep < 2e-15 and ee < 2e-14, (ep, ee)
+
+
+def test_duffy_triangle_is_worse_than_triangle_rule(orc):
+    """Sec. 4 remark: mapping the triangle to a square (Duffy) and using the 7-point
+    rectangle rule gives much larger errors at DR 100 than the 7-point triangle rule
+    (the paper quotes ~1e-8 against a few 1e-15; the size of the Duffy error depends on
+    the exact mapping, so only the ordering is pinned)."""
+    rng = np.random.default_rng(5)
+    xy, w = orc.rect_rule(0, 7)
+    errs_duffy, errs_tri = [], []
+    for _ in range(40):
+        g = random_triangle(rng)
+        P = point_at_dr(orc, 0, g, 100.0, rng)
+        A, B, C = g[0:3], g[3:6], g[6:9]
+        u, v = 0.5 * (xy[:, 0] + 1.0), 0.5 * (xy[:, 1] + 1.0)
+        Q = A + u[:, None] * (B - A) + (u * v)[:, None] * (C - B)
+        area2 = np.linalg.norm(np.cross(B - A, C - A))
+        wt = w * u * area2 / 2.0 * 2.0  # w sums to 1 over the unit square; dA = 2 area u du dv
+        d = P - Q
+        r = np.linalg.norm(d, axis=1)
+        got = np.concatenate([[np.sum(wt / r)], np.sum((wt / r ** 3)[:, None] * d, axis=0)])
+        ref = R.gl2(0, g, P, n=40)
+        errs_duffy.append(R.rel_err_E(got, ref))
+        got_t, _ = orc.element(0, g, P, orc.params(tri_rule=7), mode=0)
+        errs_tri.append(R.rel_err_E(got_t, ref))
+    assert np.mean(errs_tri) < 1e-13
+    assert np.mean(errs_duffy) > 1e3 * np.mean(errs_tri)
