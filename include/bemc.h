@@ -1,0 +1,215 @@
+/*
+ * bemc.h -- C ABI of the MI355X (gfx950) library for the electric potential and field
+ * of charged BEM triangles and rectangles by Gaussian cubature
+ * (F. Glueck, D. Hilk, arXiv:1606.03743).
+ *
+ * Method.  An element of constant charge density sigma is replaced by the point charges
+ * q_i = w_i * sigma * area at the Gaussian points Q_i of a cubature rule (Sec. 4,
+ * Eq. 4.1), and the potential and field at a field point P are the sums
+ *     phi(P) = K sum_i q_i / |P - Q_i|,    E(P) = K sum_i q_i (P - Q_i) / |P - Q_i|^3,
+ * K = 1 / (4 pi eps0) (SI units, Sec. 2 Eq. 2.1), both from the same points (Sec. 4).
+ * Gaussian points come from barycentric coordinates for triangles (Eq. 3.3, rules of
+ * Tables A1-A5) and from natural coordinates for rectangles (Eq. 3.2, tensor
+ * Gauss-Legendre n x n).  Contributions of all elements are summed per field point
+ * (Sec. 5: "integrating field solver").  The distance ratio DR = D / L, D = |P - centroid|,
+ * L = average side length (Sec. 2), selects the path: for DR >= near_dr (3 by default,
+ * the limit below which the paper's rules are not accurate enough, Sec. 1 and Sec. 4) the
+ * rule is applied directly; below it the element is subdivided recursively (triangle:
+ * four midpoint children; rectangle: 2 x 2) until every child is at DR >= near_dr of its
+ * own, in FP64.  A field point lying on an element is integrated exactly in polar
+ * coordinates about the point (principal value for the in-plane field, zero normal part).
+ *
+ * Conventions.
+ *   * All entry points return BEMC_OK (0), a negative BEMC_E_* error, or (bemc_eval
+ *     only) the positive warning BEMC_W_ON_SURFACE.  On error, bemc_last_error() gives a
+ *     message for the calling thread.  No entry point aborts the process.
+ *   * "device" pointers are GPU memory of the context's device (e.g. torch tensors on
+ *     cuda:N); "host" pointers are ordinary CPU memory.  The caller owns every buffer it
+ *     passes; the library copies host inputs before returning.
+ *   * stream arguments are hipStream_t (void* here so that the header needs no HIP
+ *     include); NULL means the default stream.  Work is enqueued on that stream.
+ *   * Element input format (host, FP64, row-major, 9 doubles per element):
+ *       triangle  = A, B, C                      (vertices)
+ *       rectangle = P0, e1, e2                   (corner and the two side vectors;
+ *                                                 |e1| = a is the x side of Eq. 3.2)
+ *     Global element index: triangles 0 .. n_tri-1, then rectangles.
+ *   * Field points and fields are SoA on the device: pts[3][n] = x[n], y[n], z[n];
+ *     E[3][n] likewise.  Units: metres, C/m^2, volts, V/m.
+ *   * One context may be used from one host thread at a time.
+ */
+#ifndef BEMC_H
+#define BEMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BEMC_OK 0
+#define BEMC_E_INVALID_ARG -1
+#define BEMC_E_DEGENERATE_ELEMENT -2 /* zero area or zero side length */
+#define BEMC_E_NOT_RECTANGLE -3      /* |e1 . e2| > 1e-10 |e1| |e2| */
+#define BEMC_E_NONFINITE -4          /* NaN or Inf in the geometry or densities */
+#define BEMC_E_NO_GEOMETRY -5        /* evaluation before bemc_upload_geometry/densities */
+#define BEMC_E_OUT_OF_MEMORY -6
+#define BEMC_E_ADMISSION -7          /* serving: the query can never fit the memory budget */
+#define BEMC_E_DEVICE -8             /* a HIP call failed; message in bemc_last_error() */
+#define BEMC_E_LIMIT -9              /* a size exceeds the library's index range */
+#define BEMC_W_ON_SURFACE 1          /* warning: some field point lies on an element */
+
+/* precision of the bulk point-charge sums */
+#define BEMC_FP64 0  /* everything in FP64 */
+#define BEMC_MIXED 1 /* far-field node sums in FP32 (offsets from the element centroid,
+                        FP32 reciprocal square root), per-element partial sums scaled by
+                        the element charge and accumulated per field point in FP64; the
+                        distance-ratio classification, the near field and on-element
+                        integrals stay FP64 */
+
+typedef struct bemc_context* bemc_handle;
+
+/* Counters of the last bemc_eval / bemc_collocation_matvec on a context. */
+typedef struct {
+    int64_t pairs;          /* field points x elements */
+    int64_t node_interactions; /* point-charge terms of the far-field sums */
+    int64_t near_pairs;     /* pairs with D < near_dr * L (handled in FP64) */
+    int64_t leaves;         /* rule applications made by the subdivision */
+    int64_t cap_hits;       /* leaves still near at the depth cap */
+    int64_t on_surface;     /* pairs whose field point lies on the element */
+    int64_t max_depth;      /* deepest subdivision level reached */
+    int64_t near_capacity;  /* current size of the near-pair list */
+    double far_ms;          /* far-field kernel time (HIP events) */
+    double near_ms;         /* near-field kernel time (HIP events) */
+} bemc_stats;
+
+/* Message for the last non-OK status returned to this host thread ("" if none). */
+const char* bemc_last_error(void);
+
+/* Create a context on HIP device `device`; *out receives the handle.  Default rules:
+ * 33-point triangle rule (Table A5), 7 x 7 Gauss-Legendre for rectangles, near_dr 3,
+ * max_depth 24.  Errors: INVALID_ARG (no such device, out NULL), DEVICE. */
+int bemc_create(int device, bemc_handle* out);
+
+/* Release every device buffer of the context (waits for its pending work). */
+int bemc_destroy(bemc_handle h);
+
+/* Cubature rules and near-field parameters (Sec. 3, Tables A1-A5; Sec. 4 distance-ratio
+ * switch).  tri_rule in {4, 7, 12, 19, 33}; rect_gl_n in 1..16 (rect_gl_n^2 points);
+ * near_dr > 0 (pairs with D < near_dr * L are subdivided); max_depth in 0..30.
+ * Takes effect for subsequent uploads and evaluations; node tables are rebuilt.
+ * Errors: INVALID_ARG. */
+int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, int max_depth);
+
+/* Upload the electrode geometry (host arrays in the element input format; either count
+ * may be 0, n_tri + n_rect < 2^31).  Validates every element (finite, positive area,
+ * orthogonal rectangle sides), computes centroids, areas, average side lengths L
+ * (triangle (a + b + c)/3, Sec. 2; rectangle (a + b)/2), normals and the centroid
+ * offsets used for node generation, and keeps them resident on the device.  Previously
+ * uploaded densities are discarded.  Synchronous with respect to `stream`.
+ * Errors: INVALID_ARG, NONFINITE, DEGENERATE_ELEMENT (index in the message),
+ * NOT_RECTANGLE, LIMIT, OUT_OF_MEMORY, DEVICE. */
+int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri,
+                         const double* rect, int64_t n_rect, void* stream);
+
+/* Upload charge densities sigma[n_rhs][n_E] (C/m^2), 1 <= n_rhs <= 8, from host memory
+ * (sigma_on_device = 0) or device memory (1).  Element charges q = sigma * area are
+ * formed on the device.  Errors: NO_GEOMETRY, INVALID_ARG, NONFINITE (host input only),
+ * OUT_OF_MEMORY, DEVICE. */
+int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sigma_on_device,
+                          void* stream);
+
+/* Potential phi[n] (device) and, if E is not NULL, field E[3][n] (device) at the n field
+ * points pts[3][n] (device), from density vector `rhs` (0 <= rhs < n_rhs).  Outputs are
+ * overwritten.  precision = BEMC_FP64 or BEMC_MIXED.  n = 0 is a no-op.
+ * The call enqueues the far-field kernel (classification, near-pair compaction and the
+ * point-charge sums) and the FP64 near-field kernel on `stream` and returns after both
+ * have finished (it waits on the host for the near-pair count: when the near-pair list
+ * overflowed, the list is grown and the evaluation repeated).  Returns BEMC_W_ON_SURFACE
+ * when a field point lies on an element (its field there is the principal value).
+ * Errors: NO_GEOMETRY, INVALID_ARG, LIMIT (n >= 2^31, or a near pair needed more than
+ * 2^22 subdivision steps), OUT_OF_MEMORY, DEVICE. */
+int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
+              double* phi, double* E, void* stream);
+
+/* Matrix-free collocation product (BEM system matrix times densities, Sec. 5: the
+ * matrix is never stored): out[r][i] = potential at the centroid of element i from the
+ * densities sigma[r][:], r < n_rhs (1..8), for every element i.  sigma and out are device
+ * arrays [n_rhs][n_E].  The element's own contribution is its exact on-element integral;
+ * neighbours below near_dr are subdivided in FP64.  precision as in bemc_eval (far pairs
+ * only).  Independent of the densities of bemc_upload_densities.  Returns after the work
+ * has finished, like bemc_eval.  Errors: NO_GEOMETRY, INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision,
+                            double* out, void* stream);
+
+/* Pre-size the near-pair list (entries of 8 bytes).  The list also grows by itself when an
+ * evaluation finds more near pairs than it holds (the evaluation is then repeated), so
+ * this only avoids that repetition.  Errors: INVALID_ARG, OUT_OF_MEMORY. */
+int bemc_set_near_capacity(bemc_handle h, int64_t pairs);
+
+/* Counters of the last evaluation.  Errors: INVALID_ARG. */
+int bemc_query_stats(bemc_handle h, bemc_stats* out);
+
+/* ---------------------------------------------------------------------------------
+ * Serving: continuous batching of field-point queries against the resident geometry
+ * and densities (density vector 0), mixed or FP64 precision.
+ *
+ * bemc_server_start launches a host scheduler thread that owns `n_streams` HIP streams
+ * (default priority).  Submitted queries wait in arrival order; whenever a stream is
+ * free the scheduler admits waiting queries in order while their points fit into
+ * max_batch_points and the device memory budget, packs them into one batch (one far-
+ * field launch over all their points, element-split when the batch is small so the GPU
+ * stays full; fixed-order reduction of the element chunks; then the FP64 near field)
+ * and copies each query's results to its host buffers when the batch completes.
+ * Batches on different streams overlap on the device.  A query's result does not
+ * depend on the other queries in its batch beyond the order of floating-point atomic
+ * additions in the near field.
+ * --------------------------------------------------------------------------------- */
+
+typedef struct {
+    size_t mem_budget_bytes;   /* device bytes for in-flight batch buffers */
+    int64_t max_batch_points;  /* points per batch (>= the largest admissible query) */
+    int n_streams;             /* 1..8 concurrent batches */
+    int precision;             /* BEMC_FP64 or BEMC_MIXED */
+} bemc_server_config;
+
+typedef struct {
+    int done;                  /* 1 once results are in the host buffers */
+    int status;                /* BEMC_OK or an error for this query */
+    double submit_s, start_s, end_s; /* host clock (s since server start): submission,
+                                        launch of its batch, results in host memory */
+    int64_t batch_id;          /* batch the query ran in */
+    int64_t batch_points;      /* points of that batch */
+} bemc_query_info;
+
+/* Start serving on the context (geometry and densities must be uploaded).
+ * Errors: NO_GEOMETRY, INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+int bemc_server_start(bemc_handle h, const bemc_server_config* cfg);
+
+/* Submit a query: pts_host[n][3] (host, AoS), results to phi_host[n] and, if not NULL,
+ * E_host[n][3] (host, AoS).  Host buffers must stay valid until the query is done.
+ * Never blocks.  *ticket receives the query id.  Errors: INVALID_ARG, ADMISSION (the
+ * query can never fit the budget or max_batch_points; returned at once). */
+int bemc_server_submit(bemc_handle h, const double* pts_host, int64_t n, double* phi_host,
+                       double* E_host, uint64_t* ticket);
+
+/* Non-blocking status of a query.  Errors: INVALID_ARG (unknown ticket). */
+int bemc_server_poll(bemc_handle h, uint64_t ticket, bemc_query_info* info);
+
+/* Block until the query is done (timeout_s < 0: no limit).  Returns its status, or
+ * BEMC_E_INVALID_ARG for an unknown ticket or when the timeout expired. */
+int bemc_server_wait(bemc_handle h, uint64_t ticket, double timeout_s, bemc_query_info* info);
+
+/* Finish all submitted queries, stop the scheduler and free the batch buffers. */
+int bemc_server_stop(bemc_handle h);
+
+/* Library facts for tests and tools: the Coulomb constant used, and the node count of
+ * the triangle rule n (-1 if unknown). */
+double bemc_coulomb_constant(void);
+int bemc_rule_size(int tri_rule);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEMC_H */

@@ -1,0 +1,561 @@
+// Host runtime and C ABI of the GPU library (see include/bemc.h).
+#include "bemc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bemc_internal.h"
+#include "server.h"
+
+using namespace bemc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return BEMC_OK;
+}
+
+#define HIP_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(BEMC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <typename T>
+void dev_free(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct bemc_context {
+    int device = 0;
+    int tri_rule = 33, rect_gl_n = 7, max_depth = 24;
+    double near_dr = 3.0;
+
+    // rule tables (device)
+    double *d_tri = nullptr, *d_rect = nullptr;
+    float *d_tri32 = nullptr, *d_rect32 = nullptr;
+    int nt = 0, nr = 0;
+
+    // elements (device)
+    int64_t n_tri = 0, n_rect = 0, ne = 0;
+    std::vector<double> h_area, h_L;  // host copies
+    double *d_geom = nullptr, *d_cen = nullptr, *d_thr2 = nullptr, *d_off = nullptr, *d_L = nullptr,
+           *d_area = nullptr, *d_nrm = nullptr, *d_q = nullptr, *d_qc = nullptr;
+    float* d_off32 = nullptr;
+    int n_rhs = 0;
+    bool have_geometry = false;
+
+    // near-pair list and counters
+    NearPair* d_near = nullptr;
+    unsigned long long near_cap = 0;
+    DevCounters* d_ctr = nullptr;
+    DevCounters* h_ctr = nullptr;  // pinned
+    hipEvent_t ev[4] = { nullptr, nullptr, nullptr, nullptr };
+    bemc_stats last{};
+
+    bemc::Server* server = nullptr;
+
+    int set_rules_tables();
+    int ensure_near_capacity(unsigned long long need);
+    Elements elements() const;
+    RuleTables rules() const;
+    int run(bool colloc, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
+            double* E, hipStream_t s);
+};
+
+Elements bemc_context::elements() const
+{
+    Elements e{};
+    e.geom = d_geom; e.cen = d_cen; e.thr2 = d_thr2; e.off = d_off; e.off32 = d_off32; e.L = d_L;
+    e.area = d_area; e.nrm = d_nrm; e.q = d_q; e.ne = ne; e.n_tri = (int)n_tri; e.n_rhs = n_rhs;
+    return e;
+}
+
+RuleTables bemc_context::rules() const
+{
+    RuleTables r{};
+    r.tri = d_tri; r.rect = d_rect; r.tri32 = d_tri32; r.rect32 = d_rect32; r.nt = nt; r.nr = nr;
+    return r;
+}
+
+int bemc_context::set_rules_tables()
+{
+    std::vector<TriNode> tn;
+    std::vector<RectNode> rn;
+    if (!triangle_rule(tri_rule, tn)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
+    if (!rectangle_gauss_rule(rect_gl_n, rn)) return fail(BEMC_E_INVALID_ARG, "invalid rectangle Gauss order %d", rect_gl_n);
+    std::vector<double> t64(4 * tn.size()), r64(4 * rn.size());
+    std::vector<float> t32(t64.size()), r32(r64.size());
+    for (size_t i = 0; i < tn.size(); ++i) {
+        t64[4 * i] = tn[i].la; t64[4 * i + 1] = tn[i].lb; t64[4 * i + 2] = tn[i].lc; t64[4 * i + 3] = tn[i].w;
+    }
+    for (size_t i = 0; i < rn.size(); ++i) {
+        r64[4 * i] = rn[i].x; r64[4 * i + 1] = rn[i].y; r64[4 * i + 2] = rn[i].w; r64[4 * i + 3] = 0.0;
+    }
+    for (size_t i = 0; i < t64.size(); ++i) t32[i] = (float)t64[i];
+    for (size_t i = 0; i < r64.size(); ++i) r32[i] = (float)r64[i];
+    HIP_TRY(hipSetDevice(device));
+    dev_free(d_tri); dev_free(d_rect); dev_free(d_tri32); dev_free(d_rect32);
+    HIP_TRY(dev_alloc(&d_tri, t64.size()));
+    HIP_TRY(dev_alloc(&d_rect, r64.size()));
+    HIP_TRY(dev_alloc(&d_tri32, t32.size()));
+    HIP_TRY(dev_alloc(&d_rect32, r32.size()));
+    HIP_TRY(hipMemcpy(d_tri, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_rect, r64.data(), r64.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_tri32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_rect32, r32.data(), r32.size() * 4, hipMemcpyHostToDevice));
+    nt = (int)tn.size();
+    nr = (int)rn.size();
+    return ok();
+}
+
+int bemc_context::ensure_near_capacity(unsigned long long need)
+{
+    if (need <= near_cap) return ok();
+    unsigned long long cap = std::max<unsigned long long>(need, 1ull << 20);
+    cap = cap + cap / 4;
+    dev_free(d_near);
+    if (dev_alloc(&d_near, (size_t)cap) != hipSuccess) {
+        near_cap = 0;
+        (void)hipGetLastError();
+        return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list of %llu entries", cap);
+    }
+    near_cap = cap;
+    return ok();
+}
+
+int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc,
+                      double* phi, double* E, hipStream_t s)
+{
+    HIP_TRY(hipSetDevice(device));
+    if (near_cap == 0) {
+        int rc = ensure_near_capacity(std::max<unsigned long long>(1ull << 20, (unsigned long long)(colloc ? ne : n) * 8));
+        if (rc) return rc;
+    }
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        FarArgs fa{};
+        fa.el = elements(); fa.rules = rules();
+        if (colloc) { fa.el.q = d_qc; fa.el.n_rhs = n_rhs_colloc; } fa.pts = pts; fa.n = colloc ? ne : n; fa.rhs = rhs;
+        fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant(); fa.phi = phi; fa.E = E; fa.partial = nullptr;
+        fa.elem_begin = 0; fa.elem_end = ne; fa.n_split = 1; fa.chunk = ne; fa.near_list = d_near; fa.near_cap = near_cap;
+        fa.ctr = d_ctr;
+        NearArgs na{};
+        na.el = fa.el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = fa.n; na.rhs = rhs;
+        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.near_list = d_near; na.near_cap = near_cap;
+        na.ctr = d_ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
+
+        HIP_TRY(launch_zero_counters(d_ctr, s));
+        HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(colloc ? launch_far_colloc(fa, precision, s) : launch_far_eval(fa, precision, s));
+        HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(launch_near(na, colloc, s));
+        HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(hipMemcpyAsync(h_ctr, d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(ev[3], s));
+        HIP_TRY(hipEventSynchronize(ev[3]));
+        const unsigned long long found = h_ctr->near_count;
+        if (found > near_cap) {  // list overflowed: grow it and evaluate again
+            int rc = ensure_near_capacity(found);
+            if (rc) return rc;
+            continue;
+        }
+        float far_ms = 0.f, near_ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&far_ms, ev[0], ev[1]));
+        HIP_TRY(hipEventElapsedTime(&near_ms, ev[1], ev[2]));
+        last = bemc_stats{};
+        const int64_t npts = colloc ? ne : n;
+        last.pairs = npts * ne;
+        last.node_interactions = npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
+        last.near_pairs = (int64_t)found;
+        last.leaves = (int64_t)h_ctr->leaves;
+        last.cap_hits = (int64_t)h_ctr->cap_hits;
+        last.on_surface = (int64_t)h_ctr->on_surface;
+        last.max_depth = (int64_t)h_ctr->max_depth;
+        last.near_capacity = (int64_t)near_cap;
+        last.far_ms = far_ms;
+        last.near_ms = near_ms;
+        if (h_ctr->visit_limit_hits)
+            return fail(BEMC_E_LIMIT, "%llu near pairs hit the subdivision visit limit", h_ctr->visit_limit_hits);
+        if (!colloc && h_ctr->on_surface) {
+            g_last_error = "some field points lie on an element (principal-value field)";
+            return BEMC_W_ON_SURFACE;
+        }
+        return ok();
+    }
+    return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list kept overflowing");
+}
+
+// ======================================================================= C ABI ====
+extern "C" {
+
+const char* bemc_last_error(void) { return g_last_error.c_str(); }
+
+double bemc_coulomb_constant(void) { return coulomb_constant(); }
+
+int bemc_rule_size(int tri_rule)
+{
+    std::vector<TriNode> t;
+    return triangle_rule(tri_rule, t) ? (int)t.size() : -1;
+}
+
+int bemc_create(int device, bemc_handle* out)
+{
+    if (!out) return fail(BEMC_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(BEMC_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(BEMC_E_INVALID_ARG, "device %d of %d", device, ndev);
+    bemc_context* h = new bemc_context();
+    h->device = device;
+    int rc = h->set_rules_tables();
+    if (rc) { bemc_destroy(h); return rc; }
+    if (dev_alloc(&h->d_ctr, 1) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->h_ctr), sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+        bemc_destroy(h);
+        return fail(BEMC_E_OUT_OF_MEMORY, "counter buffers");
+    }
+    for (auto& e : h->ev)
+        if (hipEventCreate(&e) != hipSuccess) { bemc_destroy(h); return fail(BEMC_E_DEVICE, "hipEventCreate"); }
+    *out = h;
+    return ok();
+}
+
+static void free_elements(bemc_context* h)
+{
+    dev_free(h->d_geom); dev_free(h->d_cen); dev_free(h->d_thr2); dev_free(h->d_off); dev_free(h->d_off32);
+    dev_free(h->d_L); dev_free(h->d_area); dev_free(h->d_nrm); dev_free(h->d_q); dev_free(h->d_qc);
+    h->n_rhs = 0;
+    h->have_geometry = false;
+}
+
+int bemc_destroy(bemc_handle h)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (h->server) bemc_server_stop(h);
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    free_elements(h);
+    dev_free(h->d_tri); dev_free(h->d_rect); dev_free(h->d_tri32); dev_free(h->d_rect32);
+    dev_free(h->d_near); dev_free(h->d_ctr);
+    if (h->h_ctr) (void)hipHostFree(h->h_ctr);
+    for (auto& e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+    return ok();
+}
+
+int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, int max_depth)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "rules cannot change while serving");
+    if (!(near_dr > 0.0) || !std::isfinite(near_dr)) return fail(BEMC_E_INVALID_ARG, "near_dr must be > 0");
+    if (max_depth < 0 || max_depth > 30) return fail(BEMC_E_INVALID_ARG, "max_depth must be in 0..30");
+    std::vector<TriNode> t;
+    if (!triangle_rule(tri_rule, t)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
+    if (rect_gl_n < 1 || rect_gl_n > 16) return fail(BEMC_E_INVALID_ARG, "rect_gl_n must be in 1..16");
+    const int old_t = h->tri_rule, old_r = h->rect_gl_n;
+    h->tri_rule = tri_rule;
+    h->rect_gl_n = rect_gl_n;
+    int rc = h->set_rules_tables();
+    if (rc) { h->tri_rule = old_t; h->rect_gl_n = old_r; return rc; }
+    const double old_dr = h->near_dr;
+    h->near_dr = near_dr;
+    h->max_depth = max_depth;
+    if (h->have_geometry && old_dr != near_dr) {  // thresholds (near_dr L)^2 depend on near_dr
+        std::vector<double> thr(h->h_L.size());
+        for (size_t i = 0; i < thr.size(); ++i) thr[i] = (near_dr * h->h_L[i]) * (near_dr * h->h_L[i]);
+        HIP_TRY(hipSetDevice(h->device));
+        HIP_TRY(hipMemcpy(h->d_thr2, thr.data(), thr.size() * 8, hipMemcpyHostToDevice));
+    }
+    return ok();
+}
+
+int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
+                         void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "geometry cannot change while serving");
+    if (n_tri < 0 || n_rect < 0) return fail(BEMC_E_INVALID_ARG, "negative element count");
+    if ((n_tri > 0 && !tri) || (n_rect > 0 && !rect)) return fail(BEMC_E_INVALID_ARG, "null geometry pointer");
+    const int64_t ne = n_tri + n_rect;
+    if (ne >= (1ll << 31)) return fail(BEMC_E_LIMIT, "too many elements (%lld)", (long long)ne);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    std::vector<double> geom(9 * (size_t)ne), cen(3 * (size_t)ne), thr2((size_t)ne), off(9 * (size_t)ne, 0.0),
+        L((size_t)ne), area((size_t)ne), nrm(3 * (size_t)ne);
+    std::vector<float> off32(9 * (size_t)ne, 0.0f);
+    auto at = [ne](std::vector<double>& v, int comp, int64_t e) -> double& { return v[(size_t)comp * ne + e]; };
+    for (int64_t e = 0; e < ne; ++e) {
+        const bool is_tri = e < n_tri;
+        const double* g = is_tri ? tri + 9 * e : rect + 9 * (e - n_tri);
+        for (int c = 0; c < 9; ++c) {
+            if (!std::isfinite(g[c])) return fail(BEMC_E_NONFINITE, "element %lld has a non-finite coordinate", (long long)e);
+            at(geom, c, e) = g[c];
+        }
+        double C[3], N[3], a, Lh;
+        if (is_tri) {
+            const double *A = g, *B = g + 3, *Cv = g + 6;
+            const double u[3] = { B[0] - A[0], B[1] - A[1], B[2] - A[2] };
+            const double v[3] = { Cv[0] - A[0], Cv[1] - A[1], Cv[2] - A[2] };
+            const double w[3] = { Cv[0] - B[0], Cv[1] - B[1], Cv[2] - B[2] };
+            N[0] = u[1] * v[2] - u[2] * v[1];
+            N[1] = u[2] * v[0] - u[0] * v[2];
+            N[2] = u[0] * v[1] - u[1] * v[0];
+            const double n2 = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+            a = 0.5 * n2;
+            const double la = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            const double lb = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double lc = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            Lh = (la + lb + lc) / 3.0;  // Sec. 2: L = (a + b + c) / 3
+            if (!(a > 0.0) || !(la > 0.0 && lb > 0.0 && lc > 0.0))
+                return fail(BEMC_E_DEGENERATE_ELEMENT, "triangle %lld has zero area", (long long)e);
+            for (int c = 0; c < 3; ++c) {
+                C[c] = (A[c] + B[c] + Cv[c]) / 3.0;
+                N[c] /= n2;
+            }
+            for (int c = 0; c < 3; ++c) {
+                at(off, c, e) = A[c] - C[c];
+                at(off, 3 + c, e) = B[c] - C[c];
+                at(off, 6 + c, e) = Cv[c] - C[c];
+            }
+        } else {
+            const double *P0 = g, *e1 = g + 3, *e2 = g + 6;
+            const double la = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+            const double lb = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+            if (!(la > 0.0 && lb > 0.0)) return fail(BEMC_E_DEGENERATE_ELEMENT, "rectangle %lld has a zero side", (long long)e);
+            const double dp = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+            if (std::fabs(dp) > 1e-10 * la * lb)
+                return fail(BEMC_E_NOT_RECTANGLE, "rectangle %lld: sides not orthogonal", (long long)e);
+            N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            const double n2 = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+            a = la * lb;
+            Lh = 0.5 * (la + lb);  // mean of the four sides
+            for (int c = 0; c < 3; ++c) {
+                C[c] = P0[c] + 0.5 * e1[c] + 0.5 * e2[c];  // Eq. 3.2: Q_cen
+                N[c] /= n2;
+                at(off, c, e) = 0.5 * e1[c];      // (a/2) u_x
+                at(off, 3 + c, e) = 0.5 * e2[c];  // (b/2) u_y
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            at(cen, c, e) = C[c];
+            at(nrm, c, e) = N[c];
+        }
+        area[(size_t)e] = a;
+        L[(size_t)e] = Lh;
+        thr2[(size_t)e] = (h->near_dr * Lh) * (h->near_dr * Lh);
+    }
+    for (size_t i = 0; i < off.size(); ++i) off32[i] = (float)off[i];
+
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(s));
+    free_elements(h);
+    h->n_tri = n_tri;
+    h->n_rect = n_rect;
+    h->ne = ne;
+    if (dev_alloc(&h->d_geom, geom.size()) || dev_alloc(&h->d_cen, cen.size()) || dev_alloc(&h->d_thr2, thr2.size()) ||
+        dev_alloc(&h->d_off, off.size()) || dev_alloc(&h->d_off32, off32.size()) || dev_alloc(&h->d_L, L.size()) ||
+        dev_alloc(&h->d_area, area.size()) || dev_alloc(&h->d_nrm, nrm.size())) {
+        (void)hipGetLastError();
+        free_elements(h);
+        return fail(BEMC_E_OUT_OF_MEMORY, "element arrays for %lld elements", (long long)ne);
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_geom, geom.data(), geom.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_cen, cen.data(), cen.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_thr2, thr2.data(), thr2.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_L, L.data(), L.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_area, area.data(), area.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_nrm, nrm.data(), nrm.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->h_area = area;
+    h->h_L = L;
+    h->have_geometry = true;
+    return ok();
+}
+
+int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sigma_on_device, void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry) return fail(BEMC_E_NO_GEOMETRY, "upload the geometry first");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "densities cannot change while serving");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(BEMC_E_INVALID_ARG, "n_rhs must be in 1..%d", kMaxRhs);
+    if (!sigma && h->ne > 0) return fail(BEMC_E_INVALID_ARG, "sigma is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t cnt = (size_t)n_rhs * (size_t)h->ne;
+    if (!sigma_on_device)
+        for (size_t i = 0; i < cnt; ++i)
+            if (!std::isfinite(sigma[i])) return fail(BEMC_E_NONFINITE, "sigma[%zu] is not finite", i);
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(s));
+    dev_free(h->d_q);
+    h->n_rhs = 0;
+    if (dev_alloc(&h->d_q, cnt) != hipSuccess) { (void)hipGetLastError(); return fail(BEMC_E_OUT_OF_MEMORY, "charges"); }
+    double* d_sig = nullptr;
+    if (sigma_on_device) {
+        d_sig = const_cast<double*>(sigma);
+    } else {
+        if (dev_alloc(&d_sig, cnt) != hipSuccess) { (void)hipGetLastError(); return fail(BEMC_E_OUT_OF_MEMORY, "sigma staging"); }
+        HIP_TRY(hipMemcpyAsync(d_sig, sigma, cnt * 8, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(launch_charges(d_sig, h->d_area, h->d_q, h->ne, n_rhs, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!sigma_on_device) dev_free(d_sig);
+    h->n_rhs = n_rhs;
+    return ok();
+}
+
+int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rhs, double* phi, double* E,
+              void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry || h->n_rhs == 0) return fail(BEMC_E_NO_GEOMETRY, "geometry and densities must be uploaded");
+    if (n < 0) return fail(BEMC_E_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (n >= (1ll << 31)) return fail(BEMC_E_LIMIT, "n >= 2^31");
+    if (!pts || !phi) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
+    return h->run(false, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream));
+}
+
+int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision, double* out, void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry) return fail(BEMC_E_NO_GEOMETRY, "geometry must be uploaded");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(BEMC_E_INVALID_ARG, "n_rhs must be in 1..%d", kMaxRhs);
+    if (!sigma || !out) return fail(BEMC_E_INVALID_ARG, "null pointer");
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "collocation while serving is not supported");
+    if (h->ne == 0) return ok();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(h->device));
+    // charges q = sigma * area of these densities, kept apart from the evaluation densities
+    if (!h->d_qc && dev_alloc(&h->d_qc, (size_t)kMaxRhs * (size_t)h->ne) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BEMC_E_OUT_OF_MEMORY, "collocation charges");
+    }
+    HIP_TRY(launch_charges(sigma, h->d_area, h->d_qc, h->ne, n_rhs, s));
+    return h->run(true, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
+}
+
+int bemc_set_near_capacity(bemc_handle h, int64_t pairs)
+{
+    if (!h || pairs < 1) return fail(BEMC_E_INVALID_ARG, "invalid capacity");
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipDeviceSynchronize());
+    dev_free(h->d_near);
+    h->near_cap = 0;
+    if (dev_alloc(&h->d_near, (size_t)pairs) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list of %lld entries", (long long)pairs);
+    }
+    h->near_cap = (unsigned long long)pairs;
+    return ok();
+}
+
+int bemc_query_stats(bemc_handle h, bemc_stats* out)
+{
+    if (!h || !out) return fail(BEMC_E_INVALID_ARG, "null argument");
+    *out = h->last;
+    return ok();
+}
+
+// ----------------------------------------------------------------- serving -------
+int bemc_server_start(bemc_handle h, const bemc_server_config* cfg)
+{
+    if (!h || !cfg) return fail(BEMC_E_INVALID_ARG, "null argument");
+    if (!h->have_geometry || h->n_rhs == 0) return fail(BEMC_E_NO_GEOMETRY, "geometry and densities must be uploaded");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "server already running");
+    ServerEnv env{};
+    env.device = h->device;
+    env.el = h->elements();
+    env.rules = h->rules();
+    env.near_dr = h->near_dr;
+    env.max_depth = h->max_depth;
+    env.n_tri = h->n_tri;
+    env.n_rect = h->n_rect;
+    std::string err;
+    bemc::Server* s = bemc::Server::create(env, *cfg, err);
+    if (!s) return fail(BEMC_E_INVALID_ARG, "%s", err.c_str());
+    h->server = s;
+    return ok();
+}
+
+int bemc_server_submit(bemc_handle h, const double* pts_host, int64_t n, double* phi_host, double* E_host,
+                       uint64_t* ticket)
+{
+    if (!h || !h->server) return fail(BEMC_E_INVALID_ARG, "server not running");
+    if (!ticket || (n > 0 && (!pts_host || !phi_host)) || n < 0) return fail(BEMC_E_INVALID_ARG, "bad query arguments");
+    std::string err;
+    int rc = h->server->submit(pts_host, n, phi_host, E_host, ticket, err);
+    if (rc) return fail(rc, "%s", err.c_str());
+    return ok();
+}
+
+int bemc_server_poll(bemc_handle h, uint64_t ticket, bemc_query_info* info)
+{
+    if (!h || !h->server || !info) return fail(BEMC_E_INVALID_ARG, "server not running");
+    if (!h->server->poll(ticket, info)) return fail(BEMC_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    return ok();
+}
+
+int bemc_server_wait(bemc_handle h, uint64_t ticket, double timeout_s, bemc_query_info* info)
+{
+    if (!h || !h->server) return fail(BEMC_E_INVALID_ARG, "server not running");
+    bemc_query_info tmp{};
+    bemc_query_info* inf = info ? info : &tmp;
+    const int rc = h->server->wait(ticket, timeout_s, inf);
+    if (rc == 1) return fail(BEMC_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (rc == 2) return fail(BEMC_E_INVALID_ARG, "timeout");
+    if (inf->status != BEMC_OK) return fail(inf->status, "query failed: %s", h->server->last_error().c_str());
+    return ok();
+}
+
+int bemc_server_stop(bemc_handle h)
+{
+    if (!h || !h->server) return fail(BEMC_E_INVALID_ARG, "server not running");
+    h->server->stop();
+    delete h->server;
+    h->server = nullptr;
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host runtime and the kernels of the GPU library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bemc {
+
+// ------------------------------------------------------------------ rules (host)
+struct TriNode {
+    double la, lb, lc, w;  // barycentric coordinates (Eq. 3.3) and weight
+};
+struct RectNode {
+    double x, y, w;  // natural coordinates (Eq. 3.2) and weight
+};
+bool triangle_rule(int n, std::vector<TriNode>& out);
+bool gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+bool rectangle_gauss_rule(int n, std::vector<RectNode>& out);
+
+constexpr int kMaxTriNodes = 64;
+constexpr int kMaxRectNodes = 256;
+constexpr int kMaxRhs = 8;
+
+// ------------------------------------------------------------------ device data
+// Rule tables in device memory: triangle nodes as (la, lb, lc, w), rectangle nodes as
+// (x, y, w, 0); FP32 copies for the mixed path.
+struct RuleTables {
+    const double* tri;    // [nt][4]
+    const double* rect;   // [nr][4]
+    const float* tri32;   // [nt][4]
+    const float* rect32;  // [nr][4]
+    int nt, nr;
+};
+
+// Element arrays, SoA over the global element index (triangles first).
+struct Elements {
+    const double* geom;  // [9][ne]  input geometry: A,B,C  or  P0,e1,e2
+    const double* cen;   // [3][ne]  centroid
+    const double* thr2;  // [ne]     (near_dr * L)^2
+    const double* off;   // [9][ne]  tri: A-c, B-c, C-c;  rect: e1/2, e2/2, 0
+    const float* off32;  // [9][ne]  same, FP32
+    const double* L;     // [ne]     average side length
+    const double* area;  // [ne]
+    const double* nrm;   // [3][ne]  unit normal
+    const double* q;     // [n_rhs][ne]  sigma * area
+    int64_t ne;
+    int n_tri;
+    int n_rhs;
+};
+
+struct NearPair {
+    uint32_t point;
+    uint32_t elem;
+};
+
+// Device counters of one evaluation.
+struct DevCounters {
+    unsigned long long near_count;  // near pairs found by the far kernel (may exceed capacity)
+    unsigned long long cursor;      // work cursor of the near kernel
+    unsigned long long leaves;
+    unsigned long long cap_hits;
+    unsigned long long on_surface;
+    unsigned long long max_depth;
+    unsigned long long visit_limit_hits;
+    unsigned long long pad;
+};
+
+// Arguments of the far-field kernels.
+struct FarArgs {
+    Elements el;
+    RuleTables rules;
+    const double* pts;       // [3][n] (eval)  -- unused for collocation
+    int64_t n;               // field points (eval) or rows (collocation)
+    int rhs;                 // density vector (eval)
+    int n_rhs;               // collocation right-hand sides
+    double K;                // Coulomb constant
+    double* phi;             // [n] (eval) or out[n_rhs][ne] (collocation)
+    double* E;               // [3][n] or null
+    double* partial;         // element-split partial sums [n_split][4][n] (serving) or null
+    int64_t elem_begin, elem_end;  // element range of this launch
+    int n_split;             // > 1: blockIdx.y takes elements [begin + y chunk, begin + (y+1) chunk)
+    int64_t chunk;
+    NearPair* near_list;
+    unsigned long long near_cap;
+    DevCounters* ctr;
+};
+
+struct NearArgs {
+    Elements el;
+    RuleTables rules;
+    const double* pts;  // [3][n] eval; null in collocation mode (points are centroids)
+    int64_t n;
+    int rhs;
+    int n_rhs;
+    double K;
+    double* phi;        // eval: phi[n]; collocation: out[n_rhs][ne]
+    double* E;          // eval only, may be null
+    const NearPair* near_list;
+    unsigned long long near_cap;
+    DevCounters* ctr;
+    double near_dr2;    // near_dr^2
+    int max_depth;
+    int64_t visit_limit;
+};
+
+// kernel launchers (kernels.hip)
+hipError_t launch_far_eval(const FarArgs& a, int precision, hipStream_t s);
+hipError_t launch_far_colloc(const FarArgs& a, int precision, hipStream_t s);
+hipError_t launch_near(const NearArgs& a, bool collocation, hipStream_t s);
+hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s);
+hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
+                               hipStream_t s);
+hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
+
+double coulomb_constant();
+
+}  // namespace bemc

@@ -1,0 +1,835 @@
+// HIP kernels for gfx950 (MI355X): Gaussian-cubature potential and field of charged
+// BEM triangles and rectangles (Glueck & Hilk, arXiv:1606.03743).
+//
+//  far_eval_kernel     one field point per lane and PPT points per lane; element tiles are
+//                      staged in LDS with their Gaussian points generated on the fly from
+//                      the centroid offsets (Eq. 3.2 / 3.3); FP64 distance-ratio test per
+//                      pair (Sec. 2), near pairs compacted per wavefront into a dense list;
+//                      far pairs summed as point charges (Sec. 4, Eq. 4.1), potential and
+//                      field from the same nodes.  FP64 or mixed (FP32 node sums).
+//  far_colloc_kernel   the same sum, potential only, at element centroids, for up to eight
+//                      density vectors (matrix-free collocation product).
+//  near_kernel         FP64 near field over the dense list: each lane walks the recursive
+//                      subdivision of its pair depth first (triangle: four midpoint
+//                      children; rectangle: 2 x 2) using lattice coordinates instead of a
+//                      stack; a child at DR >= near_dr of its own (or at the depth cap) gets
+//                      the element's rule; a point lying on its element gets the exact
+//                      polar integral.  Results are added with FP64 atomics.
+#include "bemc_internal.h"
+
+namespace bemc {
+
+constexpr double kEps0 = 8.8541878188e-12;  // vacuum permittivity, CODATA 2022 (F/m)
+double coulomb_constant() { return 1.0 / (4.0 * 3.14159265358979323846 * kEps0); }
+
+namespace {
+
+constexpr int kBlock = 256;       // 4 wavefronts
+constexpr int kTileNodes = 1024;  // Gaussian-point slots of one LDS tile
+constexpr int kMaxTileElems = 64;
+
+__device__ __forceinline__ int tile_elems(int nn) { return nn >= 16 ? kTileNodes / nn : kMaxTileElems; }
+
+// 1/sqrt(x) in FP64: hardware estimate (~24 bits) refined by one third-order step
+// y (1 + e/2 + 3 e^2 / 8), e = 1 - x y^2 (relative error ~ e^3).
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ float rsqrt32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v, int src)
+{
+    const unsigned lo = __shfl((unsigned)v, src);
+    const unsigned hi = __shfl((unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Wavefront-level compaction of near pairs: one atomic per wavefront, lane offsets by
+// popcount.  Called with every lane of the wavefront active.
+__device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e, NearPair* list,
+                                            unsigned long long cap, DevCounters* ctr)
+{
+    const unsigned long long m = __ballot(is_near);
+    if (m == 0ull) return;
+    const int first = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == first) base = atomicAdd(&ctr->near_count, (unsigned long long)__popcll(m));
+    base = bcast_u64(base, first);
+    if (is_near) {
+        const unsigned long long pos = base + lanes_below(m);
+        if (pos < cap) list[pos] = NearPair{ p, e };
+    }
+}
+
+// ---------------------------------------------------------------- LDS staging ------
+struct TileLds64 {
+    double4 node[kTileNodes];  // centroid offset (x, y, z) and weight
+    double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
+    double q[kMaxRhs][kMaxTileElems];
+};
+struct TileLds32 {
+    float4 node[kTileNodes];
+    double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
+    double q[kMaxRhs][kMaxTileElems];
+};
+
+// Gaussian points of elements [t0, t0 + te) relative to their centroids.
+template <bool TRI, bool MIXED, typename Lds>
+__device__ __forceinline__ void stage_tile(Lds& s, const Elements& el, const RuleTables& R, int nn, int64_t t0,
+                                           int te, int rhs0, int nrhs)
+{
+    const int64_t ne = el.ne;
+    for (int k = threadIdx.x; k < te; k += kBlock) {
+        const int64_t e = t0 + k;
+        s.cx[k] = el.cen[e];
+        s.cy[k] = el.cen[ne + e];
+        s.cz[k] = el.cen[2 * ne + e];
+        s.thr2[k] = el.thr2[e];
+        for (int r = 0; r < nrhs; ++r) s.q[r][k] = el.q[(int64_t)(rhs0 + r) * ne + e];
+    }
+    for (int k = threadIdx.x; k < te * nn; k += kBlock) {
+        const int j = k / nn;
+        const int i = k - j * nn;
+        const int64_t e = t0 + j;
+        if (!MIXED) {
+            double x, y, z, w;
+            if (TRI) {
+                const double la = R.tri[4 * i], lb = R.tri[4 * i + 1], lc = R.tri[4 * i + 2];
+                w = R.tri[4 * i + 3];
+                x = la * el.off[e] + lb * el.off[3 * ne + e] + lc * el.off[6 * ne + e];
+                y = la * el.off[ne + e] + lb * el.off[4 * ne + e] + lc * el.off[7 * ne + e];
+                z = la * el.off[2 * ne + e] + lb * el.off[5 * ne + e] + lc * el.off[8 * ne + e];
+            } else {
+                const double u = R.rect[4 * i], v = R.rect[4 * i + 1];
+                w = R.rect[4 * i + 2];
+                x = u * el.off[e] + v * el.off[3 * ne + e];
+                y = u * el.off[ne + e] + v * el.off[4 * ne + e];
+                z = u * el.off[2 * ne + e] + v * el.off[5 * ne + e];
+            }
+            reinterpret_cast<double4*>(s.node)[k] = make_double4(x, y, z, w);
+        } else {
+            float x, y, z, w;
+            if (TRI) {
+                const float la = R.tri32[4 * i], lb = R.tri32[4 * i + 1], lc = R.tri32[4 * i + 2];
+                w = R.tri32[4 * i + 3];
+                x = la * el.off32[e] + lb * el.off32[3 * ne + e] + lc * el.off32[6 * ne + e];
+                y = la * el.off32[ne + e] + lb * el.off32[4 * ne + e] + lc * el.off32[7 * ne + e];
+                z = la * el.off32[2 * ne + e] + lb * el.off32[5 * ne + e] + lc * el.off32[8 * ne + e];
+            } else {
+                const float u = R.rect32[4 * i], v = R.rect32[4 * i + 1];
+                w = R.rect32[4 * i + 2];
+                x = u * el.off32[e] + v * el.off32[3 * ne + e];
+                y = u * el.off32[ne + e] + v * el.off32[4 * ne + e];
+                z = u * el.off32[2 * ne + e] + v * el.off32[5 * ne + e];
+            }
+            reinterpret_cast<float4*>(s.node)[k] = make_float4(x, y, z, w);
+        }
+    }
+}
+
+// ------------------------------------------------------------ far field: eval -------
+template <int PPT>
+struct PointSet {
+    double x[PPT], y[PPT], z[PPT];
+    bool valid[PPT];
+    uint32_t idx[PPT];
+    double phi[PPT], ex[PPT], ey[PPT], ez[PPT];
+};
+
+// One element kind over [e_begin, e_end); NN > 0 is the compile-time node count, NN == 0
+// reads it at run time.
+template <int NN, bool TRI, bool MIXED, int PPT, typename Lds>
+__device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT>& P, int64_t e_begin,
+                                               int64_t e_end)
+{
+    const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
+    const int TE = tile_elems(nn);
+    for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
+        const int te = (int)min((int64_t)TE, e_end - t0);
+        __syncthreads();
+        stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, a.rhs, 1);
+        __syncthreads();
+        for (int j = 0; j < te; ++j) {
+            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j], q = s.q[0][j];
+            double dx[PPT], dy[PPT], dz[PPT];
+            bool nr[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                dx[k] = P.x[k] - cx;
+                dy[k] = P.y[k] - cy;
+                dz[k] = P.z[k] - cz;
+                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
+                nr[k] = P.valid[k] && (D2 < thr2);
+                record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+            }
+            if (!MIXED) {
+                double f[PPT], gx[PPT], gy[PPT], gz[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
+                const double4* nd = reinterpret_cast<const double4*>(s.node) + j * nn;
+#pragma unroll 4
+                for (int i = 0; i < nn; ++i) {
+                    const double4 Q = nd[i];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+                        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+                        const double ri = rsqrt64(r2);
+                        const double wr = Q.w * ri;
+                        f[k] += wr;
+                        const double w3 = wr * (ri * ri);
+                        gx[k] = fma(w3, rx, gx[k]);
+                        gy[k] = fma(w3, ry, gy[k]);
+                        gz[k] = fma(w3, rz, gz[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (!nr[k]) {
+                        P.phi[k] = fma(q, f[k], P.phi[k]);
+                        P.ex[k] = fma(q, gx[k], P.ex[k]);
+                        P.ey[k] = fma(q, gy[k], P.ey[k]);
+                        P.ez[k] = fma(q, gz[k], P.ez[k]);
+                    }
+                }
+            } else {
+                float f[PPT], gx[PPT], gy[PPT], gz[PPT], fx[PPT], fy[PPT], fz[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    f[k] = gx[k] = gy[k] = gz[k] = 0.0f;
+                    fx[k] = (float)dx[k];
+                    fy[k] = (float)dy[k];
+                    fz[k] = (float)dz[k];
+                }
+                const float4* nd = reinterpret_cast<const float4*>(s.node) + j * nn;
+#pragma unroll 4
+                for (int i = 0; i < nn; ++i) {
+                    const float4 Q = nd[i];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const float rx = fx[k] - Q.x, ry = fy[k] - Q.y, rz = fz[k] - Q.z;
+                        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+                        const float ri = rsqrt32(r2);
+                        const float wr = Q.w * ri;
+                        f[k] += wr;
+                        const float w3 = wr * (ri * ri);
+                        gx[k] = fmaf(w3, rx, gx[k]);
+                        gy[k] = fmaf(w3, ry, gy[k]);
+                        gz[k] = fmaf(w3, rz, gz[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (!nr[k]) {
+                        P.phi[k] = fma(q, (double)f[k], P.phi[k]);
+                        P.ex[k] = fma(q, (double)gx[k], P.ex[k]);
+                        P.ey[k] = fma(q, (double)gy[k], P.ey[k]);
+                        P.ez[k] = fma(q, (double)gz[k], P.ez[k]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NT, int NR, bool MIXED, int PPT>
+__global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
+{
+    using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
+    __shared__ Lds s;
+    PointSet<PPT> P;
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t p = base + (int64_t)k * kBlock;
+        P.valid[k] = p < a.n;
+        P.idx[k] = (uint32_t)p;
+        P.x[k] = P.valid[k] ? a.pts[p] : 0.0;
+        P.y[k] = P.valid[k] ? a.pts[a.n + p] : 0.0;
+        P.z[k] = P.valid[k] ? a.pts[2 * a.n + p] : 0.0;
+        P.phi[k] = P.ex[k] = P.ey[k] = P.ez[k] = 0.0;
+    }
+    int64_t e_lo = a.elem_begin, e_hi = a.elem_end;
+    if (a.n_split > 1) {
+        e_lo = min(a.elem_begin + (int64_t)blockIdx.y * a.chunk, a.elem_end);
+        e_hi = min(e_lo + a.chunk, a.elem_end);
+    }
+    const int64_t nt_end = min((int64_t)a.el.n_tri, e_hi);
+    if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT>(a, s, P, e_lo, nt_end);
+    const int64_t nr_begin = max((int64_t)a.el.n_tri, e_lo);
+    if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT>(a, s, P, nr_begin, e_hi);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!P.valid[k]) continue;
+        const int64_t p = base + (int64_t)k * kBlock;
+        if (a.partial) {  // element-split launch: unscaled partial sums, reduced later in fixed order
+            double* o = a.partial + (int64_t)blockIdx.y * 4 * a.n;
+            o[p] = P.phi[k];
+            o[a.n + p] = P.ex[k];
+            o[2 * a.n + p] = P.ey[k];
+            o[3 * a.n + p] = P.ez[k];
+        } else {
+            a.phi[p] = a.K * P.phi[k];
+            if (a.E) {
+                a.E[p] = a.K * P.ex[k];
+                a.E[a.n + p] = a.K * P.ey[k];
+                a.E[2 * a.n + p] = a.K * P.ez[k];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- far field: collocation -----
+template <int NN, bool TRI, bool MIXED, int PPT, typename Lds>
+__device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const double (&px)[PPT],
+                                                 const double (&py)[PPT], const double (&pz)[PPT],
+                                                 const bool (&valid)[PPT], const uint32_t (&idx)[PPT],
+                                                 double (&acc)[PPT][kMaxRhs], int64_t e_begin, int64_t e_end)
+{
+    const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
+    const int TE = tile_elems(nn);
+    const int nrhs = a.n_rhs;
+    for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
+        const int te = (int)min((int64_t)TE, e_end - t0);
+        __syncthreads();
+        stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, 0, nrhs);
+        __syncthreads();
+        for (int j = 0; j < te; ++j) {
+            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j];
+            double dx[PPT], dy[PPT], dz[PPT], sum[PPT];
+            bool nr[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                dx[k] = px[k] - cx;
+                dy[k] = py[k] - cy;
+                dz[k] = pz[k] - cz;
+                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
+                nr[k] = valid[k] && (D2 < thr2);
+                record_near(nr[k], idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+            }
+            if (!MIXED) {
+                double f[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) f[k] = 0.0;
+                const double4* nd = reinterpret_cast<const double4*>(s.node) + j * nn;
+#pragma unroll 4
+                for (int i = 0; i < nn; ++i) {
+                    const double4 Q = nd[i];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+                        f[k] = fma(Q.w, rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz))), f[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) sum[k] = f[k];
+            } else {
+                float f[PPT], fx[PPT], fy[PPT], fz[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    f[k] = 0.0f;
+                    fx[k] = (float)dx[k];
+                    fy[k] = (float)dy[k];
+                    fz[k] = (float)dz[k];
+                }
+                const float4* nd = reinterpret_cast<const float4*>(s.node) + j * nn;
+#pragma unroll 4
+                for (int i = 0; i < nn; ++i) {
+                    const float4 Q = nd[i];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const float rx = fx[k] - Q.x, ry = fy[k] - Q.y, rz = fz[k] - Q.z;
+                        f[k] = fmaf(Q.w, rsqrt32(fmaf(rx, rx, fmaf(ry, ry, rz * rz))), f[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) sum[k] = (double)f[k];
+            }
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (!nr[k]) {
+#pragma unroll
+                    for (int r = 0; r < kMaxRhs; ++r)
+                        if (r < nrhs) acc[k][r] = fma(s.q[r][j], sum[k], acc[k][r]);
+                }
+            }
+        }
+    }
+}
+
+template <int NT, int NR, bool MIXED, int PPT>
+__global__ __launch_bounds__(kBlock) void far_colloc_kernel(FarArgs a)
+{
+    using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
+    __shared__ Lds s;
+    const int64_t ne = a.el.ne;
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+    double px[PPT], py[PPT], pz[PPT];
+    bool valid[PPT];
+    uint32_t idx[PPT];
+    double acc[PPT][kMaxRhs];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t p = base + (int64_t)k * kBlock;
+        valid[k] = p < ne;
+        idx[k] = (uint32_t)p;
+        px[k] = valid[k] ? a.el.cen[p] : 0.0;
+        py[k] = valid[k] ? a.el.cen[ne + p] : 0.0;
+        pz[k] = valid[k] ? a.el.cen[2 * ne + p] : 0.0;
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r) acc[k][r] = 0.0;
+    }
+    const int64_t nt = a.el.n_tri;
+    if (nt > 0) far_colloc_range<NT, true, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, 0, nt);
+    if (nt < ne) far_colloc_range<NR, false, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, nt, ne);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!valid[k]) continue;
+        const int64_t p = base + (int64_t)k * kBlock;
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r)
+            if (r < a.n_rhs) a.phi[(int64_t)r * ne + p] = a.K * acc[k][r];
+    }
+}
+
+// --------------------------------------------------------------- near field ---------
+struct NearState {
+    int kind;        // 0 triangle, 1 rectangle
+    int level;       // 0 = the element itself
+    int i, j;        // lattice position at this level
+    bool up;         // triangle orientation (up: vertices (i,j),(i+1,j),(i,j+1))
+};
+
+// Index of a child within its parent and the parent's lattice position.
+__device__ __forceinline__ int child_index(NearState& s)
+{
+    const int a = s.i & 1, b = s.j & 1;
+    int c;
+    bool pup = true;
+    if (s.kind == 1) {
+        c = a + 2 * b;
+    } else if (s.up) {
+        if (a && b) { pup = false; c = 3; }
+        else c = a ? 1 : (b ? 2 : 0);
+    } else {
+        if (!a && !b) { pup = true; c = 3; }
+        else { pup = false; c = (a && b) ? 0 : (b ? 1 : 2); }
+    }
+    s.i >>= 1;
+    s.j >>= 1;
+    s.up = pup;
+    s.level -= 1;
+    return c;
+}
+
+// Child c of the node s (s becomes the child).
+__device__ __forceinline__ void to_child(NearState& s, int c)
+{
+    const int i2 = 2 * s.i, j2 = 2 * s.j;
+    s.level += 1;
+    if (s.kind == 1) {
+        s.i = i2 + (c & 1);
+        s.j = j2 + (c >> 1);
+    } else if (s.up) {  // up parent: up(2i,2j), up(2i+1,2j), up(2i,2j+1), down(2i,2j)
+        s.i = i2 + (c == 1 ? 1 : 0);
+        s.j = j2 + (c == 2 ? 1 : 0);
+        s.up = (c != 3);
+    } else {  // down parent: down(2i+1,2j+1), down(2i,2j+1), down(2i+1,2j), up(2i+1,2j+1)
+        s.i = i2 + (c == 1 ? 0 : 1);
+        s.j = j2 + (c == 2 ? 0 : 1);
+        s.up = (c == 3);
+    }
+}
+
+// Move to the next node of the depth-first walk after finishing node s; false when the
+// walk has returned to the root.
+__device__ __forceinline__ bool advance(NearState& s)
+{
+    while (s.level > 0) {
+        const int c = child_index(s);  // s is now the parent
+        if (c < 3) {
+            to_child(s, c + 1);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Vertices of a triangle node: root A, edge vectors eB = B - A, eC = C - A.
+__device__ __forceinline__ void tri_node_vertices(const NearState& s, const double* A, const double* eB, const double* eC,
+                                                  double V[3][3])
+{
+    const double h = ldexp(1.0, -s.level);
+    double u[3], v[3];
+    if (s.up) {
+        u[0] = s.i; v[0] = s.j; u[1] = s.i + 1; v[1] = s.j; u[2] = s.i; v[2] = s.j + 1;
+    } else {
+        u[0] = s.i + 1; v[0] = s.j + 1; u[1] = s.i; v[1] = s.j + 1; u[2] = s.i + 1; v[2] = s.j;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double uh = u[m] * h, vh = v[m] * h;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[m][c] = fma(uh, eB[c], fma(vh, eC[c], A[c]));
+    }
+}
+
+template <bool COLLOC>
+__global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
+{
+    const Elements& el = a.el;
+    const int64_t ne = el.ne;
+    const unsigned long long total = min(a.ctr->near_count, a.near_cap);
+    const int lane = lane_id();
+
+    unsigned long long n_leaves = 0, n_cap = 0, n_on = 0, n_limit = 0;
+    int max_level = 0;
+
+    bool active = false;
+    NearState st{ 0, 0, 0, 0, true };
+    uint32_t p = 0, e = 0;
+    double P[3] = { 0, 0, 0 }, g0[3] = { 0, 0, 0 }, g1[3] = { 0, 0, 0 }, g2[3] = { 0, 0, 0 };
+    double thr2 = 0.0, acc[4] = { 0, 0, 0, 0 };
+    int64_t visits = 0;
+
+    while (true) {
+        // ---- refill: one atomic per wavefront for all lanes that need a pair
+        const unsigned long long need = __ballot(!active);
+        if (need) {
+            const int first = __ffsll((long long)need) - 1;
+            unsigned long long b = 0;
+            if (lane == first) b = atomicAdd(&a.ctr->cursor, (unsigned long long)__popcll(need));
+            b = bcast_u64(b, first);
+            if (!active) {
+                const unsigned long long w = b + lanes_below(need);
+                if (w >= total) break;
+                const NearPair pr = a.near_list[w];
+                p = pr.point;
+                e = pr.elem;
+                if (COLLOC) {
+                    P[0] = el.cen[p]; P[1] = el.cen[ne + p]; P[2] = el.cen[2 * ne + p];
+                } else {
+                    P[0] = a.pts[p]; P[1] = a.pts[a.n + p]; P[2] = a.pts[2 * a.n + p];
+                }
+                st.kind = (int64_t)e < el.n_tri ? 0 : 1;
+                double G[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) G[c] = el.geom[(int64_t)c * ne + e];
+                if (st.kind == 0) {  // A, B - A, C - A
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { g0[c] = G[c]; g1[c] = G[3 + c] - G[c]; g2[c] = G[6 + c] - G[c]; }
+                } else {             // P0, e1, e2
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { g0[c] = G[c]; g1[c] = G[3 + c]; g2[c] = G[6 + c]; }
+                }
+                thr2 = el.thr2[e];
+                acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+                visits = 0;
+                active = true;
+                st.level = 0; st.i = 0; st.j = 0; st.up = true;
+
+                // ---- point on the element: exact polar integral about the point
+                const double L = el.L[e];
+                const double nx = el.nrm[e], ny = el.nrm[ne + e], nz = el.nrm[2 * ne + e];
+                const double dx = P[0] - el.cen[e], dy = P[1] - el.cen[ne + e], dz = P[2] - el.cen[2 * ne + e];
+                bool on = fabs(nx * dx + ny * dy + nz * dz) <= 1e-12 * L;
+                double V[4][3];
+                int nv;
+                if (st.kind == 0) {
+                    nv = 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { V[0][c] = G[c]; V[1][c] = G[3 + c]; V[2][c] = G[6 + c]; V[3][c] = 0.0; }
+                } else {
+                    nv = 4;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        V[0][c] = G[c]; V[1][c] = G[c] + G[3 + c];
+                        V[2][c] = G[c] + G[3 + c] + G[6 + c]; V[3][c] = G[c] + G[6 + c];
+                    }
+                }
+                if (on) {  // inside test
+                    if (st.kind == 0) {
+                        const double twoA = 2.0 * el.area[e];
+                        for (int k = 0; k < 3 && on; ++k) {
+                            const double* Va = V[(k + 1) % 3];
+                            const double* Vb = V[(k + 2) % 3];
+                            const double ax = Va[0] - P[0], ay = Va[1] - P[1], az = Va[2] - P[2];
+                            const double bx = Vb[0] - P[0], by = Vb[1] - P[1], bz = Vb[2] - P[2];
+                            const double cxp = ay * bz - az * by, cyp = az * bx - ax * bz, czp = ax * by - ay * bx;
+                            on = (nx * cxp + ny * cyp + nz * czp) / twoA >= -1e-12;
+                        }
+                    } else {
+                        const double x = 2.0 * (dx * G[3] + dy * G[4] + dz * G[5]) / (G[3] * G[3] + G[4] * G[4] + G[5] * G[5]);
+                        const double y = 2.0 * (dx * G[6] + dy * G[7] + dz * G[8]) / (G[6] * G[6] + G[7] * G[7] + G[8] * G[8]);
+                        on = fabs(x) <= 1.0 + 1e-12 && fabs(y) <= 1.0 + 1e-12;
+                    }
+                }
+                if (on) {
+                    // per edge at distance h with end offsets t1, t2 (rho^2 = h^2 + t^2):
+                    //   potential h [asinh(t/h)],  field -n [(t/rho)(1 + ln rho) - asinh(t/h)] + h t [(1 + ln rho)/rho]
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    for (int k = 0; k < nv; ++k) {
+                        const double* Va = V[k];
+                        const double* Vb = V[(k + 1) % nv];
+                        double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
+                        const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+                        tv[0] /= len; tv[1] /= len; tv[2] /= len;
+                        const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
+                        const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
+                        const double t2 = t1 + len;
+                        double fn[3] = { pa[0] - t1 * tv[0], pa[1] - t1 * tv[1], pa[2] - t1 * tv[2] };
+                        const double hh = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
+                        if (!(hh > 1e-14 * L)) continue;
+                        fn[0] /= hh; fn[1] /= hh; fn[2] /= hh;
+                        const double r1 = sqrt(hh * hh + t1 * t1), r2 = sqrt(hh * hh + t2 * t2);
+                        const double as = asinh(t2 / hh) - asinh(t1 / hh);
+                        s0 += hh * as;
+                        const double l1 = 1.0 + log(r1), l2 = 1.0 + log(r2);
+                        const double gn = (t2 / r2) * l2 - (t1 / r1) * l1 - as;
+                        const double gt = hh * (l2 / r2 - l1 / r1);
+                        s1 += -gn * fn[0] + gt * tv[0];
+                        s2 += -gn * fn[1] + gt * tv[1];
+                        s3 += -gn * fn[2] + gt * tv[2];
+                    }
+                    const double inv_area = 1.0 / el.area[e];
+                    acc[0] = s0 * inv_area; acc[1] = s1 * inv_area; acc[2] = s2 * inv_area; acc[3] = s3 * inv_area;
+                    n_on++;
+                    active = false;  // finished: fall through to the write-out below
+                    st.level = -1;
+                } else if (a.max_depth <= 0) {
+                    st.level = 0;  // evaluate the rule on the element itself (depth cap)
+                } else {
+                    st.level = 1; st.i = 0; st.j = 0; st.up = true;  // first child of the root
+                }
+            }
+        }
+
+        bool finished = false;
+        if (active) {
+            // ---- visit node st
+            const double h = ldexp(1.0, -st.level);
+            double cen[3];
+            double V[3][3];
+            if (st.kind == 0) {
+                tri_node_vertices(st, g0, g1, g2, V);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cen[c] = (V[0][c] + V[1][c] + V[2][c]) * (1.0 / 3.0);
+            } else {
+                const double ih = st.i * h, jh = st.j * h;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    V[0][c] = fma(ih, g1[c], fma(jh, g2[c], g0[c]));  // corner
+                    cen[c] = fma(0.5 * h, g1[c] + g2[c], V[0][c]);
+                }
+            }
+            const double dx = P[0] - cen[0], dy = P[1] - cen[1], dz = P[2] - cen[2];
+            const double D2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const bool is_near = D2 < thr2 * h * h;
+            ++visits;
+            if (st.level > max_level) max_level = st.level;
+            if (!is_near || st.level >= a.max_depth || visits > a.visit_limit) {
+                // leaf: the element's rule on this node, weights scaled by the area ratio h^2
+                double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
+                if (st.kind == 0) {
+                    for (int i = 0; i < a.rules.nt; ++i) {
+                        const double la = a.rules.tri[4 * i], lb = a.rules.tri[4 * i + 1], lc = a.rules.tri[4 * i + 2];
+                        const double w = a.rules.tri[4 * i + 3];
+                        const double rx = P[0] - (la * V[0][0] + lb * V[1][0] + lc * V[2][0]);
+                        const double ry = P[1] - (la * V[0][1] + lb * V[1][1] + lc * V[2][1]);
+                        const double rz = P[2] - (la * V[0][2] + lb * V[1][2] + lc * V[2][2]);
+                        const double ri = rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz)));
+                        const double wr = w * ri, w3 = wr * ri * ri;
+                        f0 += wr; f1 = fma(w3, rx, f1); f2 = fma(w3, ry, f2); f3 = fma(w3, rz, f3);
+                    }
+                } else {
+                    const double hh = 0.5 * h;
+                    for (int i = 0; i < a.rules.nr; ++i) {
+                        const double x = a.rules.rect[4 * i] * hh, y = a.rules.rect[4 * i + 1] * hh;
+                        const double w = a.rules.rect[4 * i + 2];
+                        const double rx = P[0] - fma(x, g1[0], fma(y, g2[0], cen[0]));
+                        const double ry = P[1] - fma(x, g1[1], fma(y, g2[1], cen[1]));
+                        const double rz = P[2] - fma(x, g1[2], fma(y, g2[2], cen[2]));
+                        const double ri = rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz)));
+                        const double wr = w * ri, w3 = wr * ri * ri;
+                        f0 += wr; f1 = fma(w3, rx, f1); f2 = fma(w3, ry, f2); f3 = fma(w3, rz, f3);
+                    }
+                }
+                const double h2 = h * h;
+                acc[0] = fma(h2, f0, acc[0]);
+                acc[1] = fma(h2, f1, acc[1]);
+                acc[2] = fma(h2, f2, acc[2]);
+                acc[3] = fma(h2, f3, acc[3]);
+                n_leaves++;
+                if (is_near) n_cap++;
+                if (visits > a.visit_limit) {
+                    n_limit++;
+                    finished = true;
+                } else {
+                    finished = !advance(st);
+                }
+            } else {
+                to_child(st, 0);
+            }
+        } else if (st.level == -1) {
+            finished = true;  // on-element pair completed during refill
+        }
+
+        if (finished) {
+            const double K = a.K;
+            if (COLLOC) {
+                for (int r = 0; r < a.n_rhs; ++r) {
+                    const double q = el.q[(int64_t)r * ne + e];
+                    unsafeAtomicAdd(&a.phi[(int64_t)r * ne + p], K * q * acc[0]);
+                }
+            } else {
+                const double q = el.q[(int64_t)a.rhs * ne + e];
+                unsafeAtomicAdd(&a.phi[p], K * q * acc[0]);
+                if (a.E) {
+                    unsafeAtomicAdd(&a.E[p], K * q * acc[1]);
+                    unsafeAtomicAdd(&a.E[a.n + p], K * q * acc[2]);
+                    unsafeAtomicAdd(&a.E[2 * a.n + p], K * q * acc[3]);
+                }
+            }
+            active = false;
+            st.level = 0;
+        }
+    }
+
+    // per-lane counters -> one atomic per counter per lane that has something to add
+    if (n_leaves) atomicAdd(&a.ctr->leaves, n_leaves);
+    if (n_cap) atomicAdd(&a.ctr->cap_hits, n_cap);
+    if (n_on) atomicAdd(&a.ctr->on_surface, n_on);
+    if (n_limit) atomicAdd(&a.ctr->visit_limit_hits, n_limit);
+    if (max_level) atomicMax(&a.ctr->max_depth, (unsigned long long)max_level);
+}
+
+// ---------------------------------------------------------------- small kernels -----
+__global__ void charges_kernel(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne * n_rhs) return;
+    q[i] = sigma[i] * area[i % ne];
+}
+
+__global__ void reduce_split_kernel(const double* partial, int n_split, int64_t n, double K, double* phi, double* E)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double s[4] = { 0, 0, 0, 0 };
+    for (int k = 0; k < n_split; ++k)  // fixed order: independent of timing
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += partial[((int64_t)k * 4 + c) * n + p];
+    phi[p] = K * s[0];
+    if (E) {
+        E[p] = K * s[1];
+        E[n + p] = K * s[2];
+        E[2 * n + p] = K * s[3];
+    }
+}
+
+__global__ void zero_counters_kernel(DevCounters* c)
+{
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
+    const int i = threadIdx.x;
+    if (i < (int)(sizeof(DevCounters) / sizeof(unsigned long long))) w[i] = 0ull;
+}
+
+template <int NT, int NR, bool MIXED, int PPT>
+hipError_t far_eval_launch(const FarArgs& a, hipStream_t s)
+{
+    const int64_t per = (int64_t)kBlock * PPT;
+    const int64_t blocks = (a.n + per - 1) / per;
+    if (blocks > 0x7fffffff || a.n_split < 1 || a.n_split > 65535) return hipErrorInvalidValue;
+    far_eval_kernel<NT, NR, MIXED, PPT><<<dim3((unsigned)blocks, (unsigned)a.n_split), dim3(kBlock), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
+{
+    constexpr int PPT = 2;
+    const int nt = a.rules.nt, nr = a.rules.nr;
+    if (nr == 49) {
+        if (nt == 7) return far_eval_launch<7, 49, MIXED, PPT>(a, s);
+        if (nt == 12) return far_eval_launch<12, 49, MIXED, PPT>(a, s);
+        if (nt == 19) return far_eval_launch<19, 49, MIXED, PPT>(a, s);
+        if (nt == 33) return far_eval_launch<33, 49, MIXED, PPT>(a, s);
+    }
+    return far_eval_launch<0, 0, MIXED, PPT>(a, s);
+}
+
+template <int NT, int NR, bool MIXED, int PPT>
+hipError_t far_colloc_launch(const FarArgs& a, hipStream_t s)
+{
+    const int64_t per = (int64_t)kBlock * PPT;
+    const int64_t blocks = (a.el.ne + per - 1) / per;
+    far_colloc_kernel<NT, NR, MIXED, PPT><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t far_colloc_dispatch(const FarArgs& a, hipStream_t s)
+{
+    constexpr int PPT = 2;
+    if (a.rules.nr == 49 && a.rules.nt == 33) return far_colloc_launch<33, 49, MIXED, PPT>(a, s);
+    return far_colloc_launch<0, 0, MIXED, PPT>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_far_eval(const FarArgs& a, int precision, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    return precision == 1 ? far_eval_dispatch<true>(a, s) : far_eval_dispatch<false>(a, s);
+}
+
+hipError_t launch_far_colloc(const FarArgs& a, int precision, hipStream_t s)
+{
+    if (a.el.ne <= 0) return hipSuccess;
+    return precision == 1 ? far_colloc_dispatch<true>(a, s) : far_colloc_dispatch<false>(a, s);
+}
+
+hipError_t launch_near(const NearArgs& a, bool collocation, hipStream_t s)
+{
+    // persistent lanes; every lane leaves once the shared cursor passes the pair count
+    const int blocks = 1024;
+    if (collocation) near_kernel<true><<<blocks, kBlock, 0, s>>>(a);
+    else near_kernel<false><<<blocks, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s)
+{
+    const int64_t tot = ne * n_rhs;
+    if (tot <= 0) return hipSuccess;
+    charges_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(sigma, area, q, ne, n_rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    reduce_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, n_split, n, K, phi, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(DevCounters* c, hipStream_t s)
+{
+    zero_counters_kernel<<<1, 64, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+}  // namespace bemc

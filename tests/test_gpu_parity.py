@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by
+element, on seeded inputs.
+
+Error measure (per field point): the potential error divided by the sum of the absolute
+per-element potentials, and the L1 field error divided by the sum of the per-element field
+magnitudes (both sums from the oracle).  Random-sign densities make the plain relative
+error ill-conditioned where contributions cancel; this normalisation bounds the
+accumulated rounding of an N-term sum independently of that cancellation.
+Tolerances: FP64 path 1e-12, mixed path 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_03743_amd import bemc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-6}
+
+
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def nerr(phi, E, ref):
+    ep = np.abs(phi - ref["phi"]) / ref["abs_phi"]
+    ee = np.sum(np.abs(E - ref["E"]), axis=1) / ref["abs_E"]
+    return ep, ee
+
+
+def run_gpu(ctx, pts_np, precision):
+    torch = torch_mod()
+    pts = torch.tensor(np.ascontiguousarray(pts_np.T), dtype=torch.float64, device="cuda:0")
+    phi, E, rc = ctx.eval(pts, precision=precision)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), E.cpu().numpy().T.copy(), rc
+
+
+def make_ctx(w, tri_rule=None, rect_gl_n=None):
+    ctx = bemc.Context(0)
+    ctx.set_rules(tri_rule or w.tri_rule, rect_gl_n or w.rect_gl_n)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    w = W.icosphere_workload()
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(tri_rule=7), with_abs=True)
+    return w, ref
+
+
+@pytest.fixture(scope="module")
+def cyl():
+    w = W.cylinder_workload(40, 30, 1200, n_points=3000, near_frac=0.3, seed=101)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7), with_abs=True)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_icosphere_full(sphere, precision):
+    """1,280-triangle icosphere, 4,096 points in 2 <= r <= 10, 7-point rule: every pair far."""
+    w, ref = sphere
+    ctx = make_ctx(w)
+    phi, E, rc = run_gpu(ctx, w.points, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert rc == 0 and st["near_pairs"] == 0 and ref["stats"]["near_pairs"] == 0
+    assert st["pairs"] == 4096 * 1280 and st["node_interactions"] == 4096 * 1280 * 7
+    ep, ee = nerr(phi, E, ref)
+    print(f"icosphere {precision}: phi {ep.max():.2e} E {ee.max():.2e}")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+    if precision == "mixed":  # but not FP64-exact: the FP32 path really ran
+        assert ep.max() > 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cylinder_with_near_field(cyl, precision):
+    """Triangles (33-point rule) + rectangles (7 x 7 Gauss), 30 % of points near an element."""
+    w, ref = cyl
+    ctx = make_ctx(w)
+    phi, E, rc = run_gpu(ctx, w.points, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert rc == 0
+    assert st["near_pairs"] == ref["stats"]["near_pairs"] > 0
+    assert st["leaves"] > 0 and st["cap_hits"] == 0
+    ep, ee = nerr(phi, E, ref)
+    print(f"cylinder {precision}: phi {ep.max():.2e} E {ee.max():.2e}, near pairs {st['near_pairs']}, "
+          f"leaves gpu {st['leaves']} oracle {ref['stats']['leaves']}")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+    assert abs(st["leaves"] - ref["stats"]["leaves"]) <= 0.001 * ref["stats"]["leaves"]
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 511, 513, 1025])
+def test_ragged_point_counts(cyl, n):
+    w, ref = cyl
+    ctx = make_ctx(w)
+    idx = np.arange(n) * 7 % w.points.shape[0]
+    phi, E, _ = run_gpu(ctx, w.points[idx], "fp64")
+    ctx.close()
+    sub = {k: ref[k][idx] for k in ("phi", "E", "abs_phi", "abs_E")}
+    ep, ee = nerr(phi, E, sub)
+    assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+def test_near_list_overflow_regrows(cyl):
+    w, ref = cyl
+    ctx = make_ctx(w)
+    ctx.set_near_capacity(8)
+    phi, E, _ = run_gpu(ctx, w.points, "fp64")
+    st = ctx.stats()
+    ctx.close()
+    assert st["near_capacity"] >= st["near_pairs"] > 8
+    ep, ee = nerr(phi, E, ref)
+    assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+@pytest.mark.parametrize("tri_rule,gl", [(4, 2), (7, 3), (12, 5), (19, 7), (33, 8)])
+def test_other_rules(tri_rule, gl):
+    """Generic (run-time node count) kernels and every triangle table."""
+    w = W.cylinder_workload(24, 18, 96, n_points=700, near_frac=0.3, seed=5, tri_rule=tri_rule, rect_gl_n=gl)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(tri_rule, gl), with_abs=True)
+    ctx = make_ctx(w)
+    for prec in ("fp64", "mixed"):
+        phi, E, _ = run_gpu(ctx, w.points, prec)
+        ep, ee = nerr(phi, E, ref)
+        assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec], (prec, ep.max(), ee.max())
+    ctx.close()
+
+
+def test_points_on_elements():
+    """Field points lying on an element: principal value, warning status."""
+    w = W.cylinder_workload(24, 18, 96, n_points=200, near_frac=0.5, seed=9)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, w.n_elements, 40)
+    on, _, _ = W.points_on_elements(w.tri, w.rect, idx, rng)
+    pts = np.concatenate([w.points, on])
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], pts, oracle.params(), with_abs=True)
+    ctx = make_ctx(w)
+    phi, E, rc = run_gpu(ctx, pts, "fp64")
+    st = ctx.stats()
+    ctx.close()
+    assert rc == bemc.W_ON_SURFACE
+    assert st["on_surface"] == ref["stats"]["on_surface"] >= 40
+    ep, ee = nerr(phi, E, ref)
+    assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+def test_single_kind_geometries():
+    rng = np.random.default_rng(1)
+    tri = W.icosphere(2, 1.0)
+    rect = W.cylinder_mantle(1.0, -1.0, 1.0, 12, 4)
+    pts = np.concatenate([W.shell_points(300, 1.5, 4.0, rng), rng.uniform(-0.9, 0.9, (200, 3)) * [0.5, 0.5, 1]])
+    for t, r in ((tri, None), (None, rect)):
+        ne = (0 if t is None else t.shape[0]) + (0 if r is None else r.shape[0])
+        sig = rng.standard_normal(ne)
+        ref = oracle.evaluate(t, r, sig, pts, oracle.params(), with_abs=True)
+        ctx = bemc.Context(0)
+        ctx.upload_geometry(t, r)
+        ctx.upload_densities(sig)
+        phi, E, _ = run_gpu(ctx, pts, "fp64")
+        ctx.close()
+        ep, ee = nerr(phi, E, ref)
+        assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+def test_empty_and_errors():
+    torch = torch_mod()
+    w = W.cylinder_workload(24, 18, 96, n_points=10, seed=9)
+    ctx = bemc.Context(0)
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.eval(torch.zeros((3, 4), dtype=torch.float64, device="cuda:0"))
+    assert ei.value.code == bemc.E_NO_GEOMETRY
+    bad = w.tri.copy()
+    bad[3, 3:6] = bad[3, 0:3]  # zero-area triangle
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.upload_geometry(bad, w.rect)
+    assert ei.value.code == bemc.E_DEGENERATE_ELEMENT
+    skew = w.rect.copy()
+    skew[0, 6] += 0.01
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.upload_geometry(w.tri, skew)
+    assert ei.value.code == bemc.E_NOT_RECTANGLE
+    nan = w.tri.copy()
+    nan[0, 0] = np.nan
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.upload_geometry(nan, w.rect)
+    assert ei.value.code == bemc.E_NONFINITE
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    phi, E, rc = ctx.eval(torch.zeros((3, 0), dtype=torch.float64, device="cuda:0"))
+    assert rc == 0 and phi.numel() == 0
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.eval(torch.zeros((3, 4), dtype=torch.float64, device="cuda:0"), rhs=1)
+    assert ei.value.code == bemc.E_INVALID_ARG
+    with pytest.raises(bemc.BemcError):
+        ctx.set_rules(tri_rule=5)
+    ctx.close()
+
+
+def test_far_field_is_deterministic(sphere):
+    w, _ = sphere
+    ctx = make_ctx(w)
+    a = run_gpu(ctx, w.points, "fp64")
+    b = run_gpu(ctx, w.points, "fp64")
+    ctx.close()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# --------------------------------------------------------------- collocation -----
+@pytest.fixture(scope="module")
+def nested():
+    t1, q1 = W.cylinder(1.0, -1.0, 1.0, 16, 4, 64)
+    t2, q2 = W.cylinder(2.0, -1.5, 1.5, 24, 4, 144)
+    tri, rect = np.concatenate([t1, t2]), np.concatenate([q1, q2])
+    sig = np.random.default_rng(8).standard_normal((3, tri.shape[0] + rect.shape[0]))
+    ref = oracle.collocation(tri, rect, sig)
+    return tri, rect, sig, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_collocation_matvec(nested, precision):
+    torch = torch_mod()
+    tri, rect, sig, ref = nested
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    s = torch.tensor(sig, dtype=torch.float64, device="cuda:0")
+    out = ctx.collocation(s, precision=precision)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.close()
+    out = out.cpu().numpy()
+    ne = sig.shape[1]
+    assert st["on_surface"] == ne  # every row has its self term
+    # normalise by the row's sum of |phi_j| for each right-hand side (oracle gives it for rhs 0)
+    scale = ref["abs"][None, :] * (np.abs(sig).max(axis=1) / np.abs(sig[0]).max())[:, None]
+    err = np.abs(out - ref["out"]) / scale
+    print(f"collocation {precision}: {err.max():.2e}")
+    assert err.max() <= TOL[precision]
+
+
+# ------------------------------------------------------------ full-size sampled ----
+def test_full_size_cylinder_sampled():
+    """The benchmark workload at full size (150,000 elements, 1,000,000 points) in the
+    launch configuration the benchmark uses; the oracle checks a sample of points."""
+    torch = torch_mod()
+    w = W.cylinder_150k()
+    ctx = make_ctx(w)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        phi, E, rc = ctx.eval(pts, precision=prec)
+        torch.cuda.synchronize()
+        res[prec] = (phi.cpu().numpy(), E.cpu().numpy().T.copy(), ctx.stats())
+    ctx.close()
+    rng = np.random.default_rng(42)
+    isn = w.info["is_near"]
+    idx = np.concatenate([rng.choice(np.nonzero(~isn)[0], 96, replace=False),
+                          rng.choice(np.nonzero(isn)[0], 96, replace=False)])
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points[idx], oracle.params(33, 7), with_abs=True)
+    for prec in ("fp64", "mixed"):
+        phi, E, st = res[prec]
+        sub_ref = ref
+        ep, ee = nerr(phi[idx], E[idx], sub_ref)
+        print(f"full-size {prec}: phi {ep.max():.2e} E {ee.max():.2e}; near pairs {st['near_pairs']}, "
+              f"far {st['far_ms']:.1f} ms near {st['near_ms']:.1f} ms")
+        assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
+        assert np.all(np.isfinite(phi)) and np.all(np.isfinite(E))
