@@ -24,8 +24,10 @@
  *     over each edge has a closed form; the field there is the principal value
  *     (in-plane part; the element's own normal part is zero).
  *
- * Per point, the element contributions are accumulated in element-index order
- * with Neumaier-compensated FP64 sums; the Coulomb constant is applied last.
+ * Each element is integrated in coordinates relative to its first vertex (same
+ * integrals, better conditioned close to the element).  Per point, the element
+ * contributions are accumulated in element-index order with Neumaier-compensated
+ * FP64 sums; the Coulomb constant is applied last.
  *
  * Rule tables are typed in here from the paper's appendices; Gauss-Legendre
  * nodes come from Newton iteration on the Legendre polynomial.  Nothing here
@@ -530,6 +532,28 @@ static void self_rule(const double* P, const elem* e, double* acc)
 /* ------------------------------------------------------------------ */
 /* Dispatch for one (point, element) pair: unit density, no constant   */
 /* ------------------------------------------------------------------ */
+/* The same element with its first vertex (A, or the corner P0) moved to the origin, and
+ * the field point moved with it.  Integrating in these coordinates forms P - Q_i from
+ * numbers of the element's own size instead of absolute coordinates; near the element
+ * (distances down to 1e-3 L and below) this removes the cancellation that absolute
+ * coordinates far from the origin would cause.  The integrals are unchanged. */
+static void to_local(const double* P, const elem* e, double* Pl, elem* le)
+{
+    *le = *e;
+    const double* O = e->g;
+    sub3(P, O, Pl);
+    if (e->kind == 0) {
+        for (int k = 0; k < 3; ++k) {
+            le->g[k] = 0.0;
+            le->g[3 + k] = e->g[3 + k] - O[k];
+            le->g[6 + k] = e->g[6 + k] - O[k];
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) le->g[k] = 0.0;
+    }
+    sub3(e->cen, O, le->cen);
+}
+
 static void element_contribution(const double* P, const elem* e, const rules* R, const orc_params* prm,
                                  double* out, lstats* st)
 {
@@ -538,23 +562,26 @@ static void element_contribution(const double* P, const elem* e, const rules* R,
     sub3(P, e->cen, d);
     double D2 = dot3(d, d);
     double thr = prm->near_dr * e->L;
+    double Pl[3];
+    elem le;
+    to_local(P, e, Pl, &le);
     if (!(D2 < thr * thr)) { /* far: DR >= threshold */
-        apply_rule(P, e->kind, e->g, e->area, R, out);
+        apply_rule(Pl, le.kind, le.g, le.area, R, out);
         return;
     }
     st->near_pairs++;
-    if (on_element(P, e)) {
+    if (on_element(Pl, &le)) {
         st->on_surface++;
-        self_rule(P, e, out);
+        self_rule(Pl, &le, out);
         return;
     }
     if (prm->max_depth <= 0) {
-        apply_rule(P, e->kind, e->g, e->area, R, out);
+        apply_rule(Pl, le.kind, le.g, le.area, R, out);
         st->leaves++;
         st->cap_hits++;
         return;
     }
-    near_recurse(P, e->kind, e->g, 0, R, prm, out, st);
+    near_recurse(Pl, le.kind, le.g, 0, R, prm, out, st);
 }
 
 static int build_rules(const orc_params* prm, rules* R)
@@ -711,8 +738,11 @@ int orc_element(int kind, const double* geom, const double* P, const orc_params*
     lstats ls;
     memset(&ls, 0, sizeof(ls));
     if (mode == 0) {
+        double Pl[3];
+        elem le;
+        to_local(P, &e, Pl, &le);
         out[0] = out[1] = out[2] = out[3] = 0.0;
-        apply_rule(P, kind, e.g, e.area, R, out);
+        apply_rule(Pl, kind, le.g, le.area, R, out);
     } else {
         element_contribution(P, &e, R, prm, out, &ls);
     }

@@ -209,3 +209,24 @@ def test_collocation_single_element_and_linearity(orc):
     rows = np.array([3, 0, ne - 1])
     sub = orc.collocation(tri, rect, sig, rows=rows)
     assert np.array_equal(sub["out"], col["out"][:, rows])
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_small_element_far_from_origin(orc, kind):
+    """A small element far from the coordinate origin with a point 1e-3 L above it: the
+    result equals that of the same configuration at the origin (the integral only depends
+    on P - Q), to the accuracy of the near-field method."""
+    rng = np.random.default_rng(31 + kind)
+    g = (rand_tri(rng) if kind == 0 else rand_rect(rng)) * 0.01
+    if kind == 1:
+        g[0:3] = rng.random(3) * 0.01
+    P = point_above(kind, g, rng, 1e-3, orc)
+    ref = R.fan(kind, g, P, n_sub=32, n_gl=24)
+    off = np.array([3.7, -5.1, 4.9])
+    g2 = g.copy()
+    g2[0:3] += off
+    if kind == 0:
+        g2[3:6] += off
+        g2[6:9] += off
+    got, _ = orc.element(kind, g2, P + off, orc.params(), mode=1)
+    assert R.rel_err_phi(got, ref) < 1e-13 and R.rel_err_E(got, ref) < 1e-12
