@@ -278,7 +278,11 @@ def far_points_box(tri, rect, n, lo, hi, rng, margin=3.0):
     lo, hi = np.asarray(lo, float), np.asarray(hi, float)
     out = []
     have = 0
+    rounds = 0
     while have < n:
+        rounds += 1
+        if rounds > 200 or (rounds > 20 and have == 0):
+            raise ValueError("the box leaves (almost) no room for far points: refine the mesh")
         m = int((n - have) * 1.3) + 64
         cand = lo + (hi - lo) * rng.random((m, 3))
         ok = np.ones(m, dtype=bool)

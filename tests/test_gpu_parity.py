@@ -124,7 +124,7 @@ def test_near_list_overflow_regrows(cyl):
 @pytest.mark.parametrize("tri_rule,gl", [(4, 2), (7, 3), (12, 5), (19, 7), (33, 8)])
 def test_other_rules(tri_rule, gl):
     """Generic (run-time node count) kernels and every triangle table."""
-    w = W.cylinder_workload(24, 18, 96, n_points=700, near_frac=0.3, seed=5, tri_rule=tri_rule, rect_gl_n=gl)
+    w = W.cylinder_workload(40, 30, 1200, n_points=700, near_frac=0.3, seed=5, tri_rule=tri_rule, rect_gl_n=gl)
     ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(tri_rule, gl), with_abs=True)
     ctx = make_ctx(w)
     for prec in ("fp64", "mixed"):
@@ -136,7 +136,7 @@ def test_other_rules(tri_rule, gl):
 
 def test_points_on_elements():
     """Field points lying on an element: principal value, warning status."""
-    w = W.cylinder_workload(24, 18, 96, n_points=200, near_frac=0.5, seed=9)
+    w = W.cylinder_workload(40, 30, 1200, n_points=200, near_frac=0.5, seed=9)
     rng = np.random.default_rng(3)
     idx = rng.integers(0, w.n_elements, 40)
     on, _, _ = W.points_on_elements(w.tri, w.rect, idx, rng)
@@ -155,7 +155,7 @@ def test_points_on_elements():
 def test_single_kind_geometries():
     rng = np.random.default_rng(1)
     tri = W.icosphere(2, 1.0)
-    rect = W.cylinder_mantle(1.0, -1.0, 1.0, 12, 4)
+    rect = W.cylinder_mantle(1.0, -1.0, 1.0, 12, 3)
     pts = np.concatenate([W.shell_points(300, 1.5, 4.0, rng), rng.uniform(-0.9, 0.9, (200, 3)) * [0.5, 0.5, 1]])
     for t, r in ((tri, None), (None, rect)):
         ne = (0 if t is None else t.shape[0]) + (0 if r is None else r.shape[0])
@@ -172,7 +172,7 @@ def test_single_kind_geometries():
 
 def test_empty_and_errors():
     torch = torch_mod()
-    w = W.cylinder_workload(24, 18, 96, n_points=10, seed=9)
+    w = W.cylinder_workload(40, 30, 1200, n_points=10, seed=9)
     ctx = bemc.Context(0)
     with pytest.raises(bemc.BemcError) as ei:
         ctx.eval(torch.zeros((3, 4), dtype=torch.float64, device="cuda:0"))

@@ -76,3 +76,9 @@ def test_serving_queries():
     assert step.max() <= 1e-3 + 1e-12 and np.median(step) > 0.999e-3
     t = W.poisson_arrivals(1000, 50.0)
     assert np.all(np.diff(t) > 0) and 15 < t[-1] < 25
+
+
+def test_far_points_guard():
+    """A mesh too coarse for the box raises instead of sampling forever."""
+    with pytest.raises(ValueError):
+        W.cylinder_workload(24, 18, 96, n_points=100, seed=1)
