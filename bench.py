@@ -1,0 +1,275 @@
+"""Benchmark: element-field-point interactions per second (potential + field), FP64 and
+mixed precision, on one MI355X; collocation product and serving latency beside it.
+
+One step = one evaluation of the whole hot path over the cylinder workload
+(100,000 cap triangles with the 33-point rule + 50,000 mantle rectangles with 7 x 7 Gauss,
+1,000,000 field points of which 30 % lie at distance ratio < 3 of some element):
+distance-ratio classification and near-pair compaction, far-field point-charge sums,
+FP64 near-field subdivision.  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--serving-queries Q] [--quick]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
+PEAK_FP32_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 128 FP32 FMA lanes x 2 (packed)
+FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
+FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_hbm.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per far-kernel launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def nerr(phi, E, ref):
+    ep = np.abs(phi - ref["phi"]) / ref["abs_phi"]
+    ee = np.sum(np.abs(E - ref["E"]), axis=1) / ref["abs_E"]
+    rp = np.abs(phi - ref["phi"]) / np.abs(ref["phi"])
+    return ep, ee, rp
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--serving-queries", type=int, default=120)
+    ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (points)")
+    ap.add_argument("--quick", action="store_true", help="skip collocation, serving and the CPU baseline")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one FP64 evaluation and nothing else (for counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); every box in this setup "
+              "has one GPU and the path has no multi-GPU leg.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1606_03743_amd import bemc, workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+
+    log("building the cylinder workload (150,000 elements, 1,000,000 points)")
+    w = W.cylinder_150k()
+    ctx = bemc.Context(0)
+    ctx.set_rules(w.tri_rule, w.rect_gl_n, 3.0, 24)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device=dev)
+    n = pts.shape[1]
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    E = torch.empty((3, n), dtype=torch.float64, device=dev)
+    ctx.set_near_capacity(40_000_000)
+    torch.cuda.synchronize()
+
+    if args.profile_only:
+        ctx.eval(pts, "fp64", phi=phi, E=E)
+        torch.cuda.synchronize()
+        log(f"profile run done: {ctx.stats()}")
+        return
+
+    def timed(precision, steps, warmup):
+        for i in range(warmup):
+            ctx.eval(pts, precision, phi=phi, E=E)
+            log(f"{precision} warmup {i + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        far_ms = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ctx.eval(pts, precision, phi=phi, E=E)
+            far_ms.append(ctx.stats()["far_ms"])
+            log(f"{precision} step {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, far_ms, ctx.stats()
+
+    dt64, far64, st64 = timed("fp64", args.steps, args.warmup)
+    phi64, E64 = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    dtmx, farmx, stmx = timed("mixed", args.steps, args.warmup)
+    phimx, Emx = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+
+    pairs = st64["pairs"]
+    node_int = st64["node_interactions"]
+    ms_step = 1e3 * dt64 / args.steps
+    value = pairs * args.steps / dt64
+    alg_flops = FLOP_PER_NODE_INT * node_int + FLOP_PER_PAIR * pairs
+    far_avg_s = 1e-3 * float(np.mean(far64))
+    achieved = alg_flops / far_avg_s / 1e12
+    traffic = traffic_from_profile()
+    out = {
+        "metric": "element-fieldpoint interactions/s (phi+E) FP64 vs mixed @1e-6; p99 query ms",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded cylinder mesh and points; the paper's KATRIN meshes are not available)",
+        "config": {"workload": w.name, "elements": w.n_elements, "points": n, "near_frac": 0.3,
+                   "tri_rule": w.tri_rule, "rect_gauss": f"{w.rect_gl_n}x{w.rect_gl_n}", "precision": "fp64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "far_eval_kernel<33,49,fp64>",
+                     "flops_per_launch": alg_flops, "avg_launch_ms": 1e3 * far_avg_s},
+        "node_interactions_per_s": node_int * args.steps / dt64,
+        "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
+                 "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},
+    }
+    mixed_ach = alg_flops / (1e-3 * float(np.mean(farmx))) / 1e12
+    out["mixed"] = {"value": pairs * args.steps / dtmx, "unit": "pairs/s", "ms_per_step": 1e3 * dtmx / args.steps,
+                    "speedup_vs_fp64": dt64 / dtmx, "far_kernel_ms": float(np.mean(farmx)),
+                    "roofline": {"bound": "alu", "achieved": mixed_ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": mixed_ach / PEAK_FP32_TFLOPS}}
+
+    if not args.quick:
+        import oracle
+
+        # CPU baseline on a bounded sample; the same oracle values check both precisions
+        rng = np.random.default_rng(7)
+        isn = w.info["is_near"]
+        k_near = int(round(0.3 * args.cpu_sample))
+        idx = np.concatenate([rng.choice(np.nonzero(~isn)[0], args.cpu_sample - k_near, replace=False),
+                              rng.choice(np.nonzero(isn)[0], k_near, replace=False)])
+        log(f"oracle on {idx.size} sampled points")
+        t0 = time.perf_counter()
+        ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points[idx], oracle.params(33, 7), with_abs=True)
+        tc = time.perf_counter() - t0
+        sample_pairs = idx.size * w.n_elements
+        out["cpu_baseline"] = {"value": sample_pairs / tc, "unit": "pairs/s", "cores": ref["threads"],
+                               "kind": "oracle",
+                               "sample": f"{idx.size} of the 1,000,000 points (30 % near), all 150,000 elements, "
+                                         f"{tc:.1f} s"}
+        acc = {}
+        for name, (p_, E_) in {"fp64": (phi64, E64), "mixed": (phimx, Emx)}.items():
+            ep, ee, rp = nerr(p_[idx], E_[idx], ref)
+            acc[name] = {"max_norm_err_phi": float(ep.max()), "max_norm_err_E": float(ee.max()),
+                         "median_norm_err_phi": float(np.median(ep)), "median_norm_err_E": float(np.median(ee)),
+                         "max_rel_err_phi": float(rp.max()), "median_rel_err_phi": float(np.median(rp))}
+        out["accuracy_vs_oracle"] = acc
+        out["mixed"]["within_1e-6"] = acc["mixed"]["max_norm_err_phi"] <= 1e-6 and acc["mixed"]["max_norm_err_E"] <= 1e-6
+
+        # collocation product: nested cylinders, 200,000 elements, 8 right-hand sides
+        log("collocation: nested cylinders, 200,000 elements, 8 right-hand sides")
+        wc = W.nested_cylinders_workload()
+        cctx = bemc.Context(0)
+        cctx.upload_geometry(wc.tri, wc.rect)
+        sig = torch.tensor(wc.sigma, dtype=torch.float64, device=dev)
+        colloc = {}
+        for prec in ("fp64", "mixed"):
+            res = cctx.collocation(sig, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = cctx.collocation(sig, prec, out=res)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = cctx.stats()
+            colloc[prec] = {"ms": 1e3 * dt, "pairs_per_s": st["pairs"] / dt, "near_pairs": st["near_pairs"],
+                            "far_kernel_ms": st["far_ms"], "near_kernel_ms": st["near_ms"]}
+        rows = np.random.default_rng(3).choice(wc.n_elements, 64, replace=False)
+        cref = oracle.collocation(wc.tri, wc.rect, wc.sigma, rows=rows)
+        got64 = res  # last result is mixed; recompute fp64 for the check
+        got64 = cctx.collocation(sig, "fp64").cpu().numpy()[:, rows]
+        gotmx = cctx.collocation(sig, "mixed").cpu().numpy()[:, rows]
+        scale = np.abs(wc.sigma).max() / np.abs(wc.sigma[0]).max() * cref["abs"][None, :]
+        colloc["fp64"]["max_norm_err"] = float(np.max(np.abs(got64 - cref["out"]) / scale))
+        colloc["mixed"]["max_norm_err"] = float(np.max(np.abs(gotmx - cref["out"]) / scale))
+        colloc["workload"] = wc.name
+        colloc["rhs"] = wc.sigma.shape[0]
+        out["collocation"] = colloc
+        cctx.close()
+
+        if args.serving_queries > 0:
+            out["serving"] = serving(args.serving_queries, torch, bemc, W)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def serving(n_queries, torch, bemc, W):
+    """Open-loop Poisson arrivals on the 1,000,000-element cylinder: saturation rate from a
+    burst, then arrivals at 0.7 x that rate; latency = arrival -> results in host memory."""
+    log(f"serving: 1,000,000-element cylinder, {n_queries} queries")
+    g = W.serving_geometry()
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(g.tri, g.rect)
+    ctx.upload_densities(g.sigma)
+    sizes = W.serving_query_sizes(20_000)[:n_queries]
+    qpts = [np.ascontiguousarray(W.serving_query(i, s)) for i, s in enumerate(sizes)]
+    phis = [np.empty(s) for s in sizes]
+    Es = [np.empty((s, 3)) for s in sizes]
+    ctx.server_start(mem_budget_bytes=16 << 30, max_batch_points=1 << 17, n_streams=3, precision="mixed")
+    # warm-up and saturation rate (all queries at once)
+    t0 = time.perf_counter()
+    tickets = [ctx.server_submit(qpts[i], phis[i], Es[i]) for i in range(n_queries)]
+    for t in tickets:
+        ctx.server_wait(t)
+    burst = time.perf_counter() - t0
+    sat_rate = n_queries / burst
+    log(f"serving burst: {burst:.2f} s ({sat_rate:.1f} queries/s)")
+    rate = 0.7 * sat_rate
+    arrivals = W.poisson_arrivals(n_queries, rate)
+    t0 = time.perf_counter()
+    tickets = []
+    for i in range(n_queries):
+        while time.perf_counter() - t0 < arrivals[i]:
+            time.sleep(min(1e-3, max(0.0, arrivals[i] - (time.perf_counter() - t0))))
+        tickets.append((i, ctx.server_submit(qpts[i], phis[i], Es[i])))
+    infos = [(i, ctx.server_wait(t)) for i, t in tickets]
+    total = time.perf_counter() - t0
+    # latency: submission (at the scheduled arrival) -> results in the host buffers
+    lat = [1e3 * (info["end_s"] - info["submit_s"]) for _, info in infos]
+    ctx.server_stop()
+    ctx.close()
+    pairs = int(np.sum(sizes)) * g.n_elements
+    lat = np.array(lat)
+    log(f"serving open loop: p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+    return {"workload": g.name, "queries": int(n_queries), "points": int(np.sum(sizes)),
+            "precision": "mixed far field, FP64 near field",
+            "saturation_queries_per_s": sat_rate, "arrival_rate_queries_per_s": rate,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "pairs_per_s": pairs / total, "wall_s": total,
+            "note": f"prefix of the 20,000-query stream ({n_queries} queries), sizes round(2^U(0,16))"}
+
+
+if __name__ == "__main__":
+    main()

@@ -524,15 +524,23 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     P[0] = a.pts[p]; P[1] = a.pts[a.n + p]; P[2] = a.pts[2 * a.n + p];
                 }
                 st.kind = (int64_t)e < el.n_tri ? 0 : 1;
+                // Work relative to the element's first vertex (A or P0): P - Q is then formed
+                // from numbers of the element's size, which keeps points very close to a small
+                // element far from the origin accurate.
                 double G[9];
 #pragma unroll
                 for (int c = 0; c < 9; ++c) G[c] = el.geom[(int64_t)c * ne + e];
-                if (st.kind == 0) {  // A, B - A, C - A
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { g0[c] = G[c]; g1[c] = G[3 + c] - G[c]; g2[c] = G[6 + c] - G[c]; }
-                } else {             // P0, e1, e2
+                for (int c = 0; c < 3; ++c) P[c] -= G[c];
+                if (st.kind == 0) {  // origin at A; edges B - A, C - A
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { g0[c] = G[c]; g1[c] = G[3 + c]; g2[c] = G[6 + c]; }
+                    for (int c = 0; c < 3; ++c) {
+                        g0[c] = 0.0; g1[c] = G[3 + c] - G[c]; g2[c] = G[6 + c] - G[c];
+                        G[3 + c] = g1[c]; G[6 + c] = g2[c]; G[c] = 0.0;
+                    }
+                } else {             // origin at P0; sides e1, e2
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { g0[c] = 0.0; g1[c] = G[3 + c]; g2[c] = G[6 + c]; }
                 }
                 thr2 = el.thr2[e];
                 acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
@@ -543,7 +551,9 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 // ---- point on the element: exact polar integral about the point
                 const double L = el.L[e];
                 const double nx = el.nrm[e], ny = el.nrm[ne + e], nz = el.nrm[2 * ne + e];
-                const double dx = P[0] - el.cen[e], dy = P[1] - el.cen[ne + e], dz = P[2] - el.cen[2 * ne + e];
+                const double dx = P[0] - (el.cen[e] - el.geom[e]);
+                const double dy = P[1] - (el.cen[ne + e] - el.geom[ne + e]);
+                const double dz = P[2] - (el.cen[2 * ne + e] - el.geom[2 * ne + e]);
                 bool on = fabs(nx * dx + ny * dy + nz * dz) <= 1e-12 * L;
                 double V[4][3];
                 int nv;
@@ -555,8 +565,8 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     nv = 4;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        V[0][c] = G[c]; V[1][c] = G[c] + G[3 + c];
-                        V[2][c] = G[c] + G[3 + c] + G[6 + c]; V[3][c] = G[c] + G[6 + c];
+                        V[0][c] = 0.0; V[1][c] = G[3 + c];
+                        V[2][c] = G[3 + c] + G[6 + c]; V[3][c] = G[6 + c];
                     }
                 }
                 if (on) {  // inside test
