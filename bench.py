@@ -100,6 +100,15 @@ def main():
     torch.cuda.synchronize()
 
     if args.profile_only:
+        # calibration kernels of known size for the HBM byte counters: a 1 GiB fill
+        # (writes 1 GiB) and a 1 GiB copy (reads 1 GiB, writes 1 GiB)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
         ctx.eval(pts, "fp64", phi=phi, E=E)
         torch.cuda.synchronize()
         log(f"profile run done: {ctx.stats()}")
