@@ -31,6 +31,7 @@ PEAK_FP32_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 128 FP32 FMA lanes x 2 (packed)
 FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
 FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_hbm.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_valu.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
 
 
@@ -50,6 +51,19 @@ def traffic_from_profile():
     txt = open(TRAFFIC_FILE).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def counted_flops_from_profile():
+    """Hardware FP64 flops per far-kernel launch from the committed VALU counter summary
+    (64 x (2 FMA + MUL + ADD + TRANS)), or None when the kernel changed since."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    txt = open(VALU_FILE).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    b = re.search(r"counted_fp64_flops_per_launch:\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash():
         return None
     return float(b.group(1))
@@ -142,6 +156,7 @@ def main():
     far_avg_s = 1e-3 * float(np.mean(far64))
     achieved = alg_flops / far_avg_s / 1e12
     traffic = traffic_from_profile()
+    counted = counted_flops_from_profile()
     out = {
         "metric": "element-fieldpoint interactions/s (phi+E) FP64 vs mixed @1e-6; p99 query ms",
         "value": value,
@@ -160,7 +175,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "far_eval_kernel<33,49,fp64>",
-                     "flops_per_launch": alg_flops, "avg_launch_ms": 1e3 * far_avg_s},
+                     "flops_per_launch": alg_flops, "avg_launch_ms": 1e3 * far_avg_s,
+                     "counted_fp64_tflops": None if counted is None else counted / far_avg_s / 1e12,
+                     "counted_frac": None if counted is None else counted / far_avg_s / 1e12 / PEAK_FP64_TFLOPS},
         "node_interactions_per_s": node_int * args.steps / dt64,
         "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
                  "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},

@@ -1,0 +1,102 @@
+"""Serving: continuous batching of field-point queries against resident geometry.
+
+Each query's result is the same alone and in a mix of concurrent queries (within the
+precision's tolerance), agrees with the oracle, and queries that can never fit are
+rejected at submission."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_03743_amd import bemc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    assert torch.cuda.is_available()
+    w = W.cylinder_workload(40, 30, 1200, n_points=10, seed=77)
+    rng = np.random.default_rng(5)
+    sizes = [1, 3, 17, 100, 513, 1000, 2048, 64, 5, 700, 1500, 250]
+    queries = []
+    for i, s in enumerate(sizes):
+        q = W.track_points(s, np.random.default_rng([77, i]))
+        if i % 3 == 0:  # some queries close to the electrode (near field active)
+            near, _ = W.near_points(w.tri, w.rect, s, rng)
+            q = near
+        queries.append(np.ascontiguousarray(q))
+    return w, queries
+
+
+def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096):
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    ctx.server_start(mem_budget_bytes=2 << 30, max_batch_points=max_batch, n_streams=n_streams, precision=precision)
+    phis = [np.full(len(q), np.nan) for q in queries]
+    Es = [np.full((len(q), 3), np.nan) for q in queries]
+    infos = []
+    if alone:
+        for q, p, e in zip(queries, phis, Es):
+            t = ctx.server_submit(q, p, e)
+            infos.append(ctx.server_wait(t, 60.0))
+    else:
+        ts = [ctx.server_submit(q, p, e) for q, p, e in zip(queries, phis, Es)]
+        infos = [ctx.server_wait(t, 60.0) for t in ts]
+    ctx.server_stop()
+    ctx.close()
+    return phis, Es, infos
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_alone_equals_mix_and_oracle(setup, precision, tol):
+    w, queries = setup
+    pa, Ea, ia = run_server(w, queries, precision, alone=True)
+    pm, Em, im = run_server(w, queries, precision, alone=False)
+    assert all(i["done"] == 1 and i["status"] == 0 for i in ia + im)
+    # in the mix, several queries shared a batch
+    assert len({i["batch_id"] for i in im}) < len(queries)
+    allp = np.concatenate(queries)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], allp, oracle.params(33, 7), with_abs=True)
+    off = 0
+    for q, a, b, ea, eb in zip(queries, pa, pm, Ea, Em):
+        sl = slice(off, off + len(q))
+        off += len(q)
+        # alone vs mix: same computation up to the element-split summation order and the
+        # order of the near-field atomic additions
+        d_ab = np.abs(a - b) / ref["abs_phi"][sl]
+        d_e = np.sum(np.abs(ea - eb), axis=1) / ref["abs_E"][sl]
+        assert d_ab.max() <= tol and d_e.max() <= tol
+        for phi, E in ((a, ea), (b, eb)):
+            ep = np.abs(phi - ref["phi"][sl]) / ref["abs_phi"][sl]
+            ee = np.sum(np.abs(E - ref["E"][sl]), axis=1) / ref["abs_E"][sl]
+            assert ep.max() <= tol and ee.max() <= tol
+
+
+def test_admission_and_latency_fields(setup):
+    w, queries = setup
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    with pytest.raises(bemc.BemcError) as ei:  # budget too small for one batch slot
+        ctx.server_start(mem_budget_bytes=1 << 10, max_batch_points=1 << 16, n_streams=2, precision="mixed")
+    assert ei.value.code == bemc.E_INVALID_ARG
+    ctx.server_start(mem_budget_bytes=1 << 30, max_batch_points=1024, n_streams=2, precision="mixed")
+    big = np.zeros((1025, 3))
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.server_submit(big, np.empty(1025))
+    assert ei.value.code == bemc.E_ADMISSION
+    q = queries[4]  # 513 points
+    phi = np.empty(len(q))
+    t = ctx.server_submit(q, phi)  # field not requested
+    info = ctx.server_wait(t, 60.0)
+    assert info["done"] == 1 and info["end_s"] >= info["start_s"] >= info["submit_s"] >= 0
+    assert np.all(np.isfinite(phi))
+    t0 = ctx.server_submit(np.zeros((0, 3)), np.empty(0))  # empty query
+    assert ctx.server_wait(t0, 60.0)["done"] == 1
+    with pytest.raises(bemc.BemcError):
+        ctx.server_poll(123456)
+    ctx.server_stop()
+    ctx.close()
