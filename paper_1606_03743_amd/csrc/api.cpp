@@ -82,6 +82,8 @@ struct bemc_context {
     // near-pair list and counters
     NearPair* d_near = nullptr;
     unsigned long long near_cap = 0;
+    double* d_partial = nullptr;  // element-chunk partial sums
+    size_t partial_cap = 0;       // doubles
     DevCounters* d_ctr = nullptr;
     DevCounters* h_ctr = nullptr;  // pinned
     hipEvent_t ev[4] = { nullptr, nullptr, nullptr, nullptr };
@@ -178,9 +180,37 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.near_list = d_near; na.near_cap = near_cap;
         na.ctr = d_ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
 
+        // Split the element range over blockIdx.y so that the launch has many more
+        // workgroups than resident slots: the dispatcher then balances the tail.  The chunk
+        // partial sums are reduced in fixed order (results do not depend on scheduling).
+        const int64_t npts = colloc ? ne : n;
+        const int64_t blocks = (npts + 511) / 512;
+        int n_split = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (kSplitTargetBlocks + blocks - 1) / blocks));
+        n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 64));  // chunks of >= 64 elements
+        const int64_t rows = colloc ? n_rhs_colloc : 4;
+        if (n_split > 1) {
+            const size_t need = (size_t)n_split * (size_t)rows * (size_t)npts;
+            if (need > partial_cap) {
+                dev_free(d_partial);
+                partial_cap = 0;
+                if (dev_alloc(&d_partial, need) != hipSuccess) {
+                    (void)hipGetLastError();
+                    n_split = 1;  // fall back to one chunk
+                } else {
+                    partial_cap = need;
+                }
+            }
+        }
+        fa.n_split = n_split;
+        fa.chunk = (ne + n_split - 1) / n_split;
+        fa.partial = n_split > 1 ? d_partial : nullptr;
         HIP_TRY(launch_zero_counters(d_ctr, s));
         HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(colloc ? launch_far_colloc(fa, precision, s) : launch_far_eval(fa, precision, s));
+        if (n_split > 1) {
+            if (colloc) HIP_TRY(launch_reduce_chunks(d_partial, n_split, rows, npts, fa.K, phi, s));
+            else HIP_TRY(launch_reduce_split(d_partial, n_split, npts, fa.K, phi, E, s));
+        }
         HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(launch_near(na, colloc, s));
         HIP_TRY(hipEventRecord(ev[2], s));
@@ -197,7 +227,6 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         HIP_TRY(hipEventElapsedTime(&far_ms, ev[0], ev[1]));
         HIP_TRY(hipEventElapsedTime(&near_ms, ev[1], ev[2]));
         last = bemc_stats{};
-        const int64_t npts = colloc ? ne : n;
         last.pairs = npts * ne;
         last.node_interactions = npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
         last.near_pairs = (int64_t)found;
@@ -270,7 +299,7 @@ int bemc_destroy(bemc_handle h)
     (void)hipDeviceSynchronize();
     free_elements(h);
     dev_free(h->d_tri); dev_free(h->d_rect); dev_free(h->d_tri32); dev_free(h->d_rect32);
-    dev_free(h->d_near); dev_free(h->d_ctr);
+    dev_free(h->d_near); dev_free(h->d_ctr); dev_free(h->d_partial);
     if (h->h_ctr) (void)hipHostFree(h->h_ctr);
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);

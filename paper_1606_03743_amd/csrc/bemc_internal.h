@@ -113,7 +113,13 @@ hipError_t launch_near(const NearArgs& a, bool collocation, hipStream_t s);
 hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s);
 hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
                                hipStream_t s);
+hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows, int64_t n, double K, double* out,
+                                hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
+
+// workgroups per resident slot that element splitting aims for (dispatcher load balance)
+constexpr int kSplitTargetBlocks = 16 * 1024;
+constexpr int kMaxSplit = 64;
 
 double coulomb_constant();
 

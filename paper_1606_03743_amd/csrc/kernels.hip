@@ -391,16 +391,30 @@ __global__ __launch_bounds__(kBlock) void far_colloc_kernel(FarArgs a)
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r) acc[k][r] = 0.0;
     }
+    int64_t e_lo = 0, e_hi = ne;
+    if (a.n_split > 1) {
+        e_lo = min((int64_t)blockIdx.y * a.chunk, ne);
+        e_hi = min(e_lo + a.chunk, ne);
+    }
     const int64_t nt = a.el.n_tri;
-    if (nt > 0) far_colloc_range<NT, true, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, 0, nt);
-    if (nt < ne) far_colloc_range<NR, false, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, nt, ne);
+    const int64_t t_hi = min(nt, e_hi);
+    if (e_lo < t_hi) far_colloc_range<NT, true, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, e_lo, t_hi);
+    const int64_t r_lo = max(nt, e_lo);
+    if (r_lo < e_hi) far_colloc_range<NR, false, MIXED, PPT>(a, s, px, py, pz, valid, idx, acc, r_lo, e_hi);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (!valid[k]) continue;
         const int64_t p = base + (int64_t)k * kBlock;
+        if (a.partial) {  // element chunk blockIdx.y: unscaled partial sums [split][rhs][ne]
+            double* o = a.partial + (int64_t)blockIdx.y * a.n_rhs * ne;
 #pragma unroll
-        for (int r = 0; r < kMaxRhs; ++r)
-            if (r < a.n_rhs) a.phi[(int64_t)r * ne + p] = a.K * acc[k][r];
+            for (int r = 0; r < kMaxRhs; ++r)
+                if (r < a.n_rhs) o[(int64_t)r * ne + p] = acc[k][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kMaxRhs; ++r)
+                if (r < a.n_rhs) a.phi[(int64_t)r * ne + p] = a.K * acc[k][r];
+        }
     }
 }
 
@@ -749,6 +763,17 @@ __global__ void reduce_split_kernel(const double* partial, int n_split, int64_t 
     }
 }
 
+// out[m][p] = K * sum over the element chunks k (fixed order) of partial[k][m][p]
+__global__ void reduce_chunks_kernel(const double* partial, int n_split, int64_t rows, int64_t n, double K,
+                                     double* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * n) return;
+    double s = 0.0;
+    for (int k = 0; k < n_split; ++k) s += partial[(int64_t)k * rows * n + i];
+    out[i] = K * s;
+}
+
 __global__ void zero_counters_kernel(DevCounters* c)
 {
     unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
@@ -785,7 +810,8 @@ hipError_t far_colloc_launch(const FarArgs& a, hipStream_t s)
 {
     const int64_t per = (int64_t)kBlock * PPT;
     const int64_t blocks = (a.el.ne + per - 1) / per;
-    far_colloc_kernel<NT, NR, MIXED, PPT><<<dim3((unsigned)blocks), dim3(kBlock), 0, s>>>(a);
+    if (blocks > 0x7fffffff || a.n_split < 1 || a.n_split > 65535) return hipErrorInvalidValue;
+    far_colloc_kernel<NT, NR, MIXED, PPT><<<dim3((unsigned)blocks, (unsigned)a.n_split), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -833,6 +859,15 @@ hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, do
 {
     if (n <= 0) return hipSuccess;
     reduce_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, n_split, n, K, phi, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows, int64_t n, double K, double* out,
+                                hipStream_t s)
+{
+    const int64_t tot = rows * n;
+    if (tot <= 0) return hipSuccess;
+    reduce_chunks_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(partial, n_split, rows, n, K, out);
     return hipGetLastError();
 }
 
