@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("tri_rule", ctypes.c_int), ("rect_gl_n", ctypes.c_int),
                 ("rect_table_n", ctypes.c_int), ("near_dr", ctypes.c_double),
-                ("max_depth", ctypes.c_int)]
+                ("max_depth", ctypes.c_int), ("dr_rules", ctypes.c_int),
+                ("tri_dr", ctypes.c_double * 3), ("rect_dr", ctypes.c_double * 3)]
 
 
 class _Stats(ctypes.Structure):
@@ -86,8 +87,17 @@ def _f64(a, shape_last=None):
     return a
 
 
-def params(tri_rule=33, rect_gl_n=7, rect_table_n=0, near_dr=3.0, max_depth=24):
-    return _Params(tri_rule, rect_gl_n, rect_table_n, near_dr, max_depth)
+# distance-ratio limits of the rule levels (triangles 7/12/19 points, rectangles Tables
+# B2/B3/B4): the paper's potential limits for triangles scaled by 1.25 for the field,
+# rectangle limits from the same field-error criterion
+TRI_DR = (100.0, 25.0, 10.0)
+RECT_DR = (150.0, 40.0, 15.0)
+
+
+def params(tri_rule=33, rect_gl_n=7, rect_table_n=0, near_dr=3.0, max_depth=24, dr_rules=False,
+           tri_dr=TRI_DR, rect_dr=RECT_DR):
+    return _Params(tri_rule, rect_gl_n, rect_table_n, near_dr, max_depth, int(dr_rules),
+                   (ctypes.c_double * 3)(*tri_dr), (ctypes.c_double * 3)(*rect_dr))
 
 
 def coulomb_constant() -> float:

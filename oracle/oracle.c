@@ -352,38 +352,49 @@ int orc_element_geometry(int kind, const double* geom, double* centroid, double*
 typedef struct {
     tri_rule tri;
     rect_rule rect;
+    tri_rule tri_lv[3];   /* 7, 12, 19 points (distance-ratio-dependent choice) */
+    rect_rule rect_lv[3]; /* Tables B2, B3, B4 */
 } rules;
 
+static void apply_rules(const double* P, int kind, const double* g, double area, const tri_rule* TR,
+                        const rect_rule* RR, double* acc);
+
 static void apply_rule(const double* P, int kind, const double* g, double area, const rules* R, double* acc)
+{
+    apply_rules(P, kind, g, area, &R->tri, &R->rect, acc);
+}
+
+static void apply_rules(const double* P, int kind, const double* g, double area, const tri_rule* TR,
+                        const rect_rule* RR, double* acc)
 {
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     if (kind == 0) {
         const double *A = g, *B = g + 3, *C = g + 6;
-        for (int i = 0; i < R->tri.n; ++i) {
-            const double* l = R->tri.lam[i];
+        for (int i = 0; i < TR->n; ++i) {
+            const double* l = TR->lam[i];
             double Q[3], d[3];
             for (int k = 0; k < 3; ++k) Q[k] = l[0] * A[k] + l[1] * B[k] + l[2] * C[k];
             sub3(P, Q, d);
             double r = norm3(d);
             double inv = 1.0 / r;
-            double f = R->tri.w[i] * inv * inv * inv;
-            phi += R->tri.w[i] * inv;
+            double f = TR->w[i] * inv * inv * inv;
+            phi += TR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
         }
     } else {
         const double *P0 = g, *e1 = g + 3, *e2 = g + 6;
         double cen[3];
         for (int k = 0; k < 3; ++k) cen[k] = P0[k] + 0.5 * e1[k] + 0.5 * e2[k];
-        for (int i = 0; i < R->rect.n; ++i) {
-            double x = R->rect.xy[i][0], y = R->rect.xy[i][1];
+        for (int i = 0; i < RR->n; ++i) {
+            double x = RR->xy[i][0], y = RR->xy[i][1];
             double Q[3], d[3];
             /* Q = Q_cen + (a/2) x u_x + (b/2) y u_y = Q_cen + (x/2) e1 + (y/2) e2 */
             for (int k = 0; k < 3; ++k) Q[k] = cen[k] + 0.5 * x * e1[k] + 0.5 * y * e2[k];
             sub3(P, Q, d);
             double r = norm3(d);
             double inv = 1.0 / r;
-            double f = R->rect.w[i] * inv * inv * inv;
-            phi += R->rect.w[i] * inv;
+            double f = RR->w[i] * inv * inv * inv;
+            phi += RR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
         }
     }
@@ -566,6 +577,17 @@ static void element_contribution(const double* P, const elem* e, const rules* R,
     elem le;
     to_local(P, e, Pl, &le);
     if (!(D2 < thr * thr)) { /* far: DR >= threshold */
+        if (prm->dr_rules) {
+            /* the coarsest rule whose distance-ratio limit the pair meets */
+            const double* lim = e->kind == 0 ? prm->tri_dr : prm->rect_dr;
+            for (int lv = 0; lv < 3; ++lv) {
+                const double t = lim[lv] * e->L;
+                if (D2 >= t * t) {
+                    apply_rules(Pl, le.kind, le.g, le.area, &R->tri_lv[lv], &R->rect_lv[lv], out);
+                    return;
+                }
+            }
+        }
         apply_rule(Pl, le.kind, le.g, le.area, R, out);
         return;
     }
@@ -589,6 +611,11 @@ static int build_rules(const orc_params* prm, rules* R)
     if (build_tri_rule(prm->tri_rule, &R->tri) < 0) return -1;
     if (build_rect_rule(prm->rect_gl_n, prm->rect_table_n, &R->rect) < 0) return -1;
     if (!(prm->near_dr > 0.0)) return -1;
+    const int tl[3] = { 7, 12, 19 }, rl[3] = { 7, 12, 17 };
+    for (int lv = 0; lv < 3; ++lv) {
+        build_tri_rule(tl[lv], &R->tri_lv[lv]);
+        build_rect_rule(0, rl[lv], &R->rect_lv[lv]);
+    }
     return 0;
 }
 

@@ -46,6 +46,12 @@ typedef struct {
     int rect_table_n;  /* used when rect_gl_n == 0: 4, 7, 12, 17, 33 */
     double near_dr;    /* distance-ratio threshold (3.0) */
     int max_depth;     /* subdivision depth cap */
+    int dr_rules;      /* 1: far pairs take a rule by distance ratio (Sec. 4, rule choice by DR):
+                          triangles 7 / 12 / 19 points for DR >= tri_dr[0] / tri_dr[1] /
+                          tri_dr[2], else tri_rule; rectangles Tables B2 / B3 / B4 for
+                          DR >= rect_dr[0..2], else the rectangle rule above */
+    double tri_dr[3];
+    double rect_dr[3];
 } orc_params;
 
 /* Counters of one call. */
