@@ -73,7 +73,8 @@ typedef struct bemc_context* bemc_handle;
 /* Counters of the last bemc_eval / bemc_collocation_matvec on a context. */
 typedef struct {
     int64_t pairs;          /* field points x elements */
-    int64_t node_interactions; /* point-charge terms of the far-field sums */
+    int64_t node_interactions; /* point-charge terms of the far-field sums (far pairs only
+                                  when the rule is chosen by distance ratio) */
     int64_t near_pairs;     /* pairs with D < near_dr * L (handled in FP64) */
     int64_t leaves;         /* rule applications made by the subdivision */
     int64_t cap_hits;       /* leaves still near at the depth cap */
@@ -95,12 +96,27 @@ int bemc_create(int device, bemc_handle* out);
 /* Release every device buffer of the context (waits for its pending work). */
 int bemc_destroy(bemc_handle h);
 
-/* Cubature rules and near-field parameters (Sec. 3, Tables A1-A5; Sec. 4 distance-ratio
- * switch).  tri_rule in {4, 7, 12, 19, 33}; rect_gl_n in 1..16 (rect_gl_n^2 points);
- * near_dr > 0 (pairs with D < near_dr * L are subdivided); max_depth in 0..30.
- * Takes effect for subsequent uploads and evaluations; node tables are rebuilt.
+/* Cubature rules and near-field parameters (Sec. 3, Tables A1-A5, B1-B5; Sec. 4
+ * distance-ratio switch).  tri_rule in {4, 7, 12, 19, 33}; rect_rule in 1..16 for the
+ * tensor Gauss-Legendre rule with rect_rule^2 points, or -4, -7, -12, -17, -33 for Table
+ * B1..B5 (App. B); near_dr > 0 (pairs with D < near_dr * L are subdivided); max_depth in
+ * 0..30.  Takes effect for subsequent evaluations; node tables are rebuilt.
  * Errors: INVALID_ARG. */
-int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, int max_depth);
+int bemc_set_rules(bemc_handle h, int tri_rule, int rect_rule, double near_dr, int max_depth);
+
+/* Rule choice by distance ratio for far pairs (Sec. 4: the fewest Gaussian points that
+ * reach the accuracy floor at the pair's distance ratio; field limits somewhat above the
+ * potential limits).  enable = 0 restores one rule per element kind.  When enabled, a far
+ * triangle pair uses 7 / 12 / 19 points (Tables A2 / A3 / A4) for DR >= tri_dr[0] /
+ * tri_dr[1] / tri_dr[2], else the triangle rule of bemc_set_rules; a far rectangle pair
+ * uses Tables B2 / B3 / B4 for DR >= rect_dr[0..2], else the rectangle rule.  NULL
+ * arrays select the defaults {100, 25, 10} and {150, 40, 15} (the paper's triangle
+ * potential limits x 1.25; the rectangle tables' field-accuracy limits).  bemc_eval then
+ * orders the field points along a Morton curve internally so that neighbouring lanes
+ * choose the same rule; results are returned in the caller's order.  Near pairs and
+ * collocation are unaffected.  Errors: INVALID_ARG (limits not decreasing or below
+ * near_dr). */
+int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const double* rect_dr);
 
 /* Upload the electrode geometry (host arrays in the element input format; either count
  * may be 0, n_tri + n_rect < 2^31).  Validates every element (finite, positive area,

@@ -33,7 +33,8 @@ _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 EXPORTED = ["bemc_last_error", "bemc_create", "bemc_destroy", "bemc_set_rules", "bemc_upload_geometry",
             "bemc_upload_densities", "bemc_eval", "bemc_collocation_matvec", "bemc_query_stats",
             "bemc_server_start", "bemc_server_submit", "bemc_server_poll", "bemc_server_wait",
-            "bemc_server_stop", "bemc_coulomb_constant", "bemc_rule_size", "bemc_set_near_capacity"]
+            "bemc_server_stop", "bemc_coulomb_constant", "bemc_rule_size", "bemc_set_near_capacity",
+            "bemc_set_dr_rules"]
 
 
 class BemcError(RuntimeError):
@@ -88,6 +89,7 @@ def load_library():
     lib.bemc_collocation_matvec.argtypes = [vp, vp, ci, ci, vp, vp]
     lib.bemc_query_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.bemc_set_near_capacity.argtypes = [vp, i64]
+    lib.bemc_set_dr_rules.argtypes = [vp, ci, vp, vp]
     lib.bemc_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig)]
     lib.bemc_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.bemc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(QueryInfo)]
@@ -161,8 +163,14 @@ class Context:
         self.close()
 
     # -- setup
-    def set_rules(self, tri_rule=33, rect_gl_n=7, near_dr=3.0, max_depth=24):
-        _check(self.lib.bemc_set_rules(self.h, tri_rule, rect_gl_n, float(near_dr), max_depth))
+    def set_rules(self, tri_rule=33, rect_rule=7, near_dr=3.0, max_depth=24):
+        """rect_rule > 0: Gauss-Legendre rect_rule x rect_rule; < 0: Table B with -rect_rule points."""
+        _check(self.lib.bemc_set_rules(self.h, tri_rule, rect_rule, float(near_dr), max_depth))
+
+    def set_dr_rules(self, enable=True, tri_dr=None, rect_dr=None):
+        t = None if tri_dr is None else (ctypes.c_double * 3)(*tri_dr)
+        r = None if rect_dr is None else (ctypes.c_double * 3)(*rect_dr)
+        _check(self.lib.bemc_set_dr_rules(self.h, int(enable), t, r))
 
     def upload_geometry(self, tri, rect):
         tri = np.ascontiguousarray(np.zeros((0, 9)) if tri is None else tri, dtype=np.float64).reshape(-1, 9)

@@ -62,13 +62,25 @@ void dev_free(T*& p)
 
 struct bemc_context {
     int device = 0;
-    int tri_rule = 33, rect_gl_n = 7, max_depth = 24;
+    int tri_rule = 33, rect_gl_n = 7, max_depth = 24;  // rect_gl_n < 0: Table B with -rect_gl_n points
     double near_dr = 3.0;
 
     // rule tables (device)
     double *d_tri = nullptr, *d_rect = nullptr;
     float *d_tri32 = nullptr, *d_rect32 = nullptr;
     int nt = 0, nr = 0;
+    // rule choice by distance ratio: level tables and limits
+    bool dr_rules = false;
+    double tri_dr[3] = { 100.0, 25.0, 10.0 }, rect_dr[3] = { 150.0, 40.0, 15.0 };
+    double *d_lv_tri = nullptr, *d_lv_rect = nullptr;
+    float *d_lv_tri32 = nullptr, *d_lv_rect32 = nullptr;
+    int lv_tri_off[5] = { 0, 0, 0, 0, 0 }, lv_rect_off[5] = { 0, 0, 0, 0, 0 };
+    // Morton ordering workspace
+    OrderWork ow{};
+    int64_t ow_cap = 0;
+    int ensure_order(int64_t n);
+    void free_order();
+    LevelRules levels() const;
 
     // elements (device)
     int64_t n_tri = 0, n_rect = 0, ne = 0;
@@ -114,34 +126,114 @@ RuleTables bemc_context::rules() const
     return r;
 }
 
+namespace {
+void pack_tri(const std::vector<TriNode>& tn, std::vector<double>& t64)
+{
+    for (const auto& n : tn) {
+        t64.push_back(n.la); t64.push_back(n.lb); t64.push_back(n.lc); t64.push_back(n.w);
+    }
+}
+void pack_rect(const std::vector<RectNode>& rn, std::vector<double>& r64)
+{
+    for (const auto& n : rn) {
+        r64.push_back(n.x); r64.push_back(n.y); r64.push_back(n.w); r64.push_back(0.0);
+    }
+}
+bool rect_rule_nodes(int spec, std::vector<RectNode>& rn)
+{
+    return spec > 0 ? rectangle_gauss_rule(spec, rn) : rectangle_table_rule(-spec, rn);
+}
+// FP64 and FP32 copies of a node table on the device
+int upload_table(const std::vector<double>& t64, double** d64, float** d32)
+{
+    std::vector<float> t32(t64.size());
+    for (size_t i = 0; i < t64.size(); ++i) t32[i] = (float)t64[i];
+    dev_free(*d64);
+    dev_free(*d32);
+    HIP_TRY(dev_alloc(d64, t64.size()));
+    HIP_TRY(dev_alloc(d32, t32.size()));
+    HIP_TRY(hipMemcpy(*d64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(*d32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+    return BEMC_OK;
+}
+}  // namespace
+
 int bemc_context::set_rules_tables()
 {
     std::vector<TriNode> tn;
     std::vector<RectNode> rn;
     if (!triangle_rule(tri_rule, tn)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
-    if (!rectangle_gauss_rule(rect_gl_n, rn)) return fail(BEMC_E_INVALID_ARG, "invalid rectangle Gauss order %d", rect_gl_n);
-    std::vector<double> t64(4 * tn.size()), r64(4 * rn.size());
-    std::vector<float> t32(t64.size()), r32(r64.size());
-    for (size_t i = 0; i < tn.size(); ++i) {
-        t64[4 * i] = tn[i].la; t64[4 * i + 1] = tn[i].lb; t64[4 * i + 2] = tn[i].lc; t64[4 * i + 3] = tn[i].w;
-    }
-    for (size_t i = 0; i < rn.size(); ++i) {
-        r64[4 * i] = rn[i].x; r64[4 * i + 1] = rn[i].y; r64[4 * i + 2] = rn[i].w; r64[4 * i + 3] = 0.0;
-    }
-    for (size_t i = 0; i < t64.size(); ++i) t32[i] = (float)t64[i];
-    for (size_t i = 0; i < r64.size(); ++i) r32[i] = (float)r64[i];
+    if (!rect_rule_nodes(rect_gl_n, rn)) return fail(BEMC_E_INVALID_ARG, "invalid rectangle rule %d", rect_gl_n);
     HIP_TRY(hipSetDevice(device));
-    dev_free(d_tri); dev_free(d_rect); dev_free(d_tri32); dev_free(d_rect32);
-    HIP_TRY(dev_alloc(&d_tri, t64.size()));
-    HIP_TRY(dev_alloc(&d_rect, r64.size()));
-    HIP_TRY(dev_alloc(&d_tri32, t32.size()));
-    HIP_TRY(dev_alloc(&d_rect32, r32.size()));
-    HIP_TRY(hipMemcpy(d_tri, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_rect, r64.data(), r64.size() * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_tri32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d_rect32, r32.data(), r32.size() * 4, hipMemcpyHostToDevice));
+    std::vector<double> t64, r64;
+    pack_tri(tn, t64);
+    pack_rect(rn, r64);
+    int rc = upload_table(t64, &d_tri, &d_tri32);
+    if (rc) return rc;
+    if ((rc = upload_table(r64, &d_rect, &d_rect32))) return rc;
     nt = (int)tn.size();
     nr = (int)rn.size();
+    // levels of the distance-ratio rule choice: 7 / 12 / 19 / tri_rule and B2 / B3 / B4 / rect rule
+    std::vector<double> lt, lr;
+    const int tl[3] = { 7, 12, 19 }, rl[3] = { 7, 12, 17 };
+    lv_tri_off[0] = lv_rect_off[0] = 0;
+    for (int l = 0; l < 4; ++l) {
+        std::vector<TriNode> a;
+        std::vector<RectNode> b;
+        if (l < 3) {
+            triangle_rule(tl[l], a);
+            rectangle_table_rule(rl[l], b);
+        } else {
+            a = tn;
+            b = rn;
+        }
+        pack_tri(a, lt);
+        pack_rect(b, lr);
+        lv_tri_off[l + 1] = lv_tri_off[l] + (int)a.size();
+        lv_rect_off[l + 1] = lv_rect_off[l] + (int)b.size();
+    }
+    if ((rc = upload_table(lt, &d_lv_tri, &d_lv_tri32))) return rc;
+    if ((rc = upload_table(lr, &d_lv_rect, &d_lv_rect32))) return rc;
+    return ok();
+}
+
+LevelRules bemc_context::levels() const
+{
+    LevelRules L{};
+    L.tab.tri = d_lv_tri; L.tab.rect = d_lv_rect; L.tab.tri32 = d_lv_tri32; L.tab.rect32 = d_lv_rect32;
+    L.tab.nt = lv_tri_off[4]; L.tab.nr = lv_rect_off[4];
+    for (int i = 0; i < 5; ++i) { L.tri_off[i] = lv_tri_off[i]; L.rect_off[i] = lv_rect_off[i]; }
+    for (int i = 0; i < 3; ++i) {
+        L.tri_c[i] = (tri_dr[i] / near_dr) * (tri_dr[i] / near_dr);
+        L.rect_c[i] = (rect_dr[i] / near_dr) * (rect_dr[i] / near_dr);
+    }
+    return L;
+}
+
+void bemc_context::free_order()
+{
+    dev_free(ow.keys_in); dev_free(ow.keys_out); dev_free(ow.idx_in); dev_free(ow.perm);
+    if (ow.temp) (void)hipFree(ow.temp);
+    ow.temp = nullptr;
+    dev_free(ow.bbox); dev_free(ow.pts); dev_free(ow.phi); dev_free(ow.E);
+    ow_cap = 0;
+}
+
+int bemc_context::ensure_order(int64_t n)
+{
+    if (n <= ow_cap && order_temp_bytes(n) <= ow.temp_bytes) return ok();
+    n = std::max(n, ow_cap);
+    free_order();
+    const size_t m = (size_t)n;
+    ow.temp_bytes = order_temp_bytes(n);
+    if (dev_alloc(&ow.keys_in, m) || dev_alloc(&ow.keys_out, m) || dev_alloc(&ow.idx_in, m) || dev_alloc(&ow.perm, m) ||
+        hipMalloc(&ow.temp, std::max<size_t>(ow.temp_bytes, 1)) || dev_alloc(&ow.bbox, 6 * 1024) ||
+        dev_alloc(&ow.pts, 3 * m) || dev_alloc(&ow.phi, m) || dev_alloc(&ow.E, 3 * m)) {
+        (void)hipGetLastError();
+        free_order();
+        return fail(BEMC_E_OUT_OF_MEMORY, "point-ordering workspace for %lld points", (long long)n);
+    }
+    ow_cap = n;
     return ok();
 }
 
@@ -164,6 +256,18 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
                       double* phi, double* E, hipStream_t s)
 {
     HIP_TRY(hipSetDevice(device));
+    // rule choice by distance ratio: evaluate on Morton-ordered points, scatter back at the end
+    const bool ordered = dr_rules && !colloc;
+    double* user_phi = phi;
+    double* user_E = E;
+    if (ordered) {
+        int rc = ensure_order(n);
+        if (rc) return rc;
+        HIP_TRY(order_points(pts, n, ow, s));
+        pts = ow.pts;
+        phi = ow.phi;
+        E = ow.E;
+    }
     if (near_cap == 0) {
         int rc = ensure_near_capacity(std::max<unsigned long long>(1ull << 20, (unsigned long long)(colloc ? ne : n) * 8));
         if (rc) return rc;
@@ -175,6 +279,8 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant(); fa.phi = phi; fa.E = E; fa.partial = nullptr;
         fa.elem_begin = 0; fa.elem_end = ne; fa.n_split = 1; fa.chunk = ne; fa.near_list = d_near; fa.near_cap = near_cap;
         fa.ctr = d_ctr;
+        fa.dr_rules = (dr_rules && !colloc) ? 1 : 0;
+        fa.lv = levels();
         NearArgs na{};
         na.el = fa.el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = fa.n; na.rhs = rhs;
         na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.near_list = d_near; na.near_cap = near_cap;
@@ -214,6 +320,7 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(launch_near(na, colloc, s));
         HIP_TRY(hipEventRecord(ev[2], s));
+        if (ordered) HIP_TRY(unorder_results(ow, n, user_phi, user_E, s));
         HIP_TRY(hipMemcpyAsync(h_ctr, d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(ev[3], s));
         HIP_TRY(hipEventSynchronize(ev[3]));
@@ -228,7 +335,8 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         HIP_TRY(hipEventElapsedTime(&near_ms, ev[1], ev[2]));
         last = bemc_stats{};
         last.pairs = npts * ne;
-        last.node_interactions = npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
+        last.node_interactions = fa.dr_rules ? (int64_t)h_ctr->node_ints
+                                             : npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
         last.near_pairs = (int64_t)found;
         last.leaves = (int64_t)h_ctr->leaves;
         last.cap_hits = (int64_t)h_ctr->cap_hits;
@@ -299,6 +407,8 @@ int bemc_destroy(bemc_handle h)
     (void)hipDeviceSynchronize();
     free_elements(h);
     dev_free(h->d_tri); dev_free(h->d_rect); dev_free(h->d_tri32); dev_free(h->d_rect32);
+    dev_free(h->d_lv_tri); dev_free(h->d_lv_rect); dev_free(h->d_lv_tri32); dev_free(h->d_lv_rect32);
+    h->free_order();
     dev_free(h->d_near); dev_free(h->d_ctr); dev_free(h->d_partial);
     if (h->h_ctr) (void)hipHostFree(h->h_ctr);
     for (auto& e : h->ev)
@@ -315,7 +425,11 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
     if (max_depth < 0 || max_depth > 30) return fail(BEMC_E_INVALID_ARG, "max_depth must be in 0..30");
     std::vector<TriNode> t;
     if (!triangle_rule(tri_rule, t)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
-    if (rect_gl_n < 1 || rect_gl_n > 16) return fail(BEMC_E_INVALID_ARG, "rect_gl_n must be in 1..16");
+    {
+        std::vector<RectNode> rn;
+        if (rect_gl_n == 0 || rect_gl_n > 16 || (rect_gl_n < 0 && !rectangle_table_rule(-rect_gl_n, rn)))
+            return fail(BEMC_E_INVALID_ARG, "rectangle rule must be 1..16 (Gauss n x n) or -4/-7/-12/-17/-33 (Table B)");
+    }
     const int old_t = h->tri_rule, old_r = h->rect_gl_n;
     h->tri_rule = tri_rule;
     h->rect_gl_n = rect_gl_n;
@@ -505,6 +619,22 @@ int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int p
     return h->run(true, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
 }
 
+int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const double* rect_dr)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "rules cannot change while serving");
+    double t[3] = { 100.0, 25.0, 10.0 }, r[3] = { 150.0, 40.0, 15.0 };
+    if (tri_dr) std::copy(tri_dr, tri_dr + 3, t);
+    if (rect_dr) std::copy(rect_dr, rect_dr + 3, r);
+    for (const double* v : { t, r })
+        if (!(v[0] >= v[1] && v[1] >= v[2] && v[2] >= h->near_dr) || !std::isfinite(v[0]))
+            return fail(BEMC_E_INVALID_ARG, "limits must be finite, decreasing and >= near_dr");
+    h->dr_rules = enable != 0;
+    std::copy(t, t + 3, h->tri_dr);
+    std::copy(r, r + 3, h->rect_dr);
+    return ok();
+}
+
 int bemc_set_near_capacity(bemc_handle h, int64_t pairs)
 {
     if (!h || pairs < 1) return fail(BEMC_E_INVALID_ARG, "invalid capacity");
@@ -541,6 +671,8 @@ int bemc_server_start(bemc_handle h, const bemc_server_config* cfg)
     env.max_depth = h->max_depth;
     env.n_tri = h->n_tri;
     env.n_rect = h->n_rect;
+    env.dr_rules = h->dr_rules ? 1 : 0;
+    env.lv = h->levels();
     std::string err;
     bemc::Server* s = bemc::Server::create(env, *cfg, err);
     if (!s) return fail(BEMC_E_INVALID_ARG, "%s", err.c_str());

@@ -19,6 +19,7 @@ struct RectNode {
 bool triangle_rule(int n, std::vector<TriNode>& out);
 bool gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 bool rectangle_gauss_rule(int n, std::vector<RectNode>& out);
+bool rectangle_table_rule(int n, std::vector<RectNode>& out);
 
 constexpr int kMaxTriNodes = 64;
 constexpr int kMaxRectNodes = 256;
@@ -51,6 +52,17 @@ struct Elements {
     int n_rhs;
 };
 
+// Rule choice by distance ratio: four levels per element kind, coarsest first
+// (triangles 7/12/19/tri_rule points, rectangles Tables B2/B3/B4 then the rectangle rule).
+// The level tables hold the nodes of all four levels back to back.
+struct LevelRules {
+    RuleTables tab;       // tri: [7 | 12 | 19 | nt] nodes, rect: [7 | 12 | 17 | nr] nodes
+    int tri_off[5];       // node offsets of the levels within an element's staged nodes
+    int rect_off[5];
+    double tri_c[3];      // level l is used when D^2 >= tri_c[l] * (near_dr L)^2
+    double rect_c[3];
+};
+
 struct NearPair {
     uint32_t point;
     uint32_t elem;
@@ -65,7 +77,7 @@ struct DevCounters {
     unsigned long long on_surface;
     unsigned long long max_depth;
     unsigned long long visit_limit_hits;
-    unsigned long long pad;
+    unsigned long long node_ints;  // point-charge terms summed (rule choice by distance ratio)
 };
 
 // Arguments of the far-field kernels.
@@ -86,6 +98,8 @@ struct FarArgs {
     NearPair* near_list;
     unsigned long long near_cap;
     DevCounters* ctr;
+    int dr_rules;            // 1: per-pair rule choice by distance ratio (levels below)
+    LevelRules lv;
 };
 
 struct NearArgs {
@@ -122,5 +136,19 @@ constexpr int kSplitTargetBlocks = 16 * 1024;
 constexpr int kMaxSplit = 64;
 
 double coulomb_constant();
+
+// Morton ordering of field points (order.hip).  Buffers sized for n points.
+struct OrderWork {
+    uint32_t *keys_in, *keys_out, *idx_in, *perm;
+    void* temp;
+    size_t temp_bytes;
+    double* bbox;    // [1024][6]
+    double* pts;     // [3][n] points in sorted order
+    double* phi;     // [n]    results in sorted order
+    double* E;       // [3][n]
+};
+size_t order_temp_bytes(int64_t n);
+hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStream_t s);
+hipError_t unorder_results(const OrderWork& w, int64_t n, double* phi, double* E, hipStream_t s);
 
 }  // namespace bemc

@@ -148,8 +148,91 @@ struct PointSet {
     double phi[PPT], ex[PPT], ey[PPT], ez[PPT];
 };
 
-// One element kind over [e_begin, e_end); NN > 0 is the compile-time node count, NN == 0
-// reads it at run time.
+// Point-charge sums of one element (Eq. 4.1) over its Gaussian points nd[0 .. n) for PPT
+// field points given by their offsets from the element centroid; unit element charge.
+// NN > 0: compile-time node count.
+template <int NN, int PPT>
+__device__ __forceinline__ void node_sum64(const double4* __restrict__ nd, int nn, const double (&dx)[PPT],
+                                           const double (&dy)[PPT], const double (&dz)[PPT], double (&f)[PPT],
+                                           double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT])
+{
+    const int n = NN > 0 ? NN : nn;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) {
+        const double4 Q = nd[i];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+            const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+            const double ri = rsqrt64(r2);
+            const double wr = Q.w * ri;
+            f[k] += wr;
+            const double w3 = wr * (ri * ri);
+            gx[k] = fma(w3, rx, gx[k]);
+            gy[k] = fma(w3, ry, gy[k]);
+            gz[k] = fma(w3, rz, gz[k]);
+        }
+    }
+}
+
+template <int NN, int PPT>
+__device__ __forceinline__ void node_sum32(const float4* __restrict__ nd, int nn, const float (&dx)[PPT],
+                                           const float (&dy)[PPT], const float (&dz)[PPT], float (&f)[PPT],
+                                           float (&gx)[PPT], float (&gy)[PPT], float (&gz)[PPT])
+{
+    const int n = NN > 0 ? NN : nn;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0f;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) {
+        const float4 Q = nd[i];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const float rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+            const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+            const float ri = rsqrt32(r2);
+            const float wr = Q.w * ri;
+            f[k] += wr;
+            const float w3 = wr * (ri * ri);
+            gx[k] = fmaf(w3, rx, gx[k]);
+            gy[k] = fmaf(w3, ry, gy[k]);
+            gz[k] = fmaf(w3, rz, gz[k]);
+        }
+    }
+}
+
+// Element sums for the nodes [o, o + n) of element j of the tile: FP64, or FP32 on offsets
+// from the centroid with the result widened to FP64.
+template <int NN, bool MIXED, int PPT, typename Lds>
+__device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const double (&dx)[PPT],
+                                            const double (&dy)[PPT], const double (&dz)[PPT], double (&f)[PPT],
+                                            double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT])
+{
+    if (!MIXED) {
+        node_sum64<NN, PPT>(reinterpret_cast<const double4*>(s.node) + base, n, dx, dy, dz, f, gx, gy, gz);
+    } else {
+        float fx[PPT], fy[PPT], fz[PPT], ff[PPT], fgx[PPT], fgy[PPT], fgz[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            fx[k] = (float)dx[k];
+            fy[k] = (float)dy[k];
+            fz[k] = (float)dz[k];
+        }
+        node_sum32<NN, PPT>(reinterpret_cast<const float4*>(s.node) + base, n, fx, fy, fz, ff, fgx, fgy, fgz);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            f[k] = (double)ff[k];
+            gx[k] = (double)fgx[k];
+            gy[k] = (double)fgy[k];
+            gz[k] = (double)fgz[k];
+        }
+    }
+}
+
+// One element kind over [e_begin, e_end) with one rule; NN > 0 is the compile-time node
+// count, NN == 0 reads it at run time.
 template <int NN, bool TRI, bool MIXED, int PPT, typename Lds>
 __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT>& P, int64_t e_begin,
                                                int64_t e_end)
@@ -174,77 +257,111 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
                 nr[k] = P.valid[k] && (D2 < thr2);
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
-            if (!MIXED) {
-                double f[PPT], gx[PPT], gy[PPT], gz[PPT];
+            double f[PPT], gx[PPT], gy[PPT], gz[PPT];
+            element_sum<NN, MIXED, PPT>(s, j * nn, nn, dx, dy, dz, f, gx, gy, gz);
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
-                const double4* nd = reinterpret_cast<const double4*>(s.node) + j * nn;
-#pragma unroll 4
-                for (int i = 0; i < nn; ++i) {
-                    const double4 Q = nd[i];
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-                        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-                        const double ri = rsqrt64(r2);
-                        const double wr = Q.w * ri;
-                        f[k] += wr;
-                        const double w3 = wr * (ri * ri);
-                        gx[k] = fma(w3, rx, gx[k]);
-                        gy[k] = fma(w3, ry, gy[k]);
-                        gz[k] = fma(w3, rz, gz[k]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (!nr[k]) {
-                        P.phi[k] = fma(q, f[k], P.phi[k]);
-                        P.ex[k] = fma(q, gx[k], P.ex[k]);
-                        P.ey[k] = fma(q, gy[k], P.ey[k]);
-                        P.ez[k] = fma(q, gz[k], P.ez[k]);
-                    }
-                }
-            } else {
-                float f[PPT], gx[PPT], gy[PPT], gz[PPT], fx[PPT], fy[PPT], fz[PPT];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    f[k] = gx[k] = gy[k] = gz[k] = 0.0f;
-                    fx[k] = (float)dx[k];
-                    fy[k] = (float)dy[k];
-                    fz[k] = (float)dz[k];
-                }
-                const float4* nd = reinterpret_cast<const float4*>(s.node) + j * nn;
-#pragma unroll 4
-                for (int i = 0; i < nn; ++i) {
-                    const float4 Q = nd[i];
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const float rx = fx[k] - Q.x, ry = fy[k] - Q.y, rz = fz[k] - Q.z;
-                        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-                        const float ri = rsqrt32(r2);
-                        const float wr = Q.w * ri;
-                        f[k] += wr;
-                        const float w3 = wr * (ri * ri);
-                        gx[k] = fmaf(w3, rx, gx[k]);
-                        gy[k] = fmaf(w3, ry, gy[k]);
-                        gz[k] = fmaf(w3, rz, gz[k]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (!nr[k]) {
-                        P.phi[k] = fma(q, (double)f[k], P.phi[k]);
-                        P.ex[k] = fma(q, (double)gx[k], P.ex[k]);
-                        P.ey[k] = fma(q, (double)gy[k], P.ey[k]);
-                        P.ez[k] = fma(q, (double)gz[k], P.ez[k]);
-                    }
+            for (int k = 0; k < PPT; ++k) {
+                if (!nr[k]) {
+                    P.phi[k] = fma(q, f[k], P.phi[k]);
+                    P.ex[k] = fma(q, gx[k], P.ex[k]);
+                    P.ey[k] = fma(q, gy[k], P.ey[k]);
+                    P.ez[k] = fma(q, gz[k], P.ez[k]);
                 }
             }
         }
     }
 }
 
-template <int NT, int NR, bool MIXED, int PPT>
+// One level of the distance-ratio rule choice: the wavefront runs the level's nodes only
+// if one of its lanes needs it; lanes whose points took another level discard the result.
+template <int NN, bool MIXED, int PPT, typename Lds>
+__device__ __forceinline__ void level_sum(const Lds& s, int base, int n, int lv, const int (&lvl)[PPT],
+                                          const double (&dx)[PPT], const double (&dy)[PPT], const double (&dz)[PPT],
+                                          double (&f)[PPT], double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT],
+                                          unsigned long long& terms)
+{
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) any |= (lvl[k] == lv);
+    if (__ballot(any) == 0ull) return;
+    double tf[PPT], tx[PPT], ty[PPT], tz[PPT];
+    element_sum<NN, MIXED, PPT>(s, base, n, dx, dy, dz, tf, tx, ty, tz);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (lvl[k] == lv) {
+            f[k] = tf[k];
+            gx[k] = tx[k];
+            gy[k] = ty[k];
+            gz[k] = tz[k];
+            terms += (unsigned)n;
+        }
+}
+
+// One element kind with the rule chosen per pair by distance ratio (Sec. 4): the staged
+// nodes of an element are the four levels back to back; level l is used when
+// D^2 >= c[l] (near_dr L)^2, the last level otherwise.  N0..N3 > 0: compile-time counts.
+template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, typename Lds>
+__device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT>& P, int64_t e_begin,
+                                                  int64_t e_end, unsigned long long& terms)
+{
+    const int* off = TRI ? a.lv.tri_off : a.lv.rect_off;
+    const double* c = TRI ? a.lv.tri_c : a.lv.rect_c;
+    const int o1 = off[1], o2 = off[2], o3 = off[3], nn = off[4];
+    const double c0 = c[0], c1 = c[1], c2 = c[2];
+    const int TE = tile_elems(nn);
+    for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
+        const int te = (int)min((int64_t)TE, e_end - t0);
+        __syncthreads();
+        stage_tile<TRI, MIXED>(s, a.el, a.lv.tab, nn, t0, te, a.rhs, 1);
+        __syncthreads();
+        for (int j = 0; j < te; ++j) {
+            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j], q = s.q[0][j];
+            double dx[PPT], dy[PPT], dz[PPT];
+            bool nr[PPT];
+            int lvl[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                dx[k] = P.x[k] - cx;
+                dy[k] = P.y[k] - cy;
+                dz[k] = P.z[k] - cz;
+                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
+                nr[k] = P.valid[k] && (D2 < thr2);
+                record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+                lvl[k] = D2 >= c0 * thr2 ? 0 : (D2 >= c1 * thr2 ? 1 : (D2 >= c2 * thr2 ? 2 : 3));
+                if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
+            }
+            double f[PPT], gx[PPT], gy[PPT], gz[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
+            const int b = j * nn;
+            level_sum<N0, MIXED, PPT>(s, b, o1, 0, lvl, dx, dy, dz, f, gx, gy, gz, terms);
+            level_sum<N1, MIXED, PPT>(s, b + o1, o2 - o1, 1, lvl, dx, dy, dz, f, gx, gy, gz, terms);
+            level_sum<N2, MIXED, PPT>(s, b + o2, o3 - o2, 2, lvl, dx, dy, dz, f, gx, gy, gz, terms);
+            level_sum<N3, MIXED, PPT>(s, b + o3, nn - o3, 3, lvl, dx, dy, dz, f, gx, gy, gz, terms);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                P.phi[k] = fma(q, f[k], P.phi[k]);
+                P.ex[k] = fma(q, gx[k], P.ex[k]);
+                P.ey[k] = fma(q, gy[k], P.ey[k]);
+                P.ez[k] = fma(q, gz[k], P.ez[k]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void add_terms(unsigned long long terms, DevCounters* ctr)
+{
+    // wavefront sum, one atomic per wavefront
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)terms, o);
+        const unsigned hi = __shfl_xor((unsigned)(terms >> 32), o);
+        terms += ((unsigned long long)hi << 32) | lo;
+    }
+    if (lane_id() == 0 && terms) atomicAdd(&ctr->node_ints, terms);
+}
+
+// DR == false: one rule per kind, NT / NR nodes.  DR == true: levels (T0..T3 / R0..R3).
+template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT>
 __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
 {
     using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
@@ -267,9 +384,16 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
         e_hi = min(e_lo + a.chunk, a.elem_end);
     }
     const int64_t nt_end = min((int64_t)a.el.n_tri, e_hi);
-    if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT>(a, s, P, e_lo, nt_end);
     const int64_t nr_begin = max((int64_t)a.el.n_tri, e_lo);
-    if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT>(a, s, P, nr_begin, e_hi);
+    if (DR) {
+        unsigned long long terms = 0;
+        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT>(a, s, P, e_lo, nt_end, terms);
+        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT>(a, s, P, nr_begin, e_hi, terms);
+        add_terms(terms, a.ctr);
+    } else {
+        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT>(a, s, P, e_lo, nt_end);
+        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT>(a, s, P, nr_begin, e_hi);
+    }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (!P.valid[k]) continue;
@@ -781,13 +905,14 @@ __global__ void zero_counters_kernel(DevCounters* c)
     if (i < (int)(sizeof(DevCounters) / sizeof(unsigned long long))) w[i] = 0ull;
 }
 
-template <int NT, int NR, bool MIXED, int PPT>
+template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT>
 hipError_t far_eval_launch(const FarArgs& a, hipStream_t s)
 {
     const int64_t per = (int64_t)kBlock * PPT;
     const int64_t blocks = (a.n + per - 1) / per;
     if (blocks > 0x7fffffff || a.n_split < 1 || a.n_split > 65535) return hipErrorInvalidValue;
-    far_eval_kernel<NT, NR, MIXED, PPT><<<dim3((unsigned)blocks, (unsigned)a.n_split), dim3(kBlock), 0, s>>>(a);
+    far_eval_kernel<DR, NT, NR, T1, T2, T3, R1, R2, R3, MIXED, PPT>
+        <<<dim3((unsigned)blocks, (unsigned)a.n_split), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -795,14 +920,22 @@ template <bool MIXED>
 hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
 {
     constexpr int PPT = 2;
+    if (a.dr_rules) {
+        const int* t = a.lv.tri_off;
+        const int* r = a.lv.rect_off;
+        const bool std_levels = t[1] == 7 && t[2] == 19 && t[3] == 38 && r[1] == 7 && r[2] == 19 && r[3] == 36;
+        if (std_levels && t[4] - t[3] == 33 && r[4] - r[3] == 49)
+            return far_eval_launch<true, 7, 7, 12, 19, 33, 12, 17, 49, MIXED, PPT>(a, s);
+        return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+    }
     const int nt = a.rules.nt, nr = a.rules.nr;
     if (nr == 49) {
-        if (nt == 7) return far_eval_launch<7, 49, MIXED, PPT>(a, s);
-        if (nt == 12) return far_eval_launch<12, 49, MIXED, PPT>(a, s);
-        if (nt == 19) return far_eval_launch<19, 49, MIXED, PPT>(a, s);
-        if (nt == 33) return far_eval_launch<33, 49, MIXED, PPT>(a, s);
+        if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+        if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+        if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+        if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
     }
-    return far_eval_launch<0, 0, MIXED, PPT>(a, s);
+    return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
 }
 
 template <int NT, int NR, bool MIXED, int PPT>

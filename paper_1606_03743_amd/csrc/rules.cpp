@@ -10,7 +10,8 @@
 // Weights are normalised to sum 1 (Eq. 3.1).
 //
 // Rectangle rules: tensor Gauss-Legendre n x n on the natural coordinates of Eq. 3.2,
-// weights w_i w_j / 4; Legendre roots by Newton iteration on the three-term recurrence.
+// weights w_i w_j / 4 (Legendre roots by Newton iteration on the three-term recurrence),
+// or the tables of App. B.
 #include <cmath>
 #include <vector>
 
@@ -159,6 +160,92 @@ bool gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
     }
     if (n & 1) x[n / 2] = 0.0;
     return true;
+}
+
+// Rectangle rules of App. B in natural coordinates (Eq. 3.2).  Each entry is one table
+// row; its orbit is given by the table caption: a single point, the four sign changes
+// (Tables B1-B3), or the four rotations +-(x, y), +-(-y, x) (Tables B4, B5).
+namespace {
+enum RectOrbit { ONE, SIGNS, ROTATIONS };
+struct RectRow {
+    RectOrbit orbit;
+    double x, y, w;
+};
+void expand_rect(const RectRow* rows, int nrows, std::vector<RectNode>& out)
+{
+    out.clear();
+    for (int r = 0; r < nrows; ++r) {
+        const RectRow& R = rows[r];
+        if (R.orbit == ONE) {
+            out.push_back({ R.x, R.y, R.w });
+        } else if (R.orbit == SIGNS) {
+            for (double sx : { 1.0, -1.0 })
+                for (double sy : { 1.0, -1.0 }) out.push_back({ sx * R.x, sy * R.y, R.w });
+        } else {
+            out.push_back({ R.x, R.y, R.w });
+            out.push_back({ -R.x, -R.y, R.w });
+            out.push_back({ -R.y, R.x, R.w });
+            out.push_back({ R.y, -R.x, R.w });
+        }
+    }
+}
+}  // namespace
+
+bool rectangle_table_rule(int n, std::vector<RectNode>& out)
+{
+    switch (n) {
+    case 4: {  // Table B1, degree 3
+        const double s = std::sqrt(1.0 / 3.0);
+        const RectRow rows[] = { { SIGNS, s, s, 0.25 } };
+        expand_rect(rows, 1, out);
+        return true;
+    }
+    case 7: {  // Table B2, degree 5
+        const double t = std::sqrt(14.0 / 15.0), r = std::sqrt(3.0 / 5.0), s = std::sqrt(1.0 / 3.0);
+        const RectRow rows[] = { { ONE, 0.0, 0.0, 2.0 / 7.0 }, { ONE, 0.0, t, 5.0 / 63.0 }, { ONE, 0.0, -t, 5.0 / 63.0 },
+                                 { SIGNS, r, s, 5.0 / 36.0 } };
+        expand_rect(rows, 4, out);
+        return true;
+    }
+    case 12: {  // Table B3, degree 7
+        const double q = std::sqrt(583.0);
+        const double r = std::sqrt(6.0 / 7.0);
+        const double s = std::sqrt((114.0 - 3.0 * q) / 287.0), t = std::sqrt((114.0 + 3.0 * q) / 287.0);
+        const double b1 = 49.0 / 810.0, b2 = (178981.0 + 2769.0 * q) / 1888920.0, b3 = (178981.0 - 2769.0 * q) / 1888920.0;
+        const RectRow rows[] = { { ONE, r, 0.0, b1 }, { ONE, -r, 0.0, b1 }, { ONE, 0.0, r, b1 }, { ONE, 0.0, -r, b1 },
+                                 { SIGNS, s, s, b2 }, { SIGNS, t, t, b3 } };
+        expand_rect(rows, 6, out);
+        return true;
+    }
+    case 17: {  // Table B4, degree 9
+        const RectRow rows[] = {
+            { ONE, 0.0, 0.0, 0.131687242798353921 },
+            { ROTATIONS, 0.968849966361977720, 0.630680119731668854, 0.022219844542549678 },
+            { ROTATIONS, 0.750277099978900533, 0.927961645959569667, 0.028024900532399120 },
+            { ROTATIONS, 0.523735820214429336, 0.453339821135647190, 0.099570609815517519 },
+            { ROTATIONS, 0.076208328192617173, 0.852615729333662307, 0.067262834409945196 },
+        };
+        expand_rect(rows, 5, out);
+        return true;
+    }
+    case 33: {  // Table B5, degree 13
+        const RectRow rows[] = {
+            { ONE, 0.0, 0.0, 0.075095528857806335 },
+            { ROTATIONS, 0.778809711554419422, 0.983486682439872263, 0.007497959716124783 },
+            { ROTATIONS, 0.957297699786307365, 0.859556005641638928, 0.009543605329270918 },
+            { ROTATIONS, 0.138183459862465353, 0.958925170287534857, 0.015106230954437494 },
+            { ROTATIONS, 0.941327225872925236, 0.390736216129461000, 0.019373184633276336 },
+            { ROTATIONS, 0.475808625218275905, 0.850076673699748575, 0.029711166825148901 },
+            { ROTATIONS, 0.755805356572081436, 0.647821637187010732, 0.032440887592500675 },
+            { ROTATIONS, 0.696250078491749413, 0.070741508996444936, 0.053335395364297350 },
+            { ROTATIONS, 0.342716556040406789, 0.409304561694038843, 0.064217687370491966 },
+        };
+        expand_rect(rows, 9, out);
+        return true;
+    }
+    default:
+        return false;
+    }
 }
 
 bool rectangle_gauss_rule(int n, std::vector<RectNode>& out)

@@ -208,6 +208,8 @@ bool Server::launch(Slot& s, std::string& err)
     fa.near_list = s.d_near;
     fa.near_cap = s.near_cap;
     fa.ctr = s.d_ctr;
+    fa.dr_rules = env_.dr_rules;
+    fa.lv = env_.lv;
     if (e == hipSuccess) e = launch_far_eval(fa, cfg_.precision, s.stream);
     if (e == hipSuccess && n_split > 1) e = launch_reduce_split(s.d_partial, n_split, n, K, s.d_phi, s.d_E, s.stream);
     NearArgs na{};

@@ -22,6 +22,8 @@ struct ServerEnv {
     double near_dr;
     int max_depth;
     int64_t n_tri, n_rect;
+    int dr_rules;   // rule choice by distance ratio (queries are particle tracks: already coherent)
+    LevelRules lv;
 };
 
 class Server {

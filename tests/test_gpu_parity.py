@@ -272,3 +272,64 @@ def test_full_size_cylinder_sampled():
               f"far {st['far_ms']:.1f} ms near {st['near_ms']:.1f} ms")
         assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
         assert np.all(np.isfinite(phi)) and np.all(np.isfinite(E))
+
+
+# ------------------------------------------------ rule choice by distance ratio ------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dr_rules_parity(cyl, precision):
+    """Far pairs take 7/12/19/33 (triangles) and B2/B3/B4/7x7 (rectangles) by distance
+    ratio; the points are Morton-ordered inside the library and returned in input order."""
+    w, ref_fixed = cyl
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7, dr_rules=True), with_abs=True)
+    ctx = make_ctx(w)
+    ctx.set_dr_rules(True)
+    phi, E, rc = run_gpu(ctx, w.points, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert rc == 0 and st["near_pairs"] == ref["stats"]["near_pairs"]
+    fixed_terms = w.points.shape[0] * (w.tri.shape[0] * 33 + w.rect.shape[0] * 49)
+    assert 0 < st["node_interactions"] < fixed_terms
+    ep, ee = nerr(phi, E, ref)
+    print(f"dr rules {precision}: phi {ep.max():.2e} E {ee.max():.2e}; terms {st['node_interactions']:.3e} "
+          f"vs {fixed_terms:.3e} fixed")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+    ep, ee = nerr(phi, E, ref_fixed)  # the coarser rules stay at the fixed rules' accuracy
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("table", [4, 7, 12, 17, 33])
+def test_rectangle_table_rules(table):
+    w = W.cylinder_workload(40, 30, 1200, n_points=600, near_frac=0.3, seed=17)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, rect_gl_n=0, rect_table_n=table),
+                          with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.set_rules(33, -table)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    phi, E, _ = run_gpu(ctx, w.points, "fp64")
+    ctx.close()
+    ep, ee = nerr(phi, E, ref)
+    assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+def test_dr_rules_full_size_sampled():
+    torch = torch_mod()
+    w = W.cylinder_150k()
+    ctx = make_ctx(w)
+    ctx.set_dr_rules(True)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        phi, E, _ = ctx.eval(pts, precision=prec)
+        torch.cuda.synchronize()
+        res[prec] = (phi.cpu().numpy(), E.cpu().numpy().T.copy(), ctx.stats())
+    ctx.close()
+    rng = np.random.default_rng(43)
+    idx = rng.choice(w.points.shape[0], 128, replace=False)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points[idx], oracle.params(33, 7), with_abs=True)
+    for prec in ("fp64", "mixed"):
+        phi, E, st = res[prec]
+        ep, ee = nerr(phi[idx], E[idx], ref)
+        print(f"dr full-size {prec}: phi {ep.max():.2e} E {ee.max():.2e}; terms {st['node_interactions']:.3e}, "
+              f"far {st['far_ms']:.1f} ms")
+        assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]

@@ -30,8 +30,9 @@ def setup():
     return w, queries
 
 
-def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096):
+def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096, dr=False):
     ctx = bemc.Context(0)
+    ctx.set_dr_rules(dr)
     ctx.upload_geometry(w.tri, w.rect)
     ctx.upload_densities(w.sigma)
     ctx.server_start(mem_budget_bytes=2 << 30, max_batch_points=max_batch, n_streams=n_streams, precision=precision)
@@ -50,11 +51,11 @@ def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096):
     return phis, Es, infos
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
-def test_alone_equals_mix_and_oracle(setup, precision, tol):
+@pytest.mark.parametrize("precision,tol,dr", [("fp64", 1e-12, False), ("mixed", 1e-6, False), ("mixed", 1e-6, True)])
+def test_alone_equals_mix_and_oracle(setup, precision, tol, dr):
     w, queries = setup
-    pa, Ea, ia = run_server(w, queries, precision, alone=True)
-    pm, Em, im = run_server(w, queries, precision, alone=False)
+    pa, Ea, ia = run_server(w, queries, precision, alone=True, dr=dr)
+    pm, Em, im = run_server(w, queries, precision, alone=False, dr=dr)
     assert all(i["done"] == 1 and i["status"] == 0 for i in ia + im)
     # in the mix, several queries shared a batch
     assert len({i["batch_id"] for i in im}) < len(queries)
