@@ -159,6 +159,25 @@ int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rh
 int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision,
                             double* out, void* stream);
 
+/* Result of bemc_solve_densities. */
+typedef struct {
+    int iterations;       /* collocation products used */
+    int converged;        /* 1 if the relative residual reached tol */
+    double rel_residual;  /* |potential - A sigma| / |potential|, from a final product */
+    double seconds;
+} bemc_solve_info;
+
+/* Charge densities from electrode potentials (the BEM linear-algebra step, Sec. 5): find
+ * sigma[n_E] (device) with (A sigma)_i = potential[i] (device, volts at the centroid of
+ * element i), A the operator of bemc_collocation_matvec.  Restarted GMRES (restart
+ * 1..200) right-preconditioned by the diagonal of A (exact on-element potentials), started
+ * from zero, stopped when the residual falls below tol * |potential| or after max_iter
+ * products; precision applies to the far pairs of each product.  Allocates (restart + 4)
+ * n_E doubles of workspace.  Synchronous.  Errors: NO_GEOMETRY, INVALID_ARG,
+ * OUT_OF_MEMORY, DEVICE. */
+int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
+                         int restart, int precision, bemc_solve_info* info, void* stream);
+
 /* Pre-size the near-pair list (entries of 8 bytes).  The list also grows by itself when an
  * evaluation finds more near pairs than it holds (the evaluation is then repeated), so
  * this only avoids that repetition.  Errors: INVALID_ARG, OUT_OF_MEMORY. */

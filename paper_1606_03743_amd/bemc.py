@@ -34,7 +34,7 @@ EXPORTED = ["bemc_last_error", "bemc_create", "bemc_destroy", "bemc_set_rules", 
             "bemc_upload_densities", "bemc_eval", "bemc_collocation_matvec", "bemc_query_stats",
             "bemc_server_start", "bemc_server_submit", "bemc_server_poll", "bemc_server_wait",
             "bemc_server_stop", "bemc_coulomb_constant", "bemc_rule_size", "bemc_set_near_capacity",
-            "bemc_set_dr_rules"]
+            "bemc_set_dr_rules", "bemc_solve_densities"]
 
 
 class BemcError(RuntimeError):
@@ -48,6 +48,11 @@ class Stats(ctypes.Structure):
                 ("near_pairs", ctypes.c_int64), ("leaves", ctypes.c_int64), ("cap_hits", ctypes.c_int64),
                 ("on_surface", ctypes.c_int64), ("max_depth", ctypes.c_int64),
                 ("near_capacity", ctypes.c_int64), ("far_ms", ctypes.c_double), ("near_ms", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -90,6 +95,7 @@ def load_library():
     lib.bemc_query_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.bemc_set_near_capacity.argtypes = [vp, i64]
     lib.bemc_set_dr_rules.argtypes = [vp, ci, vp, vp]
+    lib.bemc_solve_densities.argtypes = [vp, vp, vp, ctypes.c_double, ci, ci, ci, ctypes.POINTER(SolveInfo), vp]
     lib.bemc_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig)]
     lib.bemc_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.bemc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(QueryInfo)]
@@ -223,6 +229,18 @@ class Context:
 
     def set_near_capacity(self, pairs):
         _check(self.lib.bemc_set_near_capacity(self.h, int(pairs)))
+
+    def solve(self, potential, tol=1e-10, max_iter=500, restart=50, precision="fp64", sigma=None):
+        """Densities sigma [n_E] (CUDA float64) whose collocation potentials equal `potential` [n_E]."""
+        torch = _torch()
+        _dev_f64(potential, (self.n_elements,))
+        if sigma is None:
+            sigma = torch.empty_like(potential)
+        info = SolveInfo()
+        _check(self.lib.bemc_solve_densities(self.h, _dev_f64(potential), _dev_f64(sigma, (self.n_elements,)),
+                                             float(tol), int(max_iter), int(restart), _PREC[precision],
+                                             ctypes.byref(info), _stream_ptr()))
+        return sigma, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
     def stats(self):
         st = Stats()

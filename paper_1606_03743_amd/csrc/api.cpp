@@ -619,6 +619,25 @@ int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int p
     return h->run(true, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
 }
 
+int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
+                         int restart, int precision, bemc_solve_info* info, void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry) return fail(BEMC_E_NO_GEOMETRY, "geometry must be uploaded");
+    if (h->server) return fail(BEMC_E_INVALID_ARG, "not while serving");
+    if (!potential || !sigma) return fail(BEMC_E_INVALID_ARG, "null pointer");
+    if (!(tol > 0.0) || max_iter < 1 || restart < 1 || restart > 200)
+        return fail(BEMC_E_INVALID_ARG, "tol > 0, max_iter >= 1, restart in 1..200 required");
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (h->ne == 0) return ok();
+    HIP_TRY(hipSetDevice(h->device));
+    std::string err;
+    const int rc = bemc::solve_gmres(h, h->elements(), potential, sigma, tol, max_iter, restart, precision, info,
+                                     reinterpret_cast<hipStream_t>(stream), err);
+    if (rc) return fail(rc, "%s", err.c_str());
+    return ok();
+}
+
 int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const double* rect_dr)
 {
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");

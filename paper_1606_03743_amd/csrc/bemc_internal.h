@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "bemc.h"
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -131,11 +133,19 @@ hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows
                                 hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
 
+hipError_t launch_self_diag(const Elements& el, double K, double* diag, hipStream_t s);
+hipError_t launch_multi_dot(const double* V, int k, int64_t n, const double* w, double* partial, int blocks, hipStream_t s);
+hipError_t launch_combine(double* y, double a, const double* V, const double* c, int k, int64_t n, const double* d,
+                          hipStream_t s);
+hipError_t launch_divide(double* y, const double* x, const double* d, int64_t n, hipStream_t s);
+
 // workgroups per resident slot that element splitting aims for (dispatcher load balance)
 constexpr int kSplitTargetBlocks = 16 * 1024;
 constexpr int kMaxSplit = 64;
 
 double coulomb_constant();
+int solve_gmres(bemc_handle h, const Elements& el, const double* b, double* x, double tol, int max_iter, int m,
+                int precision, bemc_solve_info* info, hipStream_t s, std::string& err);
 
 // Morton ordering of field points (order.hip).  Buffers sized for n points.
 struct OrderWork {

@@ -1004,9 +1004,118 @@ hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ solver support -------
+// Potential of an element with unit density at its own centroid, K times the exact polar
+// integral (per edge at distance h with end offsets t1, t2: h [asinh(t2/h) - asinh(t1/h)]):
+// the diagonal of the collocation matrix.
+__global__ void self_diag_kernel(Elements el, double K, double* __restrict__ diag)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ne = el.ne;
+    if (e >= ne) return;
+    double G[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) G[c] = el.geom[(int64_t)c * ne + e];
+    double V[4][3];
+    int nv;
+    if (e < el.n_tri) {
+        nv = 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { V[0][c] = 0.0; V[1][c] = G[3 + c] - G[c]; V[2][c] = G[6 + c] - G[c]; V[3][c] = 0.0; }
+    } else {
+        nv = 4;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { V[0][c] = 0.0; V[1][c] = G[3 + c]; V[2][c] = G[3 + c] + G[6 + c]; V[3][c] = G[6 + c]; }
+    }
+    double P[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P[c] = el.cen[c * ne + e] - G[c];
+    double sum = 0.0;
+    for (int k = 0; k < nv; ++k) {
+        const double* Va = V[k];
+        const double* Vb = V[(k + 1) % nv];
+        double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
+        const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+        tv[0] /= len; tv[1] /= len; tv[2] /= len;
+        const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
+        const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
+        const double fx = pa[0] - t1 * tv[0], fy = pa[1] - t1 * tv[1], fz = pa[2] - t1 * tv[2];
+        const double h = sqrt(fx * fx + fy * fy + fz * fz);
+        if (h > 0.0) sum += h * (asinh((t1 + len) / h) - asinh(t1 / h));
+    }
+    diag[e] = K * sum;
+}
+
+// partial[j][b] = sum over block b's share of V[j][i] * w[i], j < k (fixed order)
+__global__ void multi_dot_kernel(const double* __restrict__ V, int k, int64_t n, const double* __restrict__ w,
+                                 double* __restrict__ partial)
+{
+    __shared__ double red[256];
+    for (int j = 0; j < k; ++j) {
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+            acc = fma(V[(int64_t)j * n + i], w[i], acc);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+// y[i] = a * y[i] + sum_j c[j] V[j][i] / d[i]^p  (p = 0 or 1; d may be null when p = 0)
+__global__ void combine_kernel(double* __restrict__ y, double a, const double* __restrict__ V, const double* __restrict__ c,
+                               int k, int64_t n, const double* __restrict__ d)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s = fma(c[j], V[(int64_t)j * n + i], s);
+    if (d) s /= d[i];
+    y[i] = fma(a, y[i], s);
+}
+
+// y[i] = x[i] / d[i]
+__global__ void divide_kernel(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ d, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = x[i] / d[i];
+}
+
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s)
 {
     zero_counters_kernel<<<1, 64, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_self_diag(const Elements& el, double K, double* diag, hipStream_t s)
+{
+    if (el.ne <= 0) return hipSuccess;
+    self_diag_kernel<<<(unsigned)((el.ne + 255) / 256), 256, 0, s>>>(el, K, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_dot(const double* V, int k, int64_t n, const double* w, double* partial, int blocks, hipStream_t s)
+{
+    multi_dot_kernel<<<blocks, 256, 0, s>>>(V, k, n, w, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(double* y, double a, const double* V, const double* c, int k, int64_t n, const double* d,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    combine_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, a, V, c, k, n, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_divide(double* y, const double* x, const double* d, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    divide_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, x, d, n);
     return hipGetLastError();
 }
 

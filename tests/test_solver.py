@@ -1,0 +1,120 @@
+"""Charge densities from electrode potentials (BEM linear-algebra step, Sec. 5).
+
+CPU: the oracle's collocation matrix, assembled column by column and solved with numpy,
+gives the capacitance of a sphere, C = 4 pi eps0 R, to the discretisation error of the
+icosphere, and the error falls as the mesh is refined.
+GPU: restarted GMRES on the matrix-free product matches that dense solution."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_03743_amd import workloads as W
+
+
+def dense_matrix(tri, rect, prm):
+    ne = (0 if tri is None else tri.shape[0]) + (0 if rect is None else rect.shape[0])
+    A = np.empty((ne, ne))
+    for c0 in range(0, ne, 64):
+        c1 = min(ne, c0 + 64)
+        sig = np.zeros((c1 - c0, ne))
+        sig[np.arange(c1 - c0), np.arange(c0, c1)] = 1.0
+        A[:, c0:c1] = oracle.collocation(tri, rect, sig, prm=prm)["out"].T
+    return A
+
+
+def areas(tri, rect):
+    a = []
+    if tri is not None and len(tri):
+        a.append(0.5 * np.linalg.norm(np.cross(tri[:, 3:6] - tri[:, 0:3], tri[:, 6:9] - tri[:, 0:3]), axis=1))
+    if rect is not None and len(rect):
+        a.append(np.linalg.norm(rect[:, 3:6], axis=1) * np.linalg.norm(rect[:, 6:9], axis=1))
+    return np.concatenate(a)
+
+
+@pytest.fixture(scope="module")
+def sphere_systems(orc):
+    out = {}
+    for sub in (1, 2):
+        tri = W.icosphere(sub, 1.0)
+        A = dense_matrix(tri, None, orc.params(tri_rule=7))
+        sig = np.linalg.solve(A, np.ones(tri.shape[0]))
+        out[sub] = (tri, A, sig)
+    return out
+
+
+def test_sphere_capacitance(orc, sphere_systems):
+    eps0 = 1.0 / (4 * math.pi * orc.coulomb_constant())
+    errs = []
+    for sub, (tri, A, sig) in sorted(sphere_systems.items()):
+        Q = np.sum(sig * areas(tri, None))
+        errs.append(abs(Q / (4 * math.pi * eps0 * 1.0) - 1.0))
+        # uniform density by symmetry (icosahedral mesh: equal up to the facet shapes)
+        assert sig.std() / sig.mean() < 0.1
+    # flat facets inside the sphere: the error falls with the square of the mesh size
+    assert errs[0] < 0.06 and errs[1] < 0.015 and errs[0] / errs[1] > 3.0
+
+
+def test_matrix_is_the_potential_operator(orc, sphere_systems):
+    """Column j of the assembled matrix is the potential of element j with unit density at
+    all centroids (direct evaluation at the centroids gives the same numbers)."""
+    tri, A, _ = sphere_systems[1]
+    cen = (tri[:, 0:3] + tri[:, 3:6] + tri[:, 6:9]) / 3
+    j = 5
+    sig = np.zeros(tri.shape[0])
+    sig[j] = 1.0
+    ev = orc.evaluate(tri, None, sig, cen, orc.params(tri_rule=7))
+    assert np.allclose(ev["phi"], A[:, j], rtol=1e-13, atol=0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("sub", [1, 2])
+def test_gpu_gmres_matches_dense_solve(sphere_systems, sub):
+    import torch
+
+    from paper_1606_03743_amd import bemc
+
+    tri, A, sig_ref = sphere_systems[sub]
+    ctx = bemc.Context(0)
+    ctx.set_rules(7, 7)
+    ctx.upload_geometry(tri, None)
+    V = torch.ones(tri.shape[0], dtype=torch.float64, device="cuda:0")
+    sig, info = ctx.solve(V, tol=1e-13, max_iter=300, restart=40)
+    torch.cuda.synchronize()
+    ctx.close()
+    s = sig.cpu().numpy()
+    print(f"sphere {tri.shape[0]}: {info}")
+    assert info["converged"] == 1 and info["rel_residual"] < 1e-12
+    assert np.linalg.norm(s - sig_ref) / np.linalg.norm(sig_ref) < 1e-10
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gpu_gmres_mixed_geometry(orc, precision):
+    """Nested triangles + rectangles (two coaxial cylinders at 1 V and 0 V)."""
+    import torch
+
+    from paper_1606_03743_amd import bemc
+
+    t1, q1 = W.cylinder(1.0, -1.0, 1.0, 12, 3, 36)
+    t2, q2 = W.cylinder(2.0, -1.5, 1.5, 16, 3, 64)
+    tri, rect = np.concatenate([t1, t2]), np.concatenate([q1, q2])
+    n_inner_t, n_inner_r = t1.shape[0], q1.shape[0]
+    ne = tri.shape[0] + rect.shape[0]
+    pot = np.zeros(ne)
+    pot[:n_inner_t] = 1.0
+    pot[tri.shape[0]:tri.shape[0] + n_inner_r] = 1.0
+    A = dense_matrix(tri, rect, orc.params(33, 7))
+    ref = np.linalg.solve(A, pot)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    sig, info = ctx.solve(torch.tensor(pot, device="cuda:0"), tol=1e-12 if precision == "fp64" else 1e-7,
+                          max_iter=400, restart=60, precision=precision)
+    torch.cuda.synchronize()
+    ctx.close()
+    s = sig.cpu().numpy()
+    err = np.linalg.norm(s - ref) / np.linalg.norm(ref)
+    print(f"nested {precision}: {info}, error {err:.2e}")
+    assert info["converged"] == 1
+    assert err < (1e-9 if precision == "fp64" else 1e-5)
