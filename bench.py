@@ -147,6 +147,13 @@ def main():
     phi64, E64 = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     dtmx, farmx, stmx = timed("mixed", args.steps, args.warmup)
     phimx, Emx = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    # rule choice by distance ratio (fewest Gaussian points at the accuracy floor per pair)
+    ctx.set_dr_rules(True)
+    dtdr, fardr, stdr = timed("fp64", args.steps, 1)
+    phidr, Edr = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    dtdrm, fardrm, stdrm = timed("mixed", args.steps, 1)
+    phidrm, Edrm = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    ctx.set_dr_rules(False)
 
     pairs = st64["pairs"]
     node_int = st64["node_interactions"]
@@ -188,6 +195,14 @@ def main():
                     "roofline": {"bound": "alu", "achieved": mixed_ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                  "frac": mixed_ach / PEAK_FP32_TFLOPS}}
 
+    out["dr_rules"] = {"value": pairs * args.steps / dtdr, "unit": "pairs/s", "precision": "fp64",
+                       "ms_per_step": 1e3 * dtdr / args.steps, "far_kernel_ms": float(np.mean(fardr)),
+                       "node_interactions": stdr["node_interactions"],
+                       "node_interactions_fixed_rules": node_int,
+                       "mixed_value": pairs * args.steps / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
+                       "rules": "triangles 7/12/19/33 points for DR >= 100/25/10/3, rectangles Tables B2/B3/B4 "
+                                "and 7x7 Gauss for DR >= 150/40/15/3"}
+
     if not args.quick:
         import oracle
 
@@ -212,6 +227,10 @@ def main():
             acc[name] = {"max_norm_err_phi": float(ep.max()), "max_norm_err_E": float(ee.max()),
                          "median_norm_err_phi": float(np.median(ep)), "median_norm_err_E": float(np.median(ee)),
                          "max_rel_err_phi": float(rp.max()), "median_rel_err_phi": float(np.median(rp))}
+        for name, (p_, E_) in {"dr_fp64": (phidr, Edr), "dr_mixed": (phidrm, Edrm)}.items():
+            ep, ee, rp = nerr(p_[idx], E_[idx], ref)
+            acc[name] = {"max_norm_err_phi": float(ep.max()), "max_norm_err_E": float(ee.max()),
+                         "median_rel_err_phi": float(np.median(rp))}
         out["accuracy_vs_oracle"] = acc
         out["mixed"]["within_1e-6"] = acc["mixed"]["max_norm_err_phi"] <= 1e-6 and acc["mixed"]["max_norm_err_E"] <= 1e-6
 
@@ -245,10 +264,40 @@ def main():
         out["collocation"] = colloc
         cctx.close()
 
+        out["solver"] = solver_bench(torch, bemc, W)
+
         if args.serving_queries > 0:
             out["serving"] = serving(args.serving_queries, torch, bemc, W)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def solver_bench(torch, bemc, W):
+    """Densities of a coaxial capacitor (inner cylinder 1 V, outer 0 V; 50,000 elements) by
+    GMRES on the matrix-free collocation product."""
+    log("solver: nested cylinders, 50,000 elements")
+    w = W.nested_cylinders_workload(inner=(100, 100, 5000), outer=(150, 100, 7500), n_rhs=1)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    n_in_t, n_in_r = 10_000, 10_000
+    pot = np.zeros(w.n_elements)
+    pot[:n_in_t] = 1.0
+    pot[w.tri.shape[0]:w.tri.shape[0] + n_in_r] = 1.0
+    V = torch.tensor(pot, device="cuda:0")
+    res = {}
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        sig, info = ctx.solve(V, tol=tol, max_iter=600, restart=60, precision=prec)
+        torch.cuda.synchronize()
+        s = sig.cpu().numpy()
+        tri, rect = w.tri, w.rect
+        a = np.concatenate([0.5 * np.linalg.norm(np.cross(tri[:, 3:6] - tri[:, 0:3], tri[:, 6:9] - tri[:, 0:3]), axis=1),
+                            np.linalg.norm(rect[:, 3:6], axis=1) * np.linalg.norm(rect[:, 6:9], axis=1)])
+        q = s * a
+        inner = np.concatenate([np.arange(n_in_t), w.tri.shape[0] + np.arange(n_in_r)])
+        res[prec] = dict(info, tol=tol, inner_charge_C=float(q[inner].sum()), total_charge_C=float(q.sum()))
+    ctx.close()
+    res["workload"] = "nested cylinders R=1 (z in [-5,5], 1 V) and R=2 (z in [-6,6], 0 V), 25k triangles + 25k rectangles"
+    return res
 
 
 def serving(n_queries, torch, bemc, W):
