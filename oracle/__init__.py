@@ -64,6 +64,8 @@ def _load():
         lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_eval.argtypes = [dp, i64, dp, i64, dp, ctypes.POINTER(_Params), dp, i64, dp, dp,
                                  dp, dp, ctypes.POINTER(_Stats), ctypes.c_int]
+        lib.orc_eval_gradient.argtypes = [dp, i64, dp, i64, dp, ctypes.POINTER(_Params), dp, i64, dp, dp,
+                                          ctypes.POINTER(_Stats), ctypes.c_int]
         lib.orc_collocation.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.POINTER(_Params),
                                         ctypes.POINTER(ctypes.c_int64), i64, dp, dp,
                                         ctypes.POINTER(_Stats), ctypes.c_int]
@@ -155,6 +157,37 @@ def evaluate(tri, rect, sigma, pts, prm=None, nthreads=0, with_abs=False):
     return out
 
 
+def gradient(tri, rect, sigma, pts, prm=None, nthreads=0):
+    """G[n, 6] = dE_i/dx_j as (xx, yy, zz, xy, xz, yz), abs[n] scale, stats."""
+    lib = _load()
+    prm = prm or params()
+    tri = _f64(tri if tri is not None else np.zeros((0, 9)), 9)
+    rect = _f64(rect if rect is not None else np.zeros((0, 9)), 9)
+    sigma = _f64(sigma).ravel()
+    pts = _f64(pts, 3)
+    n = pts.shape[0]
+    if sigma.size != tri.shape[0] + rect.shape[0]:
+        raise ValueError("sigma length must equal the element count")
+    G = np.zeros((n, 6)); aG = np.zeros(n)
+    st = _Stats()
+    rc = lib.orc_eval_gradient(_ptr(tri), tri.shape[0], _ptr(rect), rect.shape[0], _ptr(sigma),
+                               ctypes.byref(prm), _ptr(pts), n, _ptr(G), _ptr(aG), ctypes.byref(st), nthreads)
+    if rc < 0:
+        raise ValueError(f"orc_eval_gradient failed ({rc})")
+    return {"G": G, "abs_G": aG, "stats": _stats_dict(st), "threads": rc}
+
+
+def gradient_matrix(g6):
+    """[..., 6] (xx, yy, zz, xy, xz, yz) -> symmetric [..., 3, 3]."""
+    g6 = np.asarray(g6)
+    m = np.empty(g6.shape[:-1] + (3, 3))
+    m[..., 0, 0], m[..., 1, 1], m[..., 2, 2] = g6[..., 0], g6[..., 1], g6[..., 2]
+    m[..., 0, 1] = m[..., 1, 0] = g6[..., 3]
+    m[..., 0, 2] = m[..., 2, 0] = g6[..., 4]
+    m[..., 1, 2] = m[..., 2, 1] = g6[..., 5]
+    return m
+
+
 def collocation(tri, rect, sigma, rows=None, prm=None, nthreads=0):
     """out[n_rhs, n_rows]: potential at element centroids (rows) from densities sigma[n_rhs, n_E]."""
     lib = _load()
@@ -175,11 +208,13 @@ def collocation(tri, rect, sigma, rows=None, prm=None, nthreads=0):
     return {"out": out, "abs": aout, "stats": _stats_dict(st), "threads": rc}
 
 
-def element(kind, geom, P, prm=None, mode=1):
-    """(phi, Ex, Ey, Ez) of one element with unit density and no Coulomb constant."""
+def element(kind, geom, P, prm=None, mode=1, grad=False):
+    """(phi, Ex, Ey, Ez[, gradient xx yy zz xy xz yz]) of one element with unit density and
+    no Coulomb constant."""
     lib = _load()
     prm = prm or params()
-    g = _f64(geom).ravel(); P = _f64(P).ravel(); out = np.zeros(4)
+    g = _f64(geom).ravel(); P = _f64(P).ravel(); out = np.zeros(10 if grad else 4)
+    mode = mode | (2 if grad else 0)
     st = _Stats()
     rc = lib.orc_element(kind, _ptr(g), _ptr(P), ctypes.byref(prm), mode, _ptr(out), ctypes.byref(st))
     if rc < 0:

@@ -354,19 +354,34 @@ typedef struct {
     rect_rule rect;
     tri_rule tri_lv[3];   /* 7, 12, 19 points (distance-ratio-dependent choice) */
     rect_rule rect_lv[3]; /* Tables B2, B3, B4 */
+    int grad;             /* also accumulate the field gradient (acc[4..9]) */
 } rules;
 
 static void apply_rules(const double* P, int kind, const double* g, double area, const tri_rule* TR,
-                        const rect_rule* RR, double* acc);
+                        const rect_rule* RR, int grad, double* acc);
 
 static void apply_rule(const double* P, int kind, const double* g, double area, const rules* R, double* acc)
 {
-    apply_rules(P, kind, g, area, &R->tri, &R->rect, acc);
+    apply_rules(P, kind, g, area, &R->tri, &R->rect, R->grad, acc);
+}
+
+/* Field gradient of one point charge w at Q (unit density, no constant), d = P - Q:
+ * dE_i/dx_j = w (delta_ij r^2 - 3 d_i d_j) / r^5; accumulated as xx, yy, zz, xy, xz, yz. */
+static void add_gradient(const double* d, double r, double w, double* G)
+{
+    double r2 = r * r, f5 = w / (r2 * r2 * r);
+    G[0] += f5 * (r2 - 3.0 * d[0] * d[0]);
+    G[1] += f5 * (r2 - 3.0 * d[1] * d[1]);
+    G[2] += f5 * (r2 - 3.0 * d[2] * d[2]);
+    G[3] -= 3.0 * f5 * d[0] * d[1];
+    G[4] -= 3.0 * f5 * d[0] * d[2];
+    G[5] -= 3.0 * f5 * d[1] * d[2];
 }
 
 static void apply_rules(const double* P, int kind, const double* g, double area, const tri_rule* TR,
-                        const rect_rule* RR, double* acc)
+                        const rect_rule* RR, int grad, double* acc)
 {
+    double G[6] = { 0, 0, 0, 0, 0, 0 };
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     if (kind == 0) {
         const double *A = g, *B = g + 3, *C = g + 6;
@@ -380,6 +395,7 @@ static void apply_rules(const double* P, int kind, const double* g, double area,
             double f = TR->w[i] * inv * inv * inv;
             phi += TR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
+            if (grad) add_gradient(d, r, TR->w[i], G);
         }
     } else {
         const double *P0 = g, *e1 = g + 3, *e2 = g + 6;
@@ -396,9 +412,12 @@ static void apply_rules(const double* P, int kind, const double* g, double area,
             double f = RR->w[i] * inv * inv * inv;
             phi += RR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
+            if (grad) add_gradient(d, r, RR->w[i], G);
         }
     }
     acc[0] += area * phi; acc[1] += area * ex; acc[2] += area * ey; acc[3] += area * ez;
+    if (grad)
+        for (int k = 0; k < 6; ++k) acc[4 + k] += area * G[k];
 }
 
 /* ------------------------------------------------------------------ */
@@ -568,7 +587,7 @@ static void to_local(const double* P, const elem* e, double* Pl, elem* le)
 static void element_contribution(const double* P, const elem* e, const rules* R, const orc_params* prm,
                                  double* out, lstats* st)
 {
-    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (int k = 0; k < 10; ++k) out[k] = 0.0;
     double d[3];
     sub3(P, e->cen, d);
     double D2 = dot3(d, d);
@@ -583,7 +602,7 @@ static void element_contribution(const double* P, const elem* e, const rules* R,
             for (int lv = 0; lv < 3; ++lv) {
                 const double t = lim[lv] * e->L;
                 if (D2 >= t * t) {
-                    apply_rules(Pl, le.kind, le.g, le.area, &R->tri_lv[lv], &R->rect_lv[lv], out);
+                    apply_rules(Pl, le.kind, le.g, le.area, &R->tri_lv[lv], &R->rect_lv[lv], R->grad, out);
                     return;
                 }
             }
@@ -595,6 +614,8 @@ static void element_contribution(const double* P, const elem* e, const rules* R,
     if (on_element(Pl, &le)) {
         st->on_surface++;
         self_rule(Pl, &le, out);
+        if (R->grad) /* the normal field jumps across the element: no gradient there */
+            for (int k = 4; k < 10; ++k) out[k] = NAN;
         return;
     }
     if (prm->max_depth <= 0) {
@@ -611,6 +632,7 @@ static int build_rules(const orc_params* prm, rules* R)
     if (build_tri_rule(prm->tri_rule, &R->tri) < 0) return -1;
     if (build_rect_rule(prm->rect_gl_n, prm->rect_table_n, &R->rect) < 0) return -1;
     if (!(prm->near_dr > 0.0)) return -1;
+    R->grad = 0;
     const int tl[3] = { 7, 12, 19 }, rl[3] = { 7, 12, 17 };
     for (int lv = 0; lv < 3; ++lv) {
         build_tri_rule(tl[lv], &R->tri_lv[lv]);
@@ -675,7 +697,7 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
             nsum s0 = { 0, 0 }, s1 = { 0, 0 }, s2 = { 0, 0 }, s3 = { 0, 0 };
             double aphi = 0.0, aE = 0.0;
             for (int64_t j = 0; j < ne; ++j) {
-                double c[4];
+                double c[10];
                 element_contribution(P, &el[j], R, prm, c, &ls);
                 double sg = sigma[j];
                 nadd(&s0, sg * c[0]); nadd(&s1, sg * c[1]); nadd(&s2, sg * c[2]); nadd(&s3, sg * c[3]);
@@ -694,6 +716,68 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
         memcpy(st, &tot, sizeof(tot));
     }
     (void)used_threads;
+    free(el);
+    free(R);
+    return used_threads;
+}
+
+/* Field gradient dE_i/dx_j at each point: the derivative of the point-charge field of
+ * Eq. (4.1) (conclusions: higher derivatives follow from the same point charges), with the
+ * same near-field subdivision (Sec. 4) and rule choice as the field itself.  G is [n][6]
+ * (xx, yy, zz, xy, xz, yz); abs_G[p] = K sum_j |sigma_j| |G_j|_F (Frobenius norm of the
+ * element's tensor), the scale for relative errors.  A point on an element gets NaN. */
+int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
+                      const double* sigma, const orc_params* prm, const double* pts, int64_t n,
+                      double* G, double* abs_G, orc_stats* st, int nthreads)
+{
+    if (n_tri < 0 || n_rect < 0 || n < 0 || !prm || !G) return -1;
+    rules* R = (rules*)malloc(sizeof(rules));
+    if (!R) return -4;
+    if (build_rules(prm, R)) { free(R); return -1; }
+    R->grad = 1;
+    elem* el = NULL;
+    int rc = build_elems(tri, n_tri, rect, n_rect, &el);
+    if (rc) { free(R); return rc; }
+    const int64_t ne = n_tri + n_rect;
+    const double K = orc_coulomb_constant();
+    orc_stats tot;
+    memset(&tot, 0, sizeof(tot));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int used_threads = 1;
+#pragma omp parallel
+    {
+        lstats ls;
+        memset(&ls, 0, sizeof(ls));
+#ifdef _OPENMP
+#pragma omp single
+        used_threads = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t p = 0; p < n; ++p) {
+            const double* P = pts + 3 * p;
+            nsum s[6];
+            for (int k = 0; k < 6; ++k) { s[k].s = 0.0; s[k].c = 0.0; }
+            double aG = 0.0;
+            for (int64_t j = 0; j < ne; ++j) {
+                double c[10];
+                element_contribution(P, &el[j], R, prm, c, &ls);
+                const double sg = sigma[j];
+                double f2 = 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    nadd(&s[k], sg * c[4 + k]);
+                    f2 += (k < 3 ? 1.0 : 2.0) * c[4 + k] * c[4 + k];
+                }
+                aG += fabs(sg) * sqrt(f2);
+            }
+            for (int k = 0; k < 6; ++k) G[6 * p + k] = K * nval(&s[k]);
+            if (abs_G) abs_G[p] = K * aG;
+        }
+#pragma omp critical
+        merge_stats(&tot, &ls);
+    }
+    if (st) memcpy(st, &tot, sizeof(tot));
     free(el);
     free(R);
     return used_threads;
@@ -736,7 +820,7 @@ int orc_collocation(const double* tri, int64_t n_tri, const double* rect, int64_
             for (int r = 0; r < n_rhs; ++r) { acc[r].s = 0.0; acc[r].c = 0.0; }
             double a0 = 0.0;
             for (int64_t j = 0; j < ne; ++j) {
-                double c[4];
+                double c[10];
                 element_contribution(P, &el[j], R, prm, c, &ls);
                 for (int r = 0; r < n_rhs; ++r) nadd(&acc[r], sigma[(int64_t)r * ne + j] * c[0]);
                 a0 += fabs(sigma[j] * c[0]);
@@ -759,20 +843,23 @@ int orc_element(int kind, const double* geom, const double* P, const orc_params*
     rules* R = (rules*)malloc(sizeof(rules));
     if (!R) return -4;
     if (build_rules(prm, R)) { free(R); return -1; }
+    R->grad = (mode & 2) ? 1 : 0;
     elem e;
     int rc = make_elem(kind, geom, &e);
     if (rc) { free(R); return rc; }
     lstats ls;
     memset(&ls, 0, sizeof(ls));
-    if (mode == 0) {
+    double tmp[10];
+    if ((mode & 1) == 0) {
         double Pl[3];
         elem le;
         to_local(P, &e, Pl, &le);
-        out[0] = out[1] = out[2] = out[3] = 0.0;
-        apply_rule(Pl, kind, le.g, le.area, R, out);
+        for (int k = 0; k < 10; ++k) tmp[k] = 0.0;
+        apply_rule(Pl, kind, le.g, le.area, R, tmp);
     } else {
-        element_contribution(P, &e, R, prm, out, &ls);
+        element_contribution(P, &e, R, prm, tmp, &ls);
     }
+    for (int k = 0; k < (R->grad ? 10 : 4); ++k) out[k] = tmp[k];
     if (st) {
         memset(st, 0, sizeof(*st));
         merge_stats(st, &ls);

@@ -73,6 +73,17 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
              const double* pts, int64_t n, double* phi, double* E,
              double* abs_phi, double* abs_E, orc_stats* st, int nthreads);
 
+/* Field gradient dE_i/dx_j = -d^2 phi/dx_i dx_j at n points: each cubature point charge
+ * of Eq. (4.1) contributes K q (delta_ij r^2 - 3 d_i d_j) / r^5 with d = P - Q (the
+ * conclusions note that higher derivatives come from the same charges); the near-field
+ * subdivision and rule choice are those of the field.  G[n][6] = xx, yy, zz, xy, xz, yz.
+ * abs_G[n] (optional) = K sum_j |sigma_j| |G_j|_F.  A point lying on an element has no
+ * gradient (the normal field jumps there): its six values are NaN.
+ * Returns threads used or < 0. */
+int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
+                      const double* sigma, const orc_params* prm, const double* pts, int64_t n,
+                      double* G, double* abs_G, orc_stats* st, int nthreads);
+
 /* Matrix-free collocation product: out[r][k] = potential at the centroid of element
  * rows[k] from all elements with density sigma[r][:], r < n_rhs.  The element's own
  * contribution is its on-element (self) integral.  abs_out[k] (optional) = sum over
@@ -84,8 +95,10 @@ int orc_collocation(const double* tri, int64_t n_tri, const double* rect, int64_
 
 /* Single element, single point, unit density, no Coulomb constant:
  * mode 0 = the rule at the element itself (no near/far switch),
- * mode 1 = full dispatch (far rule / subdivision / on-element rule).
- * kind 0 triangle, 1 rectangle; geom[9] as above.  out[4] = phi, Ex, Ey, Ez. */
+ * mode 1 = full dispatch (far rule / subdivision / on-element rule);
+ * mode | 2 also returns the field gradient: out[4..9] = xx, yy, zz, xy, xz, yz.
+ * kind 0 triangle, 1 rectangle; geom[9] as above.  out[4] (or out[10]) = phi, Ex, Ey, Ez
+ * (, gradient). */
 int orc_element(int kind, const double* geom, const double* P, const orc_params* prm,
                 int mode, double* out, orc_stats* st);
 

@@ -159,6 +159,69 @@ def rect_closed_form(g, P):
     return np.array([phi, Evec[0], Evec[1], Evec[2]])
 
 
+def rect_gradient_closed_form(g, P):
+    """Field gradient G_ij = dE_i/dP_j = -d^2 phi/dP_i dP_j of the uniformly charged
+    rectangle (orthogonal sides), P off the rectangle's plane.  In the rectangle's frame,
+    with X = x - x0, Y = y - y0, R = sqrt(X^2 + Y^2 + z^2) and corner sums
+    C[f] = f(X2, Y2) - f(X1, Y2) - f(X2, Y1) + f(X1, Y1), the Hessian of phi is
+        H_xx = -C[X Y / ((X^2 + z^2) R)],  H_yy = -C[X Y / ((Y^2 + z^2) R)],
+        H_xy = C[1 / R],  H_xz = C[z Y / ((X^2 + z^2) R)],  H_yz = C[z X / ((Y^2 + z^2) R)],
+        H_zz = -(H_xx + H_yy)   (Laplace),
+    using int dY / R^3 = Y / ((X^2 + z^2) R).  Returns the 3x3 matrix in global axes."""
+    g = np.asarray(g, float).ravel()
+    P0, e1, e2 = g[0:3], g[3:6], g[6:9]
+    a, b = np.linalg.norm(e1), np.linalg.norm(e2)
+    ux, uy = e1 / a, e2 / b
+    uz = np.cross(ux, uy)
+    d = np.asarray(P, float) - P0
+    x0, y0, z = np.dot(d, ux), np.dot(d, uy), np.dot(d, uz)
+    if z == 0.0:
+        raise ValueError("point in the rectangle's plane")
+    X1, X2, Y1, Y2 = -x0, a - x0, -y0, b - y0
+
+    def C(fn):
+        return fn(X2, Y2) - fn(X1, Y2) - fn(X2, Y1) + fn(X1, Y1)
+
+    def R(X, Y):
+        return math.sqrt(X * X + Y * Y + z * z)
+
+    Hxx = -C(lambda X, Y: X * Y / ((X * X + z * z) * R(X, Y)))
+    Hyy = -C(lambda X, Y: X * Y / ((Y * Y + z * z) * R(X, Y)))
+    Hxy = C(lambda X, Y: 1.0 / R(X, Y))
+    Hxz = C(lambda X, Y: z * Y / ((X * X + z * z) * R(X, Y)))
+    Hyz = C(lambda X, Y: z * X / ((Y * Y + z * z) * R(X, Y)))
+    H = np.array([[Hxx, Hxy, Hxz], [Hxy, Hyy, Hyz], [Hxz, Hyz, -(Hxx + Hyy)]])
+    U = np.stack([ux, uy, uz], axis=1)  # local -> global
+    return -(U @ H @ U.T)
+
+
+def gl2_gradient(kind, g, P, n=48):
+    """Field gradient by nested Gauss-Legendre quadrature of the kernel
+    (3 d d^T - r^2 I) / r^5 ... with the sign of dE/dP: (r^2 I - 3 d d^T) / r^5."""
+    P = np.asarray(P, float)
+    x, w = leggauss01(n)
+    U, V = np.meshgrid(x, x, indexing="ij")
+    WU, WV = np.meshgrid(w, w, indexing="ij")
+    g = np.asarray(g, float).ravel()
+    if kind == 0:
+        A, B, Cc = g[0:3], g[3:6], g[6:9]
+        Q = A + U[..., None] * (B - A) + (U * V)[..., None] * (Cc - B)
+        jac = np.linalg.norm(np.cross(B - A, Cc - A)) * U
+    else:
+        P0, e1, e2 = g[0:3], g[3:6], g[6:9]
+        Q = P0 + U[..., None] * e1 + V[..., None] * e2
+        jac = np.linalg.norm(e1) * np.linalg.norm(e2) * np.ones_like(U)
+    d = (P - Q).reshape(-1, 3)
+    r2 = np.sum(d * d, axis=1)
+    wt = (WU * WV * jac).ravel() / r2 ** 2.5
+    return np.einsum("k,k->", wt, r2) * np.eye(3) - 3.0 * np.einsum("k,ki,kj->ij", wt, d, d)
+
+
+def gradient_6(G):
+    """3x3 -> (xx, yy, zz, xy, xz, yz)."""
+    return np.array([G[0, 0], G[1, 1], G[2, 2], G[0, 1], G[0, 2], G[1, 2]])
+
+
 def polygon_inplane_potential(V, P):
     """int dA / |Q - P| for P inside a convex planar polygon V (in plane):
     sum over edges of h_e [asinh(t2 / h_e) - asinh(t1 / h_e)]."""
