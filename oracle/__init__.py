@@ -64,7 +64,7 @@ def _load():
         lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_eval.argtypes = [dp, i64, dp, i64, dp, ctypes.POINTER(_Params), dp, i64, dp, dp,
                                  dp, dp, ctypes.POINTER(_Stats), ctypes.c_int]
-        lib.orc_eval_gradient.argtypes = [dp, i64, dp, i64, dp, ctypes.POINTER(_Params), dp, i64, dp, dp,
+        lib.orc_eval_gradient.argtypes = [dp, i64, dp, i64, dp, ctypes.POINTER(_Params), dp, i64, dp, dp, dp,
                                           ctypes.POINTER(_Stats), ctypes.c_int]
         lib.orc_collocation.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.POINTER(_Params),
                                         ctypes.POINTER(ctypes.c_int64), i64, dp, dp,
@@ -158,7 +158,8 @@ def evaluate(tri, rect, sigma, pts, prm=None, nthreads=0, with_abs=False):
 
 
 def gradient(tri, rect, sigma, pts, prm=None, nthreads=0):
-    """G[n, 6] = dE_i/dx_j as (xx, yy, zz, xy, xz, yz), abs[n] scale, stats."""
+    """G[n, 6] = dE_i/dx_j as (xx, yy, zz, xy, xz, yz); abs_G[n] (per-element scale) and
+    abs_T[n] (per-term scale: the rounding scale of the sum); stats."""
     lib = _load()
     prm = prm or params()
     tri = _f64(tri if tri is not None else np.zeros((0, 9)), 9)
@@ -168,13 +169,14 @@ def gradient(tri, rect, sigma, pts, prm=None, nthreads=0):
     n = pts.shape[0]
     if sigma.size != tri.shape[0] + rect.shape[0]:
         raise ValueError("sigma length must equal the element count")
-    G = np.zeros((n, 6)); aG = np.zeros(n)
+    G = np.zeros((n, 6)); aG = np.zeros(n); aT = np.zeros(n)
     st = _Stats()
     rc = lib.orc_eval_gradient(_ptr(tri), tri.shape[0], _ptr(rect), rect.shape[0], _ptr(sigma),
-                               ctypes.byref(prm), _ptr(pts), n, _ptr(G), _ptr(aG), ctypes.byref(st), nthreads)
+                               ctypes.byref(prm), _ptr(pts), n, _ptr(G), _ptr(aG), _ptr(aT), ctypes.byref(st),
+                               nthreads)
     if rc < 0:
         raise ValueError(f"orc_eval_gradient failed ({rc})")
-    return {"G": G, "abs_G": aG, "stats": _stats_dict(st), "threads": rc}
+    return {"G": G, "abs_G": aG, "abs_T": aT, "stats": _stats_dict(st), "threads": rc}
 
 
 def gradient_matrix(g6):

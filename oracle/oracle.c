@@ -381,7 +381,7 @@ static void add_gradient(const double* d, double r, double w, double* G)
 static void apply_rules(const double* P, int kind, const double* g, double area, const tri_rule* TR,
                         const rect_rule* RR, int grad, double* acc)
 {
-    double G[6] = { 0, 0, 0, 0, 0, 0 };
+    double G[6] = { 0, 0, 0, 0, 0, 0 }, T = 0.0;
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     if (kind == 0) {
         const double *A = g, *B = g + 3, *C = g + 6;
@@ -395,7 +395,7 @@ static void apply_rules(const double* P, int kind, const double* g, double area,
             double f = TR->w[i] * inv * inv * inv;
             phi += TR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
-            if (grad) add_gradient(d, r, TR->w[i], G);
+            if (grad) { add_gradient(d, r, TR->w[i], G); T += fabs(TR->w[i]) / (r * r * r); }
         }
     } else {
         const double *P0 = g, *e1 = g + 3, *e2 = g + 6;
@@ -412,12 +412,14 @@ static void apply_rules(const double* P, int kind, const double* g, double area,
             double f = RR->w[i] * inv * inv * inv;
             phi += RR->w[i] * inv;
             ex += f * d[0]; ey += f * d[1]; ez += f * d[2];
-            if (grad) add_gradient(d, r, RR->w[i], G);
+            if (grad) { add_gradient(d, r, RR->w[i], G); T += fabs(RR->w[i]) / (r * r * r); }
         }
     }
     acc[0] += area * phi; acc[1] += area * ex; acc[2] += area * ey; acc[3] += area * ez;
-    if (grad)
+    if (grad) {
         for (int k = 0; k < 6; ++k) acc[4 + k] += area * G[k];
+        acc[10] += area * sqrt(6.0) * T; /* |one term|_F = sqrt(6) |w| / r^3 */
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -587,7 +589,7 @@ static void to_local(const double* P, const elem* e, double* Pl, elem* le)
 static void element_contribution(const double* P, const elem* e, const rules* R, const orc_params* prm,
                                  double* out, lstats* st)
 {
-    for (int k = 0; k < 10; ++k) out[k] = 0.0;
+    for (int k = 0; k < 11; ++k) out[k] = 0.0;
     double d[3];
     sub3(P, e->cen, d);
     double D2 = dot3(d, d);
@@ -615,7 +617,7 @@ static void element_contribution(const double* P, const elem* e, const rules* R,
         st->on_surface++;
         self_rule(Pl, &le, out);
         if (R->grad) /* the normal field jumps across the element: no gradient there */
-            for (int k = 4; k < 10; ++k) out[k] = NAN;
+            for (int k = 4; k < 11; ++k) out[k] = NAN;
         return;
     }
     if (prm->max_depth <= 0) {
@@ -697,7 +699,7 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
             nsum s0 = { 0, 0 }, s1 = { 0, 0 }, s2 = { 0, 0 }, s3 = { 0, 0 };
             double aphi = 0.0, aE = 0.0;
             for (int64_t j = 0; j < ne; ++j) {
-                double c[10];
+                double c[11];
                 element_contribution(P, &el[j], R, prm, c, &ls);
                 double sg = sigma[j];
                 nadd(&s0, sg * c[0]); nadd(&s1, sg * c[1]); nadd(&s2, sg * c[2]); nadd(&s3, sg * c[3]);
@@ -725,10 +727,12 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
  * Eq. (4.1) (conclusions: higher derivatives follow from the same point charges), with the
  * same near-field subdivision (Sec. 4) and rule choice as the field itself.  G is [n][6]
  * (xx, yy, zz, xy, xz, yz); abs_G[p] = K sum_j |sigma_j| |G_j|_F (Frobenius norm of the
- * element's tensor), the scale for relative errors.  A point on an element gets NaN. */
+ * element's tensor); abs_T[p] = K sum over every point-charge term summed (subdivision
+ * leaves included) of |q| sqrt(6) / r^3, the magnitude scale of the rounding of the whole
+ * sum.  A point on an element gets NaN. */
 int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
                       const double* sigma, const orc_params* prm, const double* pts, int64_t n,
-                      double* G, double* abs_G, orc_stats* st, int nthreads)
+                      double* G, double* abs_G, double* abs_T, orc_stats* st, int nthreads)
 {
     if (n_tri < 0 || n_rect < 0 || n < 0 || !prm || !G) return -1;
     rules* R = (rules*)malloc(sizeof(rules));
@@ -759,9 +763,9 @@ int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int6
             const double* P = pts + 3 * p;
             nsum s[6];
             for (int k = 0; k < 6; ++k) { s[k].s = 0.0; s[k].c = 0.0; }
-            double aG = 0.0;
+            double aG = 0.0, aT = 0.0;
             for (int64_t j = 0; j < ne; ++j) {
-                double c[10];
+                double c[11];
                 element_contribution(P, &el[j], R, prm, c, &ls);
                 const double sg = sigma[j];
                 double f2 = 0.0;
@@ -770,9 +774,11 @@ int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int6
                     f2 += (k < 3 ? 1.0 : 2.0) * c[4 + k] * c[4 + k];
                 }
                 aG += fabs(sg) * sqrt(f2);
+                aT += fabs(sg) * c[10];
             }
             for (int k = 0; k < 6; ++k) G[6 * p + k] = K * nval(&s[k]);
             if (abs_G) abs_G[p] = K * aG;
+            if (abs_T) abs_T[p] = K * aT;
         }
 #pragma omp critical
         merge_stats(&tot, &ls);
@@ -820,7 +826,7 @@ int orc_collocation(const double* tri, int64_t n_tri, const double* rect, int64_
             for (int r = 0; r < n_rhs; ++r) { acc[r].s = 0.0; acc[r].c = 0.0; }
             double a0 = 0.0;
             for (int64_t j = 0; j < ne; ++j) {
-                double c[10];
+                double c[11];
                 element_contribution(P, &el[j], R, prm, c, &ls);
                 for (int r = 0; r < n_rhs; ++r) nadd(&acc[r], sigma[(int64_t)r * ne + j] * c[0]);
                 a0 += fabs(sigma[j] * c[0]);
@@ -849,12 +855,12 @@ int orc_element(int kind, const double* geom, const double* P, const orc_params*
     if (rc) { free(R); return rc; }
     lstats ls;
     memset(&ls, 0, sizeof(ls));
-    double tmp[10];
+    double tmp[11];
     if ((mode & 1) == 0) {
         double Pl[3];
         elem le;
         to_local(P, &e, Pl, &le);
-        for (int k = 0; k < 10; ++k) tmp[k] = 0.0;
+        for (int k = 0; k < 11; ++k) tmp[k] = 0.0;
         apply_rule(Pl, kind, le.g, le.area, R, tmp);
     } else {
         element_contribution(P, &e, R, prm, tmp, &ls);

@@ -77,12 +77,14 @@ int orc_eval(const double* tri, int64_t n_tri, const double* rect, int64_t n_rec
  * of Eq. (4.1) contributes K q (delta_ij r^2 - 3 d_i d_j) / r^5 with d = P - Q (the
  * conclusions note that higher derivatives come from the same charges); the near-field
  * subdivision and rule choice are those of the field.  G[n][6] = xx, yy, zz, xy, xz, yz.
- * abs_G[n] (optional) = K sum_j |sigma_j| |G_j|_F.  A point lying on an element has no
- * gradient (the normal field jumps there): its six values are NaN.
- * Returns threads used or < 0. */
+ * abs_G[n] (optional) = K sum_j |sigma_j| |G_j|_F; abs_T[n] (optional) = K times the sum,
+ * over every point-charge term the evaluation adds (near-field leaves included), of
+ * |q| sqrt(6) / r^3 (the Frobenius norm of one term): the scale of the rounding error of
+ * the whole sum.  A point lying on an element has no gradient (the normal field jumps
+ * there): its six values are NaN.  Returns threads used or < 0. */
 int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
                       const double* sigma, const orc_params* prm, const double* pts, int64_t n,
-                      double* G, double* abs_G, orc_stats* st, int nthreads);
+                      double* G, double* abs_G, double* abs_T, orc_stats* st, int nthreads);
 
 /* Matrix-free collocation product: out[r][k] = potential at the centroid of element
  * rows[k] from all elements with density sigma[r][:], r < n_rhs.  The element's own

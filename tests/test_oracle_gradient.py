@@ -115,6 +115,11 @@ def test_mesh_gradient_trace_free_and_derivative_of_field(orc, mesh):
     assert np.all(np.isfinite(G)) and np.all(aG > 0)
     # Laplace: the gradient of a source-free field is trace-free
     assert np.all(np.abs(G[:, 0] + G[:, 1] + G[:, 2]) <= 1e-13 * aG)
+    # per-term scale: at least the per-element one (triangle inequality), equal to it for
+    # a point far from every element (each element is then one cluster of like terms)
+    aT = res["abs_T"]
+    assert np.all(aT >= aG * (1 - 1e-13))
+    assert np.all(aT[:6] <= 1.05 * aG[:6]) and np.any(aT[6:] > 1.5 * aG[6:])
     # dE/dx by Richardson central differences of the oracle's field
     M = orc.gradient_matrix(G)
     for p in range(pts.shape[0]):
