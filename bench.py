@@ -30,6 +30,7 @@ PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 128 FP32 FMA lanes x 2 (packed)
 FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
 FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
+GRAD_FLOP_PER_NODE_INT = 30  # field gradient (six components) per point-charge term
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_hbm.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_valu.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
@@ -155,6 +156,22 @@ def main():
     phidrm, Edrm = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     ctx.set_dr_rules(False)
 
+    # field gradient dE_i/dx_j (six rows) on the same workload
+    G = torch.empty((6, n), dtype=torch.float64, device=dev)
+    grad = {}
+    for prec in ("fp64", "mixed"):
+        ctx.eval_gradient(pts, prec, G=G)
+        torch.cuda.synchronize()
+        log(f"gradient {prec} warmup done")
+        t0 = time.perf_counter()
+        ctx.eval_gradient(pts, prec, G=G)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.stats()
+        grad[prec] = {"value": st["pairs"] / dt, "unit": "pairs/s", "ms": 1e3 * dt, "far_kernel_ms": st["far_ms"],
+                      "near_kernel_ms": st["near_ms"], "G": G.cpu().numpy().T.copy()}
+        log(f"gradient {prec} step done")
+
     pairs = st64["pairs"]
     node_int = st64["node_interactions"]
     ms_step = 1e3 * dt64 / args.steps
@@ -195,6 +212,13 @@ def main():
                     "roofline": {"bound": "alu", "achieved": mixed_ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                  "frac": mixed_ach / PEAK_FP32_TFLOPS}}
 
+    g_flops = GRAD_FLOP_PER_NODE_INT * node_int + FLOP_PER_PAIR * pairs
+    for prec, peak in (("fp64", PEAK_FP64_TFLOPS), ("mixed", PEAK_FP32_TFLOPS)):
+        a_ = g_flops / (1e-3 * grad[prec]["far_kernel_ms"]) / 1e12
+        grad[prec]["roofline"] = {"bound": "alu", "achieved": a_, "peak": peak, "unit": "TFLOP/s", "frac": a_ / peak}
+    out["gradient"] = {k: {kk: vv for kk, vv in v.items() if kk != "G"} for k, v in grad.items()}
+    out["gradient"]["flops_per_node_interaction"] = GRAD_FLOP_PER_NODE_INT
+
     out["dr_rules"] = {"value": pairs * args.steps / dtdr, "unit": "pairs/s", "precision": "fp64",
                        "ms_per_step": 1e3 * dtdr / args.steps, "far_kernel_ms": float(np.mean(fardr)),
                        "node_interactions": stdr["node_interactions"],
@@ -232,6 +256,13 @@ def main():
             acc[name] = {"max_norm_err_phi": float(ep.max()), "max_norm_err_E": float(ee.max()),
                          "median_rel_err_phi": float(np.median(rp))}
         out["accuracy_vs_oracle"] = acc
+        gidx = idx[::10]
+        log(f"oracle gradient on {gidx.size} sampled points")
+        gref = oracle.gradient(w.tri, w.rect, w.sigma[0], w.points[gidx], oracle.params(33, 7))
+        for prec in ("fp64", "mixed"):
+            e = np.abs(grad[prec]["G"][gidx] - gref["G"]).max(axis=1) / gref["abs_T"]
+            out["gradient"][prec]["max_norm_err"] = float(e.max())
+            out["gradient"][prec]["median_norm_err"] = float(np.median(e))
         out["mixed"]["within_1e-6"] = acc["mixed"]["max_norm_err_phi"] <= 1e-6 and acc["mixed"]["max_norm_err_E"] <= 1e-6
 
         # collocation product: nested cylinders, 200,000 elements, 8 right-hand sides

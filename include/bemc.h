@@ -149,6 +149,20 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
 int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
               double* phi, double* E, void* stream);
 
+/* Field gradient dE_i/dx_j (V/m^2, symmetric and trace-free off the electrodes) at the n
+ * field points pts[3][n] (device): G[6][n] (device, overwritten) holds the rows xx, yy, zz,
+ * xy, xz, yz.  The derivative of the point-charge sums of Eq. (4.1): each Gaussian point
+ * contributes K q (delta_ij r^2 - 3 d_i d_j) / r^5, d = P - Q (Sec. 7, conclusions: higher
+ * derivatives of the field follow from the same point charges, e.g. for field maps with
+ * Hermite interpolation).  Classification, near-field
+ * subdivision, rule choice (including bemc_set_dr_rules) and precision handling are those
+ * of bemc_eval; BEMC_MIXED forms the FP32 node sums from unit vectors d/r (no power of 1/r
+ * above the third in FP32).  A field point lying on an element gets NaN in all six rows
+ * (the normal field jumps there) and the call returns BEMC_W_ON_SURFACE.  Synchronous
+ * like bemc_eval.  Errors: as bemc_eval. */
+int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
+                       double* G, void* stream);
+
 /* Matrix-free collocation product (BEM system matrix times densities, Sec. 5: the
  * matrix is never stored): out[r][i] = potential at the centroid of element i from the
  * densities sigma[r][:], r < n_rhs (1..8), for every element i.  sigma and out are device

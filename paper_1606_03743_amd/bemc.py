@@ -31,7 +31,7 @@ MIXED = 1
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 
 EXPORTED = ["bemc_last_error", "bemc_create", "bemc_destroy", "bemc_set_rules", "bemc_upload_geometry",
-            "bemc_upload_densities", "bemc_eval", "bemc_collocation_matvec", "bemc_query_stats",
+            "bemc_upload_densities", "bemc_eval", "bemc_eval_gradient", "bemc_collocation_matvec", "bemc_query_stats",
             "bemc_server_start", "bemc_server_submit", "bemc_server_poll", "bemc_server_wait",
             "bemc_server_stop", "bemc_coulomb_constant", "bemc_rule_size", "bemc_set_near_capacity",
             "bemc_set_dr_rules", "bemc_solve_densities"]
@@ -91,6 +91,7 @@ def load_library():
     lib.bemc_upload_geometry.argtypes = [vp, vp, i64, vp, i64, vp]
     lib.bemc_upload_densities.argtypes = [vp, vp, ci, ci, vp]
     lib.bemc_eval.argtypes = [vp, vp, i64, ci, ci, vp, vp, vp]
+    lib.bemc_eval_gradient.argtypes = [vp, vp, i64, ci, ci, vp, vp]
     lib.bemc_collocation_matvec.argtypes = [vp, vp, ci, ci, vp, vp]
     lib.bemc_query_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.bemc_set_near_capacity.argtypes = [vp, i64]
@@ -216,6 +217,18 @@ class Context:
                                 _dev_f64(E, (3, n)) if with_E else None, _stream_ptr())
         _check(rc, allow_warning=True)
         return phi, (E if with_E else None), rc
+
+    def eval_gradient(self, pts, precision="fp64", rhs=0, G=None):
+        """pts: float64 CUDA tensor [3, n].  Returns (G [6, n] rows xx yy zz xy xz yz, status)."""
+        torch = _torch()
+        n = pts.shape[1]
+        _dev_f64(pts, (3, n))
+        if G is None:
+            G = torch.empty((6, n), dtype=torch.float64, device=pts.device)
+        rc = self.lib.bemc_eval_gradient(self.h, _dev_f64(pts), n, _PREC[precision], rhs, _dev_f64(G, (6, n)),
+                                         _stream_ptr())
+        _check(rc, allow_warning=True)
+        return G, rc
 
     def collocation(self, sigma, precision="fp64", out=None):
         """sigma: float64 CUDA tensor [n_rhs, n_E]; returns out [n_rhs, n_E]."""

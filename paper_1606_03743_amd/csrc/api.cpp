@@ -107,7 +107,9 @@ struct bemc_context {
     int ensure_near_capacity(unsigned long long need);
     Elements elements() const;
     RuleTables rules() const;
-    int run(bool colloc, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
+    // mode kNearEval: phi, E at points; kNearColloc: out (= phi) [n_rhs][ne] at centroids;
+    // kNearGrad: G (= phi) [6][n] at points
+    int run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
             double* E, hipStream_t s);
 };
 
@@ -215,7 +217,7 @@ void bemc_context::free_order()
     dev_free(ow.keys_in); dev_free(ow.keys_out); dev_free(ow.idx_in); dev_free(ow.perm);
     if (ow.temp) (void)hipFree(ow.temp);
     ow.temp = nullptr;
-    dev_free(ow.bbox); dev_free(ow.pts); dev_free(ow.phi); dev_free(ow.E);
+    dev_free(ow.bbox); dev_free(ow.pts); dev_free(ow.res);
     ow_cap = 0;
 }
 
@@ -228,7 +230,7 @@ int bemc_context::ensure_order(int64_t n)
     ow.temp_bytes = order_temp_bytes(n);
     if (dev_alloc(&ow.keys_in, m) || dev_alloc(&ow.keys_out, m) || dev_alloc(&ow.idx_in, m) || dev_alloc(&ow.perm, m) ||
         hipMalloc(&ow.temp, std::max<size_t>(ow.temp_bytes, 1)) || dev_alloc(&ow.bbox, 6 * 1024) ||
-        dev_alloc(&ow.pts, 3 * m) || dev_alloc(&ow.phi, m) || dev_alloc(&ow.E, 3 * m)) {
+        dev_alloc(&ow.pts, 3 * m) || dev_alloc(&ow.res, 6 * m)) {
         (void)hipGetLastError();
         free_order();
         return fail(BEMC_E_OUT_OF_MEMORY, "point-ordering workspace for %lld points", (long long)n);
@@ -252,10 +254,12 @@ int bemc_context::ensure_near_capacity(unsigned long long need)
     return ok();
 }
 
-int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc,
+int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc,
                       double* phi, double* E, hipStream_t s)
 {
     HIP_TRY(hipSetDevice(device));
+    const bool colloc = mode == kNearColloc;
+    const bool grad = mode == kNearGrad;
     // rule choice by distance ratio: evaluate on Morton-ordered points, scatter back at the end
     const bool ordered = dr_rules && !colloc;
     double* user_phi = phi;
@@ -265,9 +269,11 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         if (rc) return rc;
         HIP_TRY(order_points(pts, n, ow, s));
         pts = ow.pts;
-        phi = ow.phi;
-        E = ow.E;
+        phi = ow.res;
+        E = E ? ow.res + n : nullptr;
     }
+    double* G = grad ? phi : nullptr;
+    if (grad) phi = E = nullptr;
     if (near_cap == 0) {
         int rc = ensure_near_capacity(std::max<unsigned long long>(1ull << 20, (unsigned long long)(colloc ? ne : n) * 8));
         if (rc) return rc;
@@ -276,14 +282,14 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         FarArgs fa{};
         fa.el = elements(); fa.rules = rules();
         if (colloc) { fa.el.q = d_qc; fa.el.n_rhs = n_rhs_colloc; } fa.pts = pts; fa.n = colloc ? ne : n; fa.rhs = rhs;
-        fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant(); fa.phi = phi; fa.E = E; fa.partial = nullptr;
+        fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant(); fa.phi = phi; fa.E = E; fa.G = G; fa.partial = nullptr;
         fa.elem_begin = 0; fa.elem_end = ne; fa.n_split = 1; fa.chunk = ne; fa.near_list = d_near; fa.near_cap = near_cap;
         fa.ctr = d_ctr;
         fa.dr_rules = (dr_rules && !colloc) ? 1 : 0;
         fa.lv = levels();
         NearArgs na{};
         na.el = fa.el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = fa.n; na.rhs = rhs;
-        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.near_list = d_near; na.near_cap = near_cap;
+        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_list = d_near; na.near_cap = near_cap;
         na.ctr = d_ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
 
         // Split the element range over blockIdx.y so that the launch has many more
@@ -293,7 +299,7 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         const int64_t blocks = (npts + 511) / 512;
         int n_split = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (kSplitTargetBlocks + blocks - 1) / blocks));
         n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 64));  // chunks of >= 64 elements
-        const int64_t rows = colloc ? n_rhs_colloc : 4;
+        const int64_t rows = colloc ? n_rhs_colloc : (grad ? 6 : 4);
         if (n_split > 1) {
             const size_t need = (size_t)n_split * (size_t)rows * (size_t)npts;
             if (need > partial_cap) {
@@ -312,15 +318,24 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         fa.partial = n_split > 1 ? d_partial : nullptr;
         HIP_TRY(launch_zero_counters(d_ctr, s));
         HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(colloc ? launch_far_colloc(fa, precision, s) : launch_far_eval(fa, precision, s));
+        HIP_TRY(colloc ? launch_far_colloc(fa, precision, s)
+                       : (grad ? launch_far_grad(fa, precision, s) : launch_far_eval(fa, precision, s)));
         if (n_split > 1) {
             if (colloc) HIP_TRY(launch_reduce_chunks(d_partial, n_split, rows, npts, fa.K, phi, s));
+            else if (grad) HIP_TRY(launch_reduce_chunks(d_partial, n_split, rows, npts, fa.K, G, s));
             else HIP_TRY(launch_reduce_split(d_partial, n_split, npts, fa.K, phi, E, s));
         }
         HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(launch_near(na, colloc, s));
+        HIP_TRY(launch_near(na, mode, s));
         HIP_TRY(hipEventRecord(ev[2], s));
-        if (ordered) HIP_TRY(unorder_results(ow, n, user_phi, user_E, s));
+        if (ordered) {
+            if (grad) {
+                HIP_TRY(unorder_rows(ow, n, ow.res, 6, user_phi, s));
+            } else {
+                HIP_TRY(unorder_rows(ow, n, ow.res, 1, user_phi, s));
+                if (user_E) HIP_TRY(unorder_rows(ow, n, ow.res + n, 3, user_E, s));
+            }
+        }
         HIP_TRY(hipMemcpyAsync(h_ctr, d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(ev[3], s));
         HIP_TRY(hipEventSynchronize(ev[3]));
@@ -348,7 +363,8 @@ int bemc_context::run(bool colloc, const double* pts, int64_t n, int precision, 
         if (h_ctr->visit_limit_hits)
             return fail(BEMC_E_LIMIT, "%llu near pairs hit the subdivision visit limit", h_ctr->visit_limit_hits);
         if (!colloc && h_ctr->on_surface) {
-            g_last_error = "some field points lie on an element (principal-value field)";
+            g_last_error = grad ? "some field points lie on an element (their gradient is NaN)"
+                                : "some field points lie on an element (principal-value field)";
             return BEMC_W_ON_SURFACE;
         }
         return ok();
@@ -596,7 +612,20 @@ int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rh
     if (!pts || !phi) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
     if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
     if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
-    return h->run(false, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream));
+    return h->run(kNearEval, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream));
+}
+
+int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precision, int rhs, double* G, void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry || h->n_rhs == 0) return fail(BEMC_E_NO_GEOMETRY, "geometry and densities must be uploaded");
+    if (n < 0) return fail(BEMC_E_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (n >= (1ll << 31)) return fail(BEMC_E_LIMIT, "n >= 2^31");
+    if (!pts || !G) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
+    return h->run(kNearGrad, pts, n, precision, rhs, 1, G, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision, double* out, void* stream)
@@ -616,7 +645,7 @@ int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int p
         return fail(BEMC_E_OUT_OF_MEMORY, "collocation charges");
     }
     HIP_TRY(launch_charges(sigma, h->d_area, h->d_qc, h->ne, n_rhs, s));
-    return h->run(true, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
+    return h->run(kNearColloc, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
 }
 
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,

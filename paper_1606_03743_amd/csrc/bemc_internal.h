@@ -93,7 +93,8 @@ struct FarArgs {
     double K;                // Coulomb constant
     double* phi;             // [n] (eval) or out[n_rhs][ne] (collocation)
     double* E;               // [3][n] or null
-    double* partial;         // element-split partial sums [n_split][4][n] (serving) or null
+    double* G;               // [6][n] field gradient (gradient mode)
+    double* partial;         // element-split partial sums [n_split][rows][n] or null
     int64_t elem_begin, elem_end;  // element range of this launch
     int n_split;             // > 1: blockIdx.y takes elements [begin + y chunk, begin + (y+1) chunk)
     int64_t chunk;
@@ -114,6 +115,7 @@ struct NearArgs {
     double K;
     double* phi;        // eval: phi[n]; collocation: out[n_rhs][ne]
     double* E;          // eval only, may be null
+    double* G;          // gradient mode: [6][n]
     const NearPair* near_list;
     unsigned long long near_cap;
     DevCounters* ctr;
@@ -125,7 +127,9 @@ struct NearArgs {
 // kernel launchers (kernels.hip)
 hipError_t launch_far_eval(const FarArgs& a, int precision, hipStream_t s);
 hipError_t launch_far_colloc(const FarArgs& a, int precision, hipStream_t s);
-hipError_t launch_near(const NearArgs& a, bool collocation, hipStream_t s);
+hipError_t launch_far_grad(const FarArgs& a, int precision, hipStream_t s);
+enum NearMode { kNearEval = 0, kNearColloc = 1, kNearGrad = 2 };
+hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s);
 hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s);
 hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
                                hipStream_t s);
@@ -154,11 +158,11 @@ struct OrderWork {
     size_t temp_bytes;
     double* bbox;    // [1024][6]
     double* pts;     // [3][n] points in sorted order
-    double* phi;     // [n]    results in sorted order
-    double* E;       // [3][n]
+    double* res;     // [6][n] results in sorted order (phi, E or the gradient rows)
 };
 size_t order_temp_bytes(int64_t n);
 hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStream_t s);
-hipError_t unorder_results(const OrderWork& w, int64_t n, double* phi, double* E, hipStream_t s);
+// dst[r][perm[i]] = src[r][i] for r < rows (src rows in sorted order, n points)
+hipError_t unorder_rows(const OrderWork& w, int64_t n, const double* src, int rows, double* dst, hipStream_t s);
 
 }  // namespace bemc

@@ -140,101 +140,187 @@ __device__ __forceinline__ void stage_tile(Lds& s, const Elements& el, const Rul
 }
 
 // ------------------------------------------------------------ far field: eval -------
-template <int PPT>
+// GRAD == false: per point phi, Ex, Ey, Ez.  GRAD == true: the field gradient dE_i/dx_j as
+// xx, yy, zz, xy, xz, yz (each point charge contributes q (delta_ij r^2 - 3 d_i d_j) / r^5).
+template <bool GRAD>
+struct Sums {
+    static constexpr int kOut = GRAD ? 6 : 4;  // accumulated outputs per point
+    static constexpr int kNode = GRAD ? 7 : 4; // per-element node sums per point
+};
+
+template <int PPT, bool GRAD>
 struct PointSet {
     double x[PPT], y[PPT], z[PPT];
     bool valid[PPT];
     uint32_t idx[PPT];
-    double phi[PPT], ex[PPT], ey[PPT], ez[PPT];
+    double acc[Sums<GRAD>::kOut][PPT];
 };
 
-// Point-charge sums of one element (Eq. 4.1) over its Gaussian points nd[0 .. n) for PPT
-// field points given by their offsets from the element centroid; unit element charge.
-// NN > 0: compile-time node count.
-template <int NN, int PPT>
-__device__ __forceinline__ void node_sum64(const double4* __restrict__ nd, int nn, const double (&dx)[PPT],
-                                           const double (&dy)[PPT], const double (&dz)[PPT], double (&f)[PPT],
-                                           double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT])
+// Terms of one Gaussian point Q (offset and weight) for PPT field points.
+template <int PPT, bool GRAD>
+__device__ __forceinline__ void node_term64(const double4 Q, const double (&dx)[PPT], const double (&dy)[PPT],
+                                            const double (&dz)[PPT], double (&o)[Sums<GRAD>::kNode][PPT])
 {
-    const int n = NN > 0 ? NN : nn;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < n; ++i) {
-        const double4 Q = nd[i];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-            const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-            const double ri = rsqrt64(r2);
-            const double wr = Q.w * ri;
-            f[k] += wr;
+    for (int k = 0; k < PPT; ++k) {
+        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ri = rsqrt64(r2);
+        const double wr = Q.w * ri;
+        if (!GRAD) {
+            o[0][k] += wr;
             const double w3 = wr * (ri * ri);
-            gx[k] = fma(w3, rx, gx[k]);
-            gy[k] = fma(w3, ry, gy[k]);
-            gz[k] = fma(w3, rz, gz[k]);
+            o[1][k] = fma(w3, rx, o[1][k]);
+            o[2][k] = fma(w3, ry, o[2][k]);
+            o[3][k] = fma(w3, rz, o[3][k]);
+        } else {
+            const double ri2 = ri * ri;
+            const double w3 = wr * ri2;
+            const double w5 = w3 * ri2;
+            o[0][k] += w3;
+            const double ux = w5 * rx, uy = w5 * ry, uz = w5 * rz;
+            o[1][k] = fma(ux, rx, o[1][k]);
+            o[2][k] = fma(uy, ry, o[2][k]);
+            o[3][k] = fma(uz, rz, o[3][k]);
+            o[4][k] = fma(ux, ry, o[4][k]);
+            o[5][k] = fma(ux, rz, o[5][k]);
+            o[6][k] = fma(uy, rz, o[6][k]);
         }
     }
 }
 
-template <int NN, int PPT>
-__device__ __forceinline__ void node_sum32(const float4* __restrict__ nd, int nn, const float (&dx)[PPT],
-                                           const float (&dy)[PPT], const float (&dz)[PPT], float (&f)[PPT],
-                                           float (&gx)[PPT], float (&gy)[PPT], float (&gz)[PPT])
+// Point-charge sums of one element (Eq. 4.1) over its Gaussian points nd[0 .. n) for PPT
+// field points given by their offsets from the element centroid; unit element charge.
+// Field: o = (sum w/r, sum w d/r^3).  Gradient: o = (sum w/r^3, sum w d_i d_j / r^5 for
+// xx, yy, zz, xy, xz, yz).  NN > 0: compile-time node count.
+template <int NN, int PPT, bool GRAD>
+__device__ __forceinline__ void node_sum64(const double4* __restrict__ nd, int nn, const double (&dx)[PPT],
+                                           const double (&dy)[PPT], const double (&dz)[PPT],
+                                           double (&o)[Sums<GRAD>::kNode][PPT])
 {
     const int n = NN > 0 ? NN : nn;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0f;
-#pragma unroll 4
-    for (int i = 0; i < n; ++i) {
-        const float4 Q = nd[i];
+    for (int c = 0; c < Sums<GRAD>::kNode; ++c)
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const float rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-            const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-            const float ri = rsqrt32(r2);
-            const float wr = Q.w * ri;
-            f[k] += wr;
-            const float w3 = wr * (ri * ri);
-            gx[k] = fmaf(w3, rx, gx[k]);
-            gy[k] = fmaf(w3, ry, gy[k]);
-            gz[k] = fmaf(w3, rz, gz[k]);
+        for (int k = 0; k < PPT; ++k) o[c][k] = 0.0;
+    // Long rules: groups of four nodes, then the remainder.  This keeps the accumulators in
+    // place; an unrolled loop with a remainder makes the compiler copy them every iteration.
+    if (NN > 0 && NN < 32) {  // the short rules of the distance-ratio levels
+#pragma unroll 4
+        for (int i = 0; i < n; ++i) node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o);
+        return;
+    }
+    int i = 0;
+#pragma unroll 1
+    for (; i + 4 <= n; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) node_term64<PPT, GRAD>(nd[i + u], dx, dy, dz, o);
+    }
+    for (; i < n; ++i) node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o);
+}
+
+// FP32 versions.  The gradient uses unit vectors (d / r) so that no power of 1/r above the
+// third is formed in single precision.
+template <int PPT, bool GRAD>
+__device__ __forceinline__ void node_term32(const float4 Q, const float (&dx)[PPT], const float (&dy)[PPT],
+                                            const float (&dz)[PPT], float (&o)[Sums<GRAD>::kNode][PPT])
+{
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const float rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
+        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+        const float ri = rsqrt32(r2);
+        const float wr = Q.w * ri;
+        const float w3 = wr * (ri * ri);
+        if (!GRAD) {
+            o[0][k] += wr;
+            o[1][k] = fmaf(w3, rx, o[1][k]);
+            o[2][k] = fmaf(w3, ry, o[2][k]);
+            o[3][k] = fmaf(w3, rz, o[3][k]);
+        } else {
+            o[0][k] += w3;
+            const float vx = rx * ri, vy = ry * ri, vz = rz * ri;
+            const float ux = w3 * vx, uy = w3 * vy, uz = w3 * vz;
+            o[1][k] = fmaf(ux, vx, o[1][k]);
+            o[2][k] = fmaf(uy, vy, o[2][k]);
+            o[3][k] = fmaf(uz, vz, o[3][k]);
+            o[4][k] = fmaf(ux, vy, o[4][k]);
+            o[5][k] = fmaf(ux, vz, o[5][k]);
+            o[6][k] = fmaf(uy, vz, o[6][k]);
         }
     }
+}
+
+template <int NN, int PPT, bool GRAD>
+__device__ __forceinline__ void node_sum32(const float4* __restrict__ nd, int nn, const float (&dx)[PPT],
+                                           const float (&dy)[PPT], const float (&dz)[PPT],
+                                           float (&o)[Sums<GRAD>::kNode][PPT])
+{
+    const int n = NN > 0 ? NN : nn;
+#pragma unroll
+    for (int c = 0; c < Sums<GRAD>::kNode; ++c)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) o[c][k] = 0.0f;
+    if (NN > 0 && NN < 32) {  // the short rules of the distance-ratio levels
+#pragma unroll 4
+        for (int i = 0; i < n; ++i) node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o);
+        return;
+    }
+    int i = 0;
+#pragma unroll 1
+    for (; i + 4 <= n; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) node_term32<PPT, GRAD>(nd[i + u], dx, dy, dz, o);
+    }
+    for (; i < n; ++i) node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o);
 }
 
 // Element sums for the nodes [o, o + n) of element j of the tile: FP64, or FP32 on offsets
 // from the centroid with the result widened to FP64.
-template <int NN, bool MIXED, int PPT, typename Lds>
+template <int NN, bool MIXED, int PPT, bool GRAD, typename Lds>
 __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const double (&dx)[PPT],
-                                            const double (&dy)[PPT], const double (&dz)[PPT], double (&f)[PPT],
-                                            double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT])
+                                            const double (&dy)[PPT], const double (&dz)[PPT],
+                                            double (&o)[Sums<GRAD>::kNode][PPT])
 {
     if (!MIXED) {
-        node_sum64<NN, PPT>(reinterpret_cast<const double4*>(s.node) + base, n, dx, dy, dz, f, gx, gy, gz);
+        node_sum64<NN, PPT, GRAD>(reinterpret_cast<const double4*>(s.node) + base, n, dx, dy, dz, o);
     } else {
-        float fx[PPT], fy[PPT], fz[PPT], ff[PPT], fgx[PPT], fgy[PPT], fgz[PPT];
+        float fx[PPT], fy[PPT], fz[PPT], fo[Sums<GRAD>::kNode][PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             fx[k] = (float)dx[k];
             fy[k] = (float)dy[k];
             fz[k] = (float)dz[k];
         }
-        node_sum32<NN, PPT>(reinterpret_cast<const float4*>(s.node) + base, n, fx, fy, fz, ff, fgx, fgy, fgz);
+        node_sum32<NN, PPT, GRAD>(reinterpret_cast<const float4*>(s.node) + base, n, fx, fy, fz, fo);
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            f[k] = (double)ff[k];
-            gx[k] = (double)fgx[k];
-            gy[k] = (double)fgy[k];
-            gz[k] = (double)fgz[k];
-        }
+        for (int c = 0; c < Sums<GRAD>::kNode; ++c)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) o[c][k] = (double)fo[c][k];
+    }
+}
+
+// acc += q * (element sums of point k), in the output form
+template <int PPT, bool GRAD>
+__device__ __forceinline__ void add_element(PointSet<PPT, GRAD>& P, int k, double q,
+                                            const double (&o)[Sums<GRAD>::kNode][PPT])
+{
+    if (!GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) P.acc[c][k] = fma(q, o[c][k], P.acc[c][k]);
+    } else {
+        // dE_i/dx_j = sum w (delta_ij / r^3 - 3 d_i d_j / r^5)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P.acc[c][k] = fma(q, fma(-3.0, o[1 + c][k], o[0][k]), P.acc[c][k]);
+#pragma unroll
+        for (int c = 3; c < 6; ++c) P.acc[c][k] = fma(-3.0 * q, o[1 + c][k], P.acc[c][k]);
     }
 }
 
 // One element kind over [e_begin, e_end) with one rule; NN > 0 is the compile-time node
 // count, NN == 0 reads it at run time.
-template <int NN, bool TRI, bool MIXED, int PPT, typename Lds>
-__device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT>& P, int64_t e_begin,
+template <int NN, bool TRI, bool MIXED, int PPT, bool GRAD, typename Lds>
+__device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT, GRAD>& P, int64_t e_begin,
                                                int64_t e_end)
 {
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
@@ -257,42 +343,33 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
                 nr[k] = P.valid[k] && (D2 < thr2);
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
-            double f[PPT], gx[PPT], gy[PPT], gz[PPT];
-            element_sum<NN, MIXED, PPT>(s, j * nn, nn, dx, dy, dz, f, gx, gy, gz);
+            double o[Sums<GRAD>::kNode][PPT];
+            element_sum<NN, MIXED, PPT, GRAD>(s, j * nn, nn, dx, dy, dz, o);
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!nr[k]) {
-                    P.phi[k] = fma(q, f[k], P.phi[k]);
-                    P.ex[k] = fma(q, gx[k], P.ex[k]);
-                    P.ey[k] = fma(q, gy[k], P.ey[k]);
-                    P.ez[k] = fma(q, gz[k], P.ez[k]);
-                }
-            }
+            for (int k = 0; k < PPT; ++k)
+                if (!nr[k]) add_element<PPT, GRAD>(P, k, q, o);
         }
     }
 }
 
 // One level of the distance-ratio rule choice: the wavefront runs the level's nodes only
 // if one of its lanes needs it; lanes whose points took another level discard the result.
-template <int NN, bool MIXED, int PPT, typename Lds>
+template <int NN, bool MIXED, int PPT, bool GRAD, typename Lds>
 __device__ __forceinline__ void level_sum(const Lds& s, int base, int n, int lv, const int (&lvl)[PPT],
                                           const double (&dx)[PPT], const double (&dy)[PPT], const double (&dz)[PPT],
-                                          double (&f)[PPT], double (&gx)[PPT], double (&gy)[PPT], double (&gz)[PPT],
-                                          unsigned long long& terms)
+                                          double (&o)[Sums<GRAD>::kNode][PPT], unsigned long long& terms)
 {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) any |= (lvl[k] == lv);
     if (__ballot(any) == 0ull) return;
-    double tf[PPT], tx[PPT], ty[PPT], tz[PPT];
-    element_sum<NN, MIXED, PPT>(s, base, n, dx, dy, dz, tf, tx, ty, tz);
+    double t[Sums<GRAD>::kNode][PPT];
+    element_sum<NN, MIXED, PPT, GRAD>(s, base, n, dx, dy, dz, t);
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
         if (lvl[k] == lv) {
-            f[k] = tf[k];
-            gx[k] = tx[k];
-            gy[k] = ty[k];
-            gz[k] = tz[k];
+#pragma unroll
+            for (int c = 0; c < Sums<GRAD>::kNode; ++c) o[c][k] = t[c][k];
             terms += (unsigned)n;
         }
 }
@@ -300,8 +377,8 @@ __device__ __forceinline__ void level_sum(const Lds& s, int base, int n, int lv,
 // One element kind with the rule chosen per pair by distance ratio (Sec. 4): the staged
 // nodes of an element are the four levels back to back; level l is used when
 // D^2 >= c[l] (near_dr L)^2, the last level otherwise.  N0..N3 > 0: compile-time counts.
-template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, typename Lds>
-__device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT>& P, int64_t e_begin,
+template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, bool GRAD, typename Lds>
+__device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, GRAD>& P, int64_t e_begin,
                                                   int64_t e_end, unsigned long long& terms)
 {
     const int* off = TRI ? a.lv.tri_off : a.lv.rect_off;
@@ -330,21 +407,18 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
                 lvl[k] = D2 >= c0 * thr2 ? 0 : (D2 >= c1 * thr2 ? 1 : (D2 >= c2 * thr2 ? 2 : 3));
                 if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
             }
-            double f[PPT], gx[PPT], gy[PPT], gz[PPT];
+            double o[Sums<GRAD>::kNode][PPT];
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) f[k] = gx[k] = gy[k] = gz[k] = 0.0;
+            for (int cc = 0; cc < Sums<GRAD>::kNode; ++cc)
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) o[cc][k] = 0.0;
             const int b = j * nn;
-            level_sum<N0, MIXED, PPT>(s, b, o1, 0, lvl, dx, dy, dz, f, gx, gy, gz, terms);
-            level_sum<N1, MIXED, PPT>(s, b + o1, o2 - o1, 1, lvl, dx, dy, dz, f, gx, gy, gz, terms);
-            level_sum<N2, MIXED, PPT>(s, b + o2, o3 - o2, 2, lvl, dx, dy, dz, f, gx, gy, gz, terms);
-            level_sum<N3, MIXED, PPT>(s, b + o3, nn - o3, 3, lvl, dx, dy, dz, f, gx, gy, gz, terms);
+            level_sum<N0, MIXED, PPT, GRAD>(s, b, o1, 0, lvl, dx, dy, dz, o, terms);
+            level_sum<N1, MIXED, PPT, GRAD>(s, b + o1, o2 - o1, 1, lvl, dx, dy, dz, o, terms);
+            level_sum<N2, MIXED, PPT, GRAD>(s, b + o2, o3 - o2, 2, lvl, dx, dy, dz, o, terms);
+            level_sum<N3, MIXED, PPT, GRAD>(s, b + o3, nn - o3, 3, lvl, dx, dy, dz, o, terms);
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                P.phi[k] = fma(q, f[k], P.phi[k]);
-                P.ex[k] = fma(q, gx[k], P.ex[k]);
-                P.ey[k] = fma(q, gy[k], P.ey[k]);
-                P.ez[k] = fma(q, gz[k], P.ez[k]);
-            }
+            for (int k = 0; k < PPT; ++k) add_element<PPT, GRAD>(P, k, q, o);
         }
     }
 }
@@ -361,12 +435,14 @@ __device__ __forceinline__ void add_terms(unsigned long long terms, DevCounters*
 }
 
 // DR == false: one rule per kind, NT / NR nodes.  DR == true: levels (T0..T3 / R0..R3).
-template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT>
+// GRAD: field gradient instead of potential and field.
+template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT, bool GRAD>
 __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
 {
     using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
+    constexpr int NO = Sums<GRAD>::kOut;
     __shared__ Lds s;
-    PointSet<PPT> P;
+    PointSet<PPT, GRAD> P;
     const int64_t base = (int64_t)blockIdx.x * (kBlock * PPT) + threadIdx.x;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -376,7 +452,8 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
         P.x[k] = P.valid[k] ? a.pts[p] : 0.0;
         P.y[k] = P.valid[k] ? a.pts[a.n + p] : 0.0;
         P.z[k] = P.valid[k] ? a.pts[2 * a.n + p] : 0.0;
-        P.phi[k] = P.ex[k] = P.ey[k] = P.ez[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NO; ++c) P.acc[c][k] = 0.0;
     }
     int64_t e_lo = a.elem_begin, e_hi = a.elem_end;
     if (a.n_split > 1) {
@@ -387,29 +464,30 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
     const int64_t nr_begin = max((int64_t)a.el.n_tri, e_lo);
     if (DR) {
         unsigned long long terms = 0;
-        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT>(a, s, P, e_lo, nt_end, terms);
-        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT>(a, s, P, nr_begin, e_hi, terms);
+        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, GRAD>(a, s, P, e_lo, nt_end, terms);
+        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, GRAD>(a, s, P, nr_begin, e_hi, terms);
         add_terms(terms, a.ctr);
     } else {
-        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT>(a, s, P, e_lo, nt_end);
-        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT>(a, s, P, nr_begin, e_hi);
+        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, GRAD>(a, s, P, e_lo, nt_end);
+        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, GRAD>(a, s, P, nr_begin, e_hi);
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (!P.valid[k]) continue;
         const int64_t p = base + (int64_t)k * kBlock;
         if (a.partial) {  // element-split launch: unscaled partial sums, reduced later in fixed order
-            double* o = a.partial + (int64_t)blockIdx.y * 4 * a.n;
-            o[p] = P.phi[k];
-            o[a.n + p] = P.ex[k];
-            o[2 * a.n + p] = P.ey[k];
-            o[3 * a.n + p] = P.ez[k];
+            double* o = a.partial + (int64_t)blockIdx.y * NO * a.n;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) o[c * a.n + p] = P.acc[c][k];
+        } else if (GRAD) {
+#pragma unroll
+            for (int c = 0; c < NO; ++c) a.G[c * a.n + p] = a.K * P.acc[c][k];
         } else {
-            a.phi[p] = a.K * P.phi[k];
+            a.phi[p] = a.K * P.acc[0][k];
             if (a.E) {
-                a.E[p] = a.K * P.ex[k];
-                a.E[a.n + p] = a.K * P.ey[k];
-                a.E[2 * a.n + p] = a.K * P.ez[k];
+                a.E[p] = a.K * P.acc[1][k];
+                a.E[a.n + p] = a.K * P.acc[2][k];
+                a.E[2 * a.n + p] = a.K * P.acc[3][k];
             }
         }
     }
@@ -624,9 +702,33 @@ __device__ __forceinline__ void tri_node_vertices(const NearState& s, const doub
     }
 }
 
-template <bool COLLOC>
+// Point-charge terms of one Gaussian point at offset r from the field point (unit weight
+// w): field mode f = (w/r, w r/r^3); gradient mode f = (w/r^3, w r_i r_j / r^5 for xx, yy,
+// zz, xy, xz, yz).
+template <bool GRAD>
+__device__ __forceinline__ void leaf_terms(double w, double rx, double ry, double rz, double (&f)[7])
+{
+    const double ri = rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz)));
+    const double wr = w * ri;
+    if (!GRAD) {
+        const double w3 = wr * ri * ri;
+        f[0] += wr; f[1] = fma(w3, rx, f[1]); f[2] = fma(w3, ry, f[2]); f[3] = fma(w3, rz, f[3]);
+    } else {
+        const double ri2 = ri * ri, w3 = wr * ri2, w5 = w3 * ri2;
+        const double ux = w5 * rx, uy = w5 * ry, uz = w5 * rz;
+        f[0] += w3;
+        f[1] = fma(ux, rx, f[1]); f[2] = fma(uy, ry, f[2]); f[3] = fma(uz, rz, f[3]);
+        f[4] = fma(ux, ry, f[4]); f[5] = fma(ux, rz, f[5]); f[6] = fma(uy, rz, f[6]);
+    }
+}
+
+// MODE: kNearEval (phi, E at field points), kNearColloc (phi at centroids, several density
+// vectors), kNearGrad (field gradient at field points; NaN for a point on its element).
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
 {
+    constexpr bool COLLOC = MODE == kNearColloc;
+    constexpr bool GRAD = MODE == kNearGrad;
     const Elements& el = a.el;
     const int64_t ne = el.ne;
     const unsigned long long total = min(a.ctr->near_count, a.near_cap);
@@ -639,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     NearState st{ 0, 0, 0, 0, true };
     uint32_t p = 0, e = 0;
     double P[3] = { 0, 0, 0 }, g0[3] = { 0, 0, 0 }, g1[3] = { 0, 0, 0 }, g2[3] = { 0, 0, 0 };
-    double thr2 = 0.0, acc[4] = { 0, 0, 0, 0 };
+    double thr2 = 0.0, acc[6] = { 0, 0, 0, 0, 0, 0 };
     int64_t visits = 0;
 
     while (true) {
@@ -681,7 +783,8 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     for (int c = 0; c < 3; ++c) { g0[c] = 0.0; g1[c] = G[3 + c]; g2[c] = G[6 + c]; }
                 }
                 thr2 = el.thr2[e];
-                acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] = 0.0;
                 visits = 0;
                 active = true;
                 st.level = 0; st.i = 0; st.j = 0; st.up = true;
@@ -753,6 +856,10 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     }
                     const double inv_area = 1.0 / el.area[e];
                     acc[0] = s0 * inv_area; acc[1] = s1 * inv_area; acc[2] = s2 * inv_area; acc[3] = s3 * inv_area;
+                    if (GRAD) {  // the normal field jumps across the element: no gradient there
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc[c] = __builtin_nan("");
+                    }
                     n_on++;
                     active = false;  // finished: fall through to the write-out below
                     st.level = -1;
@@ -789,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
             if (st.level > max_level) max_level = st.level;
             if (!is_near || st.level >= a.max_depth || visits > a.visit_limit) {
                 // leaf: the element's rule on this node, weights scaled by the area ratio h^2
-                double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
+                double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
                 if (st.kind == 0) {
                     for (int i = 0; i < a.rules.nt; ++i) {
                         const double la = a.rules.tri[4 * i], lb = a.rules.tri[4 * i + 1], lc = a.rules.tri[4 * i + 2];
@@ -797,9 +904,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                         const double rx = P[0] - (la * V[0][0] + lb * V[1][0] + lc * V[2][0]);
                         const double ry = P[1] - (la * V[0][1] + lb * V[1][1] + lc * V[2][1]);
                         const double rz = P[2] - (la * V[0][2] + lb * V[1][2] + lc * V[2][2]);
-                        const double ri = rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz)));
-                        const double wr = w * ri, w3 = wr * ri * ri;
-                        f0 += wr; f1 = fma(w3, rx, f1); f2 = fma(w3, ry, f2); f3 = fma(w3, rz, f3);
+                        leaf_terms<GRAD>(w, rx, ry, rz, f);
                     }
                 } else {
                     const double hh = 0.5 * h;
@@ -809,16 +914,19 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                         const double rx = P[0] - fma(x, g1[0], fma(y, g2[0], cen[0]));
                         const double ry = P[1] - fma(x, g1[1], fma(y, g2[1], cen[1]));
                         const double rz = P[2] - fma(x, g1[2], fma(y, g2[2], cen[2]));
-                        const double ri = rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz)));
-                        const double wr = w * ri, w3 = wr * ri * ri;
-                        f0 += wr; f1 = fma(w3, rx, f1); f2 = fma(w3, ry, f2); f3 = fma(w3, rz, f3);
+                        leaf_terms<GRAD>(w, rx, ry, rz, f);
                     }
                 }
                 const double h2 = h * h;
-                acc[0] = fma(h2, f0, acc[0]);
-                acc[1] = fma(h2, f1, acc[1]);
-                acc[2] = fma(h2, f2, acc[2]);
-                acc[3] = fma(h2, f3, acc[3]);
+                if (!GRAD) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = fma(h2, f[c], acc[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] = fma(h2, fma(-3.0, f[1 + c], f[0]), acc[c]);
+#pragma unroll
+                    for (int c = 3; c < 6; ++c) acc[c] = fma(-3.0 * h2, f[1 + c], acc[c]);
+                }
                 n_leaves++;
                 if (is_near) n_cap++;
                 if (visits > a.visit_limit) {
@@ -841,6 +949,10 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     const double q = el.q[(int64_t)r * ne + e];
                     unsafeAtomicAdd(&a.phi[(int64_t)r * ne + p], K * q * acc[0]);
                 }
+            } else if (GRAD) {
+                const double q = el.q[(int64_t)a.rhs * ne + e];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&a.G[c * a.n + p], K * q * acc[c]);
             } else {
                 const double q = el.q[(int64_t)a.rhs * ne + e];
                 unsafeAtomicAdd(&a.phi[p], K * q * acc[0]);
@@ -905,13 +1017,13 @@ __global__ void zero_counters_kernel(DevCounters* c)
     if (i < (int)(sizeof(DevCounters) / sizeof(unsigned long long))) w[i] = 0ull;
 }
 
-template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT>
+template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT, bool GRAD>
 hipError_t far_eval_launch(const FarArgs& a, hipStream_t s)
 {
     const int64_t per = (int64_t)kBlock * PPT;
     const int64_t blocks = (a.n + per - 1) / per;
     if (blocks > 0x7fffffff || a.n_split < 1 || a.n_split > 65535) return hipErrorInvalidValue;
-    far_eval_kernel<DR, NT, NR, T1, T2, T3, R1, R2, R3, MIXED, PPT>
+    far_eval_kernel<DR, NT, NR, T1, T2, T3, R1, R2, R3, MIXED, PPT, GRAD>
         <<<dim3((unsigned)blocks, (unsigned)a.n_split), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
@@ -925,17 +1037,34 @@ hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
         const int* r = a.lv.rect_off;
         const bool std_levels = t[1] == 7 && t[2] == 19 && t[3] == 38 && r[1] == 7 && r[2] == 19 && r[3] == 36;
         if (std_levels && t[4] - t[3] == 33 && r[4] - r[3] == 49)
-            return far_eval_launch<true, 7, 7, 12, 19, 33, 12, 17, 49, MIXED, PPT>(a, s);
-        return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+            return far_eval_launch<true, 7, 7, 12, 19, 33, 12, 17, 49, MIXED, PPT, false>(a, s);
+        return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
     }
     const int nt = a.rules.nt, nr = a.rules.nr;
     if (nr == 49) {
-        if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
-        if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
-        if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
-        if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+        if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
+        if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
+        if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
+        if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
     }
-    return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT>(a, s);
+    return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
+}
+
+// Gradient: compile-time node counts for the default rules only.
+template <bool MIXED>
+hipError_t far_grad_dispatch(const FarArgs& a, hipStream_t s)
+{
+    constexpr int PPT = 2;
+    if (a.dr_rules) {
+        const int* t = a.lv.tri_off;
+        const int* r = a.lv.rect_off;
+        const bool std_levels = t[1] == 7 && t[2] == 19 && t[3] == 38 && r[1] == 7 && r[2] == 19 && r[3] == 36;
+        if (std_levels && t[4] - t[3] == 33 && r[4] - r[3] == 49)
+            return far_eval_launch<true, 7, 7, 12, 19, 33, 12, 17, 49, MIXED, PPT, true>(a, s);
+        return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
+    }
+    if (a.rules.nt == 33 && a.rules.nr == 49) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
+    return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
 }
 
 template <int NT, int NR, bool MIXED, int PPT>
@@ -970,12 +1099,19 @@ hipError_t launch_far_colloc(const FarArgs& a, int precision, hipStream_t s)
     return precision == 1 ? far_colloc_dispatch<true>(a, s) : far_colloc_dispatch<false>(a, s);
 }
 
-hipError_t launch_near(const NearArgs& a, bool collocation, hipStream_t s)
+hipError_t launch_far_grad(const FarArgs& a, int precision, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    return precision == 1 ? far_grad_dispatch<true>(a, s) : far_grad_dispatch<false>(a, s);
+}
+
+hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
 {
     // persistent lanes; every lane leaves once the shared cursor passes the pair count
     const int blocks = 1024;
-    if (collocation) near_kernel<true><<<blocks, kBlock, 0, s>>>(a);
-    else near_kernel<false><<<blocks, kBlock, 0, s>>>(a);
+    if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, 0, s>>>(a);
+    else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, 0, s>>>(a);
+    else near_kernel<kNearEval><<<blocks, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

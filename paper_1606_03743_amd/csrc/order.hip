@@ -91,17 +91,13 @@ __global__ void gather_kernel(const double* __restrict__ pts, int64_t n, const u
     for (int c = 0; c < 3; ++c) out[c * n + i] = pts[c * n + j];
 }
 
-__global__ void scatter_kernel(const double* __restrict__ phi_s, const double* __restrict__ E_s, int64_t n,
-                               const uint32_t* __restrict__ perm, double* __restrict__ phi, double* __restrict__ E)
+__global__ void scatter_kernel(const double* __restrict__ src, int rows, int64_t n, const uint32_t* __restrict__ perm,
+                               double* __restrict__ dst)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t j = perm[i];
-    phi[j] = phi_s[i];
-    if (E) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) E[c * n + j] = E_s[c * n + i];
-    }
+    for (int r = 0; r < rows; ++r) dst[r * n + j] = src[r * n + i];
 }
 
 }  // namespace
@@ -131,10 +127,10 @@ hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStr
     return hipGetLastError();
 }
 
-hipError_t unorder_results(const OrderWork& w, int64_t n, double* phi, double* E, hipStream_t s)
+hipError_t unorder_rows(const OrderWork& w, int64_t n, const double* src, int rows, double* dst, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    scatter_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(w.phi, w.E, n, w.perm, phi, E);
+    if (n <= 0 || rows <= 0) return hipSuccess;
+    scatter_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(src, rows, n, w.perm, dst);
     return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-// Cubature rules of the GPU library (host side; expanded once and uploaded to
-// constant memory).
+// Cubature rules of the GPU library (host side; expanded once per rule change and
+// copied to device memory as FP64 and FP32 node tables).
 //
 // Triangle rules: barycentric coordinates and weights of App. A (Tables A1-A5), one
 // entry per table row with the symmetry that row stands for (table captions):
@@ -7,7 +7,7 @@
 //   S21       (a, b, b) and the placements of the distinct value: 3 points
 //   CYCLIC    (a, b, c), (b, c, a), (c, a, b): 3 points          (Table A3 only)
 //   S111      all six permutations of (a, b, c)
-// Weights are normalised to sum 1 (Eq. 3.1).
+// Weights are the printed digits; they sum to 1 (Eq. 3.1) to the printed precision.
 //
 // Rectangle rules: tensor Gauss-Legendre n x n on the natural coordinates of Eq. 3.2,
 // weights w_i w_j / 4 (Legendre roots by Newton iteration on the three-term recurrence),

@@ -228,7 +228,7 @@ bool Server::launch(Slot& s, std::string& err)
     na.near_dr2 = env_.near_dr * env_.near_dr;
     na.max_depth = env_.max_depth;
     na.visit_limit = 1ll << 22;
-    if (e == hipSuccess) e = launch_near(na, false, s.stream);
+    if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_phi, (size_t)n * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out + n, s.d_E, (size_t)n * 3 * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);

@@ -1,0 +1,165 @@
+"""GPU parity of the field gradient dE_i/dx_j (bemc_eval_gradient, through the C ABI)
+against the FP64 oracle, on seeded inputs.
+
+Error measure per field point: max over the six components of |G - G_ref| divided by the
+oracle's abs_T, K times the sum over every point-charge term (near-field leaves included)
+of its magnitude sqrt(6) |q| / r^3.  That sum bounds the accumulated rounding of the
+evaluation; near an element the subdivision leaves' gradients cancel strongly (up to a
+few hundred times more than the element totals), so the per-element scale abs_G would
+measure cancellation rather than arithmetic.  Far from every element abs_T equals abs_G.
+Tolerances: FP64 path 1e-12, mixed path 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_03743_amd import bemc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-6}
+
+
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def gpu_gradient(ctx, pts_np, precision):
+    torch = torch_mod()
+    pts = torch.tensor(np.ascontiguousarray(pts_np.T), dtype=torch.float64, device="cuda:0")
+    G, rc = ctx.eval_gradient(pts, precision=precision)
+    torch.cuda.synchronize()
+    return G.cpu().numpy().T.copy(), rc
+
+
+def gerr(G, ref):
+    return np.abs(G - ref["G"]).max(axis=1) / ref["abs_T"]
+
+
+def make_ctx(tri, rect, sigma, tri_rule=33, rect_gl_n=7, dr=False):
+    ctx = bemc.Context(0)
+    ctx.set_rules(tri_rule, rect_gl_n)
+    ctx.set_dr_rules(dr)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(sigma)
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def cyl():
+    w = W.cylinder_workload(40, 30, 1200, n_points=3000, near_frac=0.3, seed=101)
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dr", [False, True])
+def test_gradient_cylinder(cyl, precision, dr):
+    """3,600 elements, 3,000 points (30 % within distance ratio 3 of an element)."""
+    w = cyl
+    ref = oracle.gradient(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7, dr_rules=dr))
+    ctx = make_ctx(w.tri, w.rect, w.sigma, dr=dr)
+    G, rc = gpu_gradient(ctx, w.points, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert rc == 0 and st["near_pairs"] == ref["stats"]["near_pairs"] > 0
+    assert st["leaves"] == ref["stats"]["leaves"]
+    e = gerr(G, ref)
+    print(f"gradient {precision} dr={dr}: max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() <= TOL[precision]
+    if precision == "mixed":
+        assert e.max() > 1e-12  # the FP32 path really ran
+    # trace-free off the electrodes, at the precision's level
+    tr = np.abs(G[:, 0] + G[:, 1] + G[:, 2]) / ref["abs_T"]
+    assert tr.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 513])
+def test_gradient_ragged(cyl, n):
+    w = cyl
+    pts = w.points[:n]
+    ref = oracle.gradient(w.tri, w.rect, w.sigma[0], pts, oracle.params(33, 7))
+    ctx = make_ctx(w.tri, w.rect, w.sigma)
+    G, _ = gpu_gradient(ctx, pts, "fp64")
+    ctx.close()
+    assert gerr(G, ref).max() <= TOL["fp64"]
+
+
+def test_gradient_unsplit_launch():
+    """Fewer than 128 elements: one element chunk (no partial-sum reduction)."""
+    rng = np.random.default_rng(5)
+    tri = W.icosphere(1, 1.0)
+    sig = rng.standard_normal(tri.shape[0])
+    pts = np.concatenate([W.shell_points(200, 1.05, 5.0, rng), rng.uniform(-0.5, 0.5, (50, 3))])
+    ref = oracle.gradient(tri, None, sig, pts, oracle.params(7, 7))
+    ctx = make_ctx(tri, None, sig, tri_rule=7)
+    G, _ = gpu_gradient(ctx, pts, "fp64")
+    ctx.close()
+    assert ref["stats"]["near_pairs"] > 0
+    assert gerr(G, ref).max() <= TOL["fp64"]
+
+
+def test_gradient_on_element_is_nan():
+    w = W.cylinder_workload(40, 30, 1200, n_points=200, near_frac=0.5, seed=9)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, w.n_elements, 20)
+    on, _, _ = W.points_on_elements(w.tri, w.rect, idx, rng)
+    pts = np.concatenate([w.points, on])
+    ref = oracle.gradient(w.tri, w.rect, w.sigma[0], pts, oracle.params())
+    ctx = make_ctx(w.tri, w.rect, w.sigma)
+    G, rc = gpu_gradient(ctx, pts, "fp64")
+    ctx.close()
+    assert rc == bemc.W_ON_SURFACE
+    bad = np.isnan(ref["G"]).any(axis=1)
+    assert bad[200:].all() and not bad[:200].any()
+    assert np.array_equal(np.isnan(G), np.isnan(ref["G"]))
+    assert gerr(G[~bad], {"G": ref["G"][~bad], "abs_T": ref["abs_T"][~bad]}).max() <= TOL["fp64"]
+
+
+def test_gradient_errors():
+    torch = torch_mod()
+    w = W.cylinder_workload(40, 30, 1200, n_points=10, seed=9)
+    ctx = bemc.Context(0)
+    pts = torch.zeros((3, 4), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.eval_gradient(pts)
+    assert ei.value.code == bemc.E_NO_GEOMETRY
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.eval_gradient(pts, rhs=1)
+    assert ei.value.code == bemc.E_INVALID_ARG
+    G, rc = ctx.eval_gradient(torch.zeros((3, 0), dtype=torch.float64, device="cuda:0"))
+    assert rc == 0 and G.shape == (6, 0)
+    ctx.close()
+
+
+def test_gradient_full_size_sampled():
+    """150,000 elements and 1,000,000 points in the benchmark's launch configuration; the
+    oracle checks a sample of far and near points, trace-freeness checks every point."""
+    torch = torch_mod()
+    w = W.cylinder_150k()
+    ctx = make_ctx(w.tri, w.rect, w.sigma)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        G, rc = ctx.eval_gradient(pts, precision=prec)
+        torch.cuda.synchronize()
+        res[prec] = (G.cpu().numpy().T.copy(), ctx.stats())
+    ctx.close()
+    rng = np.random.default_rng(44)
+    isn = w.info["is_near"]
+    idx = np.concatenate([rng.choice(np.nonzero(~isn)[0], 48, replace=False),
+                          rng.choice(np.nonzero(isn)[0], 48, replace=False)])
+    ref = oracle.gradient(w.tri, w.rect, w.sigma[0], w.points[idx], oracle.params(33, 7))
+    for prec in ("fp64", "mixed"):
+        G, st = res[prec]
+        e = gerr(G[idx], ref)
+        print(f"gradient full-size {prec}: max {e.max():.2e}; far {st['far_ms']:.1f} ms near {st['near_ms']:.1f} ms")
+        assert e.max() <= TOL[prec]
+        assert np.all(np.isfinite(G))
+        if prec == "fp64":
+            scale = np.abs(G).max(axis=1)
+            assert np.all(np.abs(G[:, 0] + G[:, 1] + G[:, 2]) <= 1e-6 * scale)
