@@ -57,14 +57,15 @@ def traffic_from_profile():
     return float(b.group(1))
 
 
-def counted_flops_from_profile():
-    """Hardware FP64 flops per far-kernel launch from the committed VALU counter summary
-    (64 x (2 FMA + MUL + ADD + TRANS)), or None when the kernel changed since."""
+def counted_flops_from_profile(key="counted_fp64_flops_per_launch"):
+    """Hardware flops per far-kernel launch from the committed VALU counter summary
+    (64 x (2 FMA + MUL + ADD + TRANS) of the FP64 kernel's FP64 instructions, or of the
+    mixed kernel's FP32 instructions), or None when the kernel changed since."""
     if not os.path.exists(VALU_FILE):
         return None
     txt = open(VALU_FILE).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    b = re.search(r"counted_fp64_flops_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(key + r":\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash():
         return None
     return float(b.group(1))
@@ -126,7 +127,10 @@ def main():
         del src, dst
         ctx.eval(pts, "fp64", phi=phi, E=E)
         torch.cuda.synchronize()
-        log(f"profile run done: {ctx.stats()}")
+        log(f"profile run: FP64 evaluation done: {ctx.stats()}")
+        ctx.eval(pts, "mixed", phi=phi, E=E)
+        torch.cuda.synchronize()
+        log(f"profile run: mixed evaluation done: {ctx.stats()}")
         return
 
     def timed(precision, steps, warmup):
@@ -207,10 +211,14 @@ def main():
                  "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},
     }
     mixed_ach = alg_flops / (1e-3 * float(np.mean(farmx))) / 1e12
+    counted32 = counted_flops_from_profile("counted_fp32_flops_per_launch_mixed")
+    c32 = None if counted32 is None else counted32 / (1e-3 * float(np.mean(farmx))) / 1e12
     out["mixed"] = {"value": pairs * args.steps / dtmx, "unit": "pairs/s", "ms_per_step": 1e3 * dtmx / args.steps,
                     "speedup_vs_fp64": dt64 / dtmx, "far_kernel_ms": float(np.mean(farmx)),
                     "roofline": {"bound": "alu", "achieved": mixed_ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                                 "frac": mixed_ach / PEAK_FP32_TFLOPS}}
+                                 "frac": mixed_ach / PEAK_FP32_TFLOPS,
+                                 "counted_fp32_tflops": c32,
+                                 "counted_frac": None if c32 is None else c32 / PEAK_FP32_TFLOPS}}
 
     g_flops = GRAD_FLOP_PER_NODE_INT * node_int + FLOP_PER_PAIR * pairs
     for prec, peak in (("fp64", PEAK_FP64_TFLOPS), ("mixed", PEAK_FP32_TFLOPS)):
