@@ -306,7 +306,12 @@ def main():
         out["solver"] = solver_bench(torch, bemc, W)
 
         if args.serving_queries > 0:
-            out["serving"] = serving(args.serving_queries, torch, bemc, W)
+            # one stream for long batches, one for queries of <= 4096 points; fixed rules,
+            # then the rule choice by distance ratio on the same stream of queries
+            g = W.serving_geometry()
+            policy = dict(max_batch_points=1 << 16, small_query_points=4096, n_streams=2)
+            out["serving"] = serving(args.serving_queries, torch, bemc, W, g=g, **policy)
+            out["serving_dr"] = serving(args.serving_queries, torch, bemc, W, g=g, dr=True, **policy)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -339,19 +344,23 @@ def solver_bench(torch, bemc, W):
     return res
 
 
-def serving(n_queries, torch, bemc, W):
+def serving(n_queries, torch, bemc, W, g=None, dr=False, small_query_points=4096, max_batch_points=1 << 16,
+            n_streams=2):
     """Open-loop Poisson arrivals on the 1,000,000-element cylinder: saturation rate from a
     burst, then arrivals at 0.7 x that rate; latency = arrival -> results in host memory."""
-    log(f"serving: 1,000,000-element cylinder, {n_queries} queries")
-    g = W.serving_geometry()
+    log(f"serving: 1,000,000-element cylinder, {n_queries} queries, rule choice by DR {dr}, "
+        f"short-query class {small_query_points}, batch {max_batch_points}, {n_streams} streams")
+    g = g or W.serving_geometry()
     ctx = bemc.Context(0)
+    ctx.set_dr_rules(dr)
     ctx.upload_geometry(g.tri, g.rect)
     ctx.upload_densities(g.sigma)
     sizes = W.serving_query_sizes(20_000)[:n_queries]
     qpts = [np.ascontiguousarray(W.serving_query(i, s)) for i, s in enumerate(sizes)]
     phis = [np.empty(s) for s in sizes]
     Es = [np.empty((s, 3)) for s in sizes]
-    ctx.server_start(mem_budget_bytes=16 << 30, max_batch_points=1 << 17, n_streams=3, precision="mixed")
+    ctx.server_start(mem_budget_bytes=16 << 30, max_batch_points=max_batch_points, n_streams=n_streams,
+                     precision="mixed", small_query_points=small_query_points)
     # warm-up and saturation rate (all queries at once)
     t0 = time.perf_counter()
     tickets = [ctx.server_submit(qpts[i], phis[i], Es[i]) for i in range(n_queries)]
@@ -377,8 +386,13 @@ def serving(n_queries, torch, bemc, W):
     pairs = int(np.sum(sizes)) * g.n_elements
     lat = np.array(lat)
     log(f"serving open loop: p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+    lat_small = lat[np.array(sizes) <= max(small_query_points, 4096)]
     return {"workload": g.name, "queries": int(n_queries), "points": int(np.sum(sizes)),
             "precision": "mixed far field, FP64 near field",
+            "rules": "by distance ratio" if dr else "33-point triangles, 7x7 rectangles",
+            "policy": {"max_batch_points": max_batch_points, "streams": n_streams,
+                       "short_query_class_points": small_query_points},
+            "p50_ms_queries_le_4096_points": float(np.percentile(lat_small, 50)),
             "saturation_queries_per_s": sat_rate, "arrival_rate_queries_per_s": rate,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "pairs_per_s": pairs / total, "wall_s": total,

@@ -202,7 +202,8 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
 
 /* ---------------------------------------------------------------------------------
  * Serving: continuous batching of field-point queries against the resident geometry
- * and densities (density vector 0), mixed or FP64 precision.
+ * and densities (density vector 0), mixed or FP64 precision, with the rules of the
+ * context (including the distance-ratio rule choice when enabled).
  *
  * bemc_server_start launches a host scheduler thread that owns `n_streams` HIP streams
  * (default priority).  Submitted queries wait in arrival order; whenever a stream is
@@ -211,9 +212,12 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
  * field launch over all their points, element-split when the batch is small so the GPU
  * stays full; fixed-order reduction of the element chunks; then the FP64 near field)
  * and copies each query's results to its host buffers when the batch completes.
- * Batches on different streams overlap on the device.  A query's result does not
- * depend on the other queries in its batch beyond the order of floating-point atomic
- * additions in the near field.
+ * Batches on different streams overlap on the device.  With small_query_points > 0 and
+ * at least two streams, queries of at most that many points wait in a queue of their
+ * own, and one stream serves only that queue, so that short queries do not wait behind
+ * long batches; the other streams take the long queue first and the short one when the
+ * long one is empty.  A query's result does not depend on the other queries in its
+ * batch beyond the order of floating-point atomic additions in the near field.
  * --------------------------------------------------------------------------------- */
 
 typedef struct {
@@ -221,6 +225,8 @@ typedef struct {
     int64_t max_batch_points;  /* points per batch (>= the largest admissible query) */
     int n_streams;             /* 1..8 concurrent batches */
     int precision;             /* BEMC_FP64 or BEMC_MIXED */
+    int64_t small_query_points; /* > 0: queries of at most this many points form their own
+                                   class with a stream of their own; 0: one class */
 } bemc_server_config;
 
 typedef struct {

@@ -57,7 +57,8 @@ class SolveInfo(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_size_t), ("max_batch_points", ctypes.c_int64),
-                ("n_streams", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("n_streams", ctypes.c_int), ("precision", ctypes.c_int),
+                ("small_query_points", ctypes.c_int64)]
 
 
 class QueryInfo(ctypes.Structure):
@@ -261,8 +262,9 @@ class Context:
         return {f: getattr(st, f) for f, _ in Stats._fields_}
 
     # -- serving
-    def server_start(self, mem_budget_bytes=8 << 30, max_batch_points=1 << 17, n_streams=4, precision="mixed"):
-        cfg = ServerConfig(mem_budget_bytes, max_batch_points, n_streams, _PREC[precision])
+    def server_start(self, mem_budget_bytes=8 << 30, max_batch_points=1 << 17, n_streams=4, precision="mixed",
+                     small_query_points=0):
+        cfg = ServerConfig(mem_budget_bytes, max_batch_points, n_streams, _PREC[precision], small_query_points)
         _check(self.lib.bemc_server_start(self.h, ctypes.byref(cfg)))
 
     def server_submit(self, pts_host, phi_host, E_host=None):

@@ -1,11 +1,12 @@
 // Continuous-batching query server.
 //
 // Geometry and densities stay resident; each free stream slot takes the longest prefix of
-// the waiting queue (arrival order) whose points fit into one batch, runs one far-field
+// a waiting queue (arrival order) whose points fit into one batch, runs one far-field
 // launch over all of them (split over element chunks when the batch is small, with a
 // fixed-order reduction of the chunks), the FP64 near field, and copies the results back.
 // Slots on different streams overlap on the device; queries arriving while batches run
-// are admitted as soon as a slot is free.
+// are admitted as soon as a slot is free.  Optionally short queries have a queue and a
+// slot of their own (the other slots take them only when no long query waits).
 #include "server.h"
 
 #include <algorithm>
@@ -15,7 +16,11 @@
 namespace bemc {
 
 namespace {
-constexpr int kWavesTarget = 2048;  // workgroups that keep all 256 CUs busy
+// Workgroups per far-field launch: many times the resident capacity, so that every
+// workgroup is short and a batch on another stream gets compute units within a few ms.
+constexpr int kWavesTarget = 16 * 1024;
+constexpr int kMaxServeSplit = 1024;  // element chunks of one serving launch
+constexpr int kSlotSplit = 256;       // partial-sum rows of a slot: kSlotSplit x max_batch_points
 constexpr int kPointsPerBlock = 512;
 }  // namespace
 
@@ -43,13 +48,13 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
     t0_ = 0.0;
     t0_ = now();
     if (cfg.max_batch_points < 1 || cfg.max_batch_points >= (1ll << 31) || cfg.n_streams < 1 || cfg.n_streams > 8 ||
-        (cfg.precision != BEMC_FP64 && cfg.precision != BEMC_MIXED)) {
+        (cfg.precision != BEMC_FP64 && cfg.precision != BEMC_MIXED) || cfg.small_query_points < 0) {
         err = "invalid server configuration";
         return false;
     }
     const int64_t M = cfg.max_batch_points;
     const int64_t blocks = (M + kPointsPerBlock - 1) / kPointsPerBlock;
-    max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(64, kWavesTarget / std::max<int64_t>(1, blocks / 16)));
+    max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(kSlotSplit, kWavesTarget / std::max<int64_t>(1, blocks)));
     const unsigned long long near0 = (unsigned long long)std::max<int64_t>(1 << 16, 16 * M);
     const size_t slot_bytes = (size_t)M * 8 * (3 + 1 + 3 + 4 * (size_t)max_split_) + near0 * sizeof(NearPair) + 4096;
     int n_slots = (int)std::min<size_t>((size_t)cfg.n_streams, cfg.mem_budget_bytes / slot_bytes);
@@ -78,6 +83,7 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
         }
         s.near_cap = near0;
     }
+    if (cfg.small_query_points > 0 && slots_.size() >= 2) slots_.back().small_only = true;
     thread_ = std::thread([this] { loop(); });
     return true;
 }
@@ -109,8 +115,9 @@ int Server::submit(const double* pts, int64_t n, double* phi, double* E, uint64_
     q.E = E;
     q.info.submit_s = now();
     q.info.batch_id = -1;
+    q.small = cfg_.small_query_points > 0 && n <= cfg_.small_query_points;
     queries_.emplace(q.id, q);
-    waiting_.push_back(q.id);
+    (q.small ? waiting_small_ : waiting_).push_back(q.id);
     *ticket = q.id;
     cv_.notify_one();
     return BEMC_OK;
@@ -184,7 +191,13 @@ bool Server::launch(Slot& s, std::string& err)
         off += q.n;
     }
     const int64_t blocks = (n + kPointsPerBlock - 1) / kPointsPerBlock;
-    const int n_split = (int)std::max<int64_t>(1, std::min<int64_t>(max_split_, kWavesTarget / blocks));
+    // Element chunks: enough workgroups to fill the chip, and short ones for a small batch
+    // so that it finishes soon even while long batches hold most of the compute units;
+    // bounded by the partial-sum buffer (max_split_ x max_batch_points rows of 4) and by
+    // chunks of at least 64 elements.
+    const int64_t cap = (int64_t)max_split_ * cfg_.max_batch_points / std::max<int64_t>(1, n);
+    const int n_split = (int)std::max<int64_t>(
+        1, std::min({ kWavesTarget / blocks, cap, env_.el.ne / 64, (int64_t)kMaxServeSplit }));
     const int64_t ne = env_.el.ne;
     const int64_t chunk = (ne + n_split - 1) / n_split;
     const double K = coulomb_constant();
@@ -328,17 +341,19 @@ void Server::loop()
                 progressed = true;
             }
         }
-        // admissions: each free slot takes the longest prefix of the queue that fits
+        // admissions: each free slot takes the longest prefix of its queue that fits
         for (auto& s : slots_) {
-            if (s.busy || waiting_.empty()) continue;
+            if (s.busy) continue;
+            std::deque<uint64_t>* wq = s.small_only ? &waiting_small_ : (waiting_.empty() ? &waiting_small_ : &waiting_);
+            if (wq->empty()) continue;
             int64_t pts = 0;
             s.queries.clear();
-            while (!waiting_.empty()) {
-                Query& q = queries_[waiting_.front()];
+            while (!wq->empty()) {
+                Query& q = queries_[wq->front()];
                 if (pts + q.n > cfg_.max_batch_points) break;
                 pts += q.n;
                 s.queries.push_back(q.id);
-                waiting_.pop_front();
+                wq->pop_front();
             }
             if (s.queries.empty()) continue;
             s.n = pts;
@@ -376,7 +391,7 @@ void Server::loop()
         }
         bool any_busy = false;
         for (auto& s : slots_) any_busy |= s.busy;
-        if (stopping_ && waiting_.empty() && !any_busy) break;
+        if (stopping_ && waiting_.empty() && waiting_small_.empty() && !any_busy) break;
         if (!progressed) cv_.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 2000));
     }
 }

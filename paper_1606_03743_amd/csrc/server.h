@@ -43,6 +43,7 @@ private:
         int64_t n;
         double* phi;
         double* E;
+        bool small;
         bemc_query_info info;
     };
     struct Slot {
@@ -54,6 +55,7 @@ private:
         unsigned long long near_cap = 0;
         DevCounters *d_ctr = nullptr, *h_ctr = nullptr;
         bool busy = false;
+        bool small_only = false;  // serves the short-query class only
         int64_t batch_id = -1;
         int64_t n = 0;
         std::vector<uint64_t> queries;
@@ -73,7 +75,8 @@ private:
     std::mutex mu_;
     std::condition_variable cv_;       // scheduler wake-up
     std::condition_variable done_cv_;  // query completion
-    std::deque<uint64_t> waiting_;
+    std::deque<uint64_t> waiting_;        // long queries (all queries with one class)
+    std::deque<uint64_t> waiting_small_;  // short queries (small_query_points > 0)
     std::unordered_map<uint64_t, Query> queries_;
     uint64_t next_id_ = 1;
     int64_t next_batch_ = 0;

@@ -30,12 +30,13 @@ def setup():
     return w, queries
 
 
-def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096, dr=False):
+def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096, dr=False, small=0):
     ctx = bemc.Context(0)
     ctx.set_dr_rules(dr)
     ctx.upload_geometry(w.tri, w.rect)
     ctx.upload_densities(w.sigma)
-    ctx.server_start(mem_budget_bytes=2 << 30, max_batch_points=max_batch, n_streams=n_streams, precision=precision)
+    ctx.server_start(mem_budget_bytes=2 << 30, max_batch_points=max_batch, n_streams=n_streams, precision=precision,
+                     small_query_points=small)
     phis = [np.full(len(q), np.nan) for q in queries]
     Es = [np.full((len(q), 3), np.nan) for q in queries]
     infos = []
@@ -51,14 +52,20 @@ def run_server(w, queries, precision, alone, n_streams=3, max_batch=4096, dr=Fal
     return phis, Es, infos
 
 
-@pytest.mark.parametrize("precision,tol,dr", [("fp64", 1e-12, False), ("mixed", 1e-6, False), ("mixed", 1e-6, True)])
-def test_alone_equals_mix_and_oracle(setup, precision, tol, dr):
+@pytest.mark.parametrize("precision,tol,dr,small", [("fp64", 1e-12, False, 0), ("mixed", 1e-6, False, 0),
+                                                   ("mixed", 1e-6, True, 0), ("fp64", 1e-12, False, 128)])
+def test_alone_equals_mix_and_oracle(setup, precision, tol, dr, small):
+    """small > 0: short queries (<= small points) have a queue and a stream of their own."""
     w, queries = setup
-    pa, Ea, ia = run_server(w, queries, precision, alone=True, dr=dr)
-    pm, Em, im = run_server(w, queries, precision, alone=False, dr=dr)
+    pa, Ea, ia = run_server(w, queries, precision, alone=True, dr=dr, small=small)
+    pm, Em, im = run_server(w, queries, precision, alone=False, dr=dr, small=small)
     assert all(i["done"] == 1 and i["status"] == 0 for i in ia + im)
     # in the mix, several queries shared a batch
     assert len({i["batch_id"] for i in im}) < len(queries)
+    if small:  # short and long queries never share a batch
+        for b in {i["batch_id"] for i in im}:
+            kinds = {len(q) <= small for q, i in zip(queries, im) if i["batch_id"] == b}
+            assert len(kinds) == 1
     allp = np.concatenate(queries)
     ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], allp, oracle.params(33, 7), with_abs=True)
     off = 0
