@@ -112,10 +112,13 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_rule, double near_dr, i
  * uses Tables B2 / B3 / B4 for DR >= rect_dr[0..2], else the rectangle rule.  NULL
  * arrays select the defaults {100, 25, 10} and {150, 40, 15} (the paper's triangle
  * potential limits x 1.25; the rectangle tables' field-accuracy limits).  bemc_eval then
- * orders the field points along a Morton curve internally so that neighbouring lanes
- * choose the same rule; results are returned in the caller's order.  Near pairs and
- * collocation are unaffected.  Errors: INVALID_ARG (limits not decreasing or below
- * near_dr). */
+ * orders the field points along a Morton curve internally, and for each element a
+ * wavefront of 128 neighbouring points uses the finest of the rules its pairs need (never
+ * a coarser rule than a pair's own distance ratio asks for); results are returned in the
+ * caller's order.  Near pairs and collocation are unaffected.  The rules of
+ * bemc_set_rules must be at least as fine as the third level (>= 19 triangle points,
+ * >= 17 rectangle points) while this is enabled.  Errors: INVALID_ARG (limits not
+ * decreasing or below near_dr; rules too coarse). */
 int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const double* rect_dr);
 
 /* Upload the electrode geometry (host arrays in the element input format; either count

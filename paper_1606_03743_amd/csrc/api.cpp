@@ -445,6 +445,10 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
         std::vector<RectNode> rn;
         if (rect_gl_n == 0 || rect_gl_n > 16 || (rect_gl_n < 0 && !rectangle_table_rule(-rect_gl_n, rn)))
             return fail(BEMC_E_INVALID_ARG, "rectangle rule must be 1..16 (Gauss n x n) or -4/-7/-12/-17/-33 (Table B)");
+        const int nr = rect_gl_n > 0 ? rect_gl_n * rect_gl_n : (int)rn.size();
+        if (h->dr_rules && ((int)t.size() < kMinDrTriNodes || nr < kMinDrRectNodes))
+            return fail(BEMC_E_INVALID_ARG, "with the rule choice by distance ratio enabled, the rules must have at "
+                        "least %d (triangle) and %d (rectangle) points", kMinDrTriNodes, kMinDrRectNodes);
     }
     const int old_t = h->tri_rule, old_r = h->rect_gl_n;
     h->tri_rule = tri_rule;
@@ -677,6 +681,12 @@ int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const dou
     for (const double* v : { t, r })
         if (!(v[0] >= v[1] && v[1] >= v[2] && v[2] >= h->near_dr) || !std::isfinite(v[0]))
             return fail(BEMC_E_INVALID_ARG, "limits must be finite, decreasing and >= near_dr");
+    // the levels must get finer in order: a wavefront runs the finest level one of its
+    // pairs needs, which must then be at least as accurate as every lane's own choice
+    if (enable && (h->nt < kMinDrTriNodes || h->nr < kMinDrRectNodes))
+        return fail(BEMC_E_INVALID_ARG, "the rule choice by distance ratio needs rules of at least %d (triangle) "
+                    "and %d (rectangle) points, finer than its 19-point and Table B4 levels", kMinDrTriNodes,
+                    kMinDrRectNodes);
     h->dr_rules = enable != 0;
     std::copy(t, t + 3, h->tri_dr);
     std::copy(r, r + 3, h->rect_dr);

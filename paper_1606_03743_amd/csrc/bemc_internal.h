@@ -26,6 +26,10 @@ bool rectangle_table_rule(int n, std::vector<RectNode>& out);
 constexpr int kMaxTriNodes = 64;
 constexpr int kMaxRectNodes = 256;
 constexpr int kMaxRhs = 8;
+// rule choice by distance ratio: the last level (the context's rules) must be at least as
+// fine as the third level (19-point triangle rule, Table B4)
+constexpr int kMinDrTriNodes = 19;
+constexpr int kMinDrRectNodes = 17;
 
 // ------------------------------------------------------------------ device data
 // Rule tables in device memory: triangle nodes as (la, lb, lc, w), rectangle nodes as

@@ -1,12 +1,13 @@
 // HIP kernels for gfx950 (MI355X): Gaussian-cubature potential and field of charged
 // BEM triangles and rectangles (Glueck & Hilk, arXiv:1606.03743).
 //
-//  far_eval_kernel     one field point per lane and PPT points per lane; element tiles are
-//                      staged in LDS with their Gaussian points generated on the fly from
-//                      the centroid offsets (Eq. 3.2 / 3.3); FP64 distance-ratio test per
-//                      pair (Sec. 2), near pairs compacted per wavefront into a dense list;
-//                      far pairs summed as point charges (Sec. 4, Eq. 4.1), potential and
-//                      field from the same nodes.  FP64 or mixed (FP32 node sums).
+//  far_eval_kernel     PPT field points per lane; element tiles are staged in LDS with
+//                      their Gaussian points generated on the fly from the centroid offsets
+//                      (Eq. 3.2 / 3.3); FP64 distance-ratio test per pair (Sec. 2), near
+//                      pairs compacted per wavefront into a dense list; far pairs summed as
+//                      point charges (Sec. 4, Eq. 4.1), potential and field from the same
+//                      nodes.  FP64 or mixed (FP32 node sums); one rule per element kind or
+//                      the rule chosen by distance ratio; field or field gradient.
 //  far_colloc_kernel   the same sum, potential only, at element centroids, for up to eight
 //                      density vectors (matrix-free collocation product).
 //  near_kernel         FP64 near field over the dense list: each lane walks the recursive
@@ -352,31 +353,12 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
     }
 }
 
-// One level of the distance-ratio rule choice: the wavefront runs the level's nodes only
-// if one of its lanes needs it; lanes whose points took another level discard the result.
-template <int NN, bool MIXED, int PPT, bool GRAD, typename Lds>
-__device__ __forceinline__ void level_sum(const Lds& s, int base, int n, int lv, const int (&lvl)[PPT],
-                                          const double (&dx)[PPT], const double (&dy)[PPT], const double (&dz)[PPT],
-                                          double (&o)[Sums<GRAD>::kNode][PPT], unsigned long long& terms)
-{
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) any |= (lvl[k] == lv);
-    if (__ballot(any) == 0ull) return;
-    double t[Sums<GRAD>::kNode][PPT];
-    element_sum<NN, MIXED, PPT, GRAD>(s, base, n, dx, dy, dz, t);
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-        if (lvl[k] == lv) {
-#pragma unroll
-            for (int c = 0; c < Sums<GRAD>::kNode; ++c) o[c][k] = t[c][k];
-            terms += (unsigned)n;
-        }
-}
-
-// One element kind with the rule chosen per pair by distance ratio (Sec. 4): the staged
-// nodes of an element are the four levels back to back; level l is used when
-// D^2 >= c[l] (near_dr L)^2, the last level otherwise.  N0..N3 > 0: compile-time counts.
+// One element kind with the rule chosen by distance ratio (Sec. 4): the staged nodes of an
+// element are the four levels back to back; a pair needs level l when D^2 >= c[l] (near_dr
+// L)^2 (the last level otherwise).  The wavefront runs the finest level that any of its
+// pairs needs, once, for all its lanes: a finer rule is at least as accurate at a larger
+// distance ratio, and one level per wavefront costs less than each level a lane needs.
+// N0..N3 > 0: compile-time counts.
 template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, bool GRAD, typename Lds>
 __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, GRAD>& P, int64_t e_begin,
                                                   int64_t e_end, unsigned long long& terms)
@@ -407,18 +389,25 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
                 lvl[k] = D2 >= c0 * thr2 ? 0 : (D2 >= c1 * thr2 ? 1 : (D2 >= c2 * thr2 ? 2 : 3));
                 if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
             }
+            // the finest level any lane of the wavefront needs
+            int mx = -1;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) mx = max(mx, lvl[k]);
+            const int wl = __ballot(mx >= 3) ? 3 : (__ballot(mx >= 2) ? 2 : (__ballot(mx >= 1) ? 1 : (__ballot(mx >= 0) ? 0 : -1)));
+            if (wl < 0) continue;
             double o[Sums<GRAD>::kNode][PPT];
-#pragma unroll
-            for (int cc = 0; cc < Sums<GRAD>::kNode; ++cc)
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) o[cc][k] = 0.0;
             const int b = j * nn;
-            level_sum<N0, MIXED, PPT, GRAD>(s, b, o1, 0, lvl, dx, dy, dz, o, terms);
-            level_sum<N1, MIXED, PPT, GRAD>(s, b + o1, o2 - o1, 1, lvl, dx, dy, dz, o, terms);
-            level_sum<N2, MIXED, PPT, GRAD>(s, b + o2, o3 - o2, 2, lvl, dx, dy, dz, o, terms);
-            level_sum<N3, MIXED, PPT, GRAD>(s, b + o3, nn - o3, 3, lvl, dx, dy, dz, o, terms);
+            int nw;
+            if (wl == 0) { element_sum<N0, MIXED, PPT, GRAD>(s, b, o1, dx, dy, dz, o); nw = o1; }
+            else if (wl == 1) { element_sum<N1, MIXED, PPT, GRAD>(s, b + o1, o2 - o1, dx, dy, dz, o); nw = o2 - o1; }
+            else if (wl == 2) { element_sum<N2, MIXED, PPT, GRAD>(s, b + o2, o3 - o2, dx, dy, dz, o); nw = o3 - o2; }
+            else { element_sum<N3, MIXED, PPT, GRAD>(s, b + o3, nn - o3, dx, dy, dz, o); nw = nn - o3; }
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) add_element<PPT, GRAD>(P, k, q, o);
+            for (int k = 0; k < PPT; ++k)
+                if (lvl[k] >= 0) {
+                    add_element<PPT, GRAD>(P, k, q, o);
+                    terms += (unsigned)nw;
+                }
         }
     }
 }

@@ -97,6 +97,27 @@ def test_cylinder_with_near_field(cyl, precision):
     assert abs(st["leaves"] - ref["stats"]["leaves"]) <= 0.001 * ref["stats"]["leaves"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_uniform_density_plain_relative_error(cyl, precision):
+    """sigma = 1 everywhere: no cancellation between elements, so the paper's plain relative
+    error of the potential (Sec. 2) is well conditioned and gated directly; the field is
+    gated by its norm against the sum of per-element field magnitudes as above."""
+    w, _ = cyl
+    ones = np.ones(w.n_elements)
+    ref = oracle.evaluate(w.tri, w.rect, ones, w.points, oracle.params(33, 7), with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(ones)
+    phi, E, _ = run_gpu(ctx, w.points, precision)
+    ctx.close()
+    rel = np.abs(phi - ref["phi"]) / np.abs(ref["phi"])
+    print(f"sigma=1 {precision}: plain relative phi max {rel.max():.2e} median {np.median(rel):.2e}")
+    assert rel.max() <= TOL[precision]
+    assert np.allclose(ref["phi"], ref["abs_phi"])  # all contributions positive
+    _, ee = nerr(phi, E, ref)
+    assert ee.max() <= TOL[precision]
+
+
 @pytest.mark.parametrize("n", [1, 2, 255, 511, 513, 1025])
 def test_ragged_point_counts(cyl, n):
     w, ref = cyl
@@ -294,6 +315,33 @@ def test_dr_rules_parity(cyl, precision):
           f"vs {fixed_terms:.3e} fixed")
     assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
     ep, ee = nerr(phi, E, ref_fixed)  # the coarser rules stay at the fixed rules' accuracy
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dr_rules_custom_limits_and_rules(precision):
+    """Other limits and other finest rules (19-point triangles, Table B4 rectangles): the
+    run-time node-count kernel, checked against the oracle with the same settings.  Rules
+    coarser than the third level are rejected while the rule choice is on."""
+    w = W.cylinder_workload(40, 30, 1200, n_points=1500, near_frac=0.3, seed=23)
+    tri_dr, rect_dr = (60.0, 20.0, 8.0), (90.0, 30.0, 10.0)
+    prm = oracle.params(19, rect_gl_n=0, rect_table_n=17, dr_rules=True, tri_dr=tri_dr, rect_dr=rect_dr)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, prm, with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.set_rules(19, -17)
+    ctx.set_dr_rules(True, tri_dr, rect_dr)
+    with pytest.raises(bemc.BemcError):
+        ctx.set_rules(12, -17)
+    with pytest.raises(bemc.BemcError):
+        ctx.set_rules(19, -12)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    phi, E, _ = run_gpu(ctx, w.points, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert st["near_pairs"] == ref["stats"]["near_pairs"] and st["leaves"] == ref["stats"]["leaves"]
+    ep, ee = nerr(phi, E, ref)
+    print(f"dr custom {precision}: phi {ep.max():.2e} E {ee.max():.2e}")
     assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
 
 
