@@ -157,6 +157,27 @@ struct PointSet {
     double acc[Sums<GRAD>::kOut][PPT];
 };
 
+// Runs term(i) for the nodes i = 0 .. n-1 of one element.  Long rules (and run-time
+// counts) go in groups of four with a separate remainder: this keeps the accumulators in
+// place, where an unrolled loop with a remainder makes the compiler copy them every
+// iteration.  The short rules of the distance-ratio levels use a plain unrolled loop.
+template <int NN, typename Term>
+__device__ __forceinline__ void for_nodes(int n, Term term)
+{
+    if (NN > 0 && NN < 32) {
+#pragma unroll 4
+        for (int i = 0; i < n; ++i) term(i);
+        return;
+    }
+    int i = 0;
+#pragma unroll 1
+    for (; i + 4 <= n; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(i + u);
+    }
+    for (; i < n; ++i) term(i);
+}
+
 // Terms of one Gaussian point Q (offset and weight) for PPT field points.
 template <int PPT, bool GRAD>
 __device__ __forceinline__ void node_term64(const double4 Q, const double (&dx)[PPT], const double (&dy)[PPT],
@@ -204,20 +225,7 @@ __device__ __forceinline__ void node_sum64(const double4* __restrict__ nd, int n
     for (int c = 0; c < Sums<GRAD>::kNode; ++c)
 #pragma unroll
         for (int k = 0; k < PPT; ++k) o[c][k] = 0.0;
-    // Long rules: groups of four nodes, then the remainder.  This keeps the accumulators in
-    // place; an unrolled loop with a remainder makes the compiler copy them every iteration.
-    if (NN > 0 && NN < 32) {  // the short rules of the distance-ratio levels
-#pragma unroll 4
-        for (int i = 0; i < n; ++i) node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o);
-        return;
-    }
-    int i = 0;
-#pragma unroll 1
-    for (; i + 4 <= n; i += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) node_term64<PPT, GRAD>(nd[i + u], dx, dy, dz, o);
-    }
-    for (; i < n; ++i) node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o);
+    for_nodes<NN>(n, [&](int i) { node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o); });
 }
 
 // FP32 versions.  The gradient uses unit vectors (d / r) so that no power of 1/r above the
@@ -262,18 +270,7 @@ __device__ __forceinline__ void node_sum32(const float4* __restrict__ nd, int nn
     for (int c = 0; c < Sums<GRAD>::kNode; ++c)
 #pragma unroll
         for (int k = 0; k < PPT; ++k) o[c][k] = 0.0f;
-    if (NN > 0 && NN < 32) {  // the short rules of the distance-ratio levels
-#pragma unroll 4
-        for (int i = 0; i < n; ++i) node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o);
-        return;
-    }
-    int i = 0;
-#pragma unroll 1
-    for (; i + 4 <= n; i += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) node_term32<PPT, GRAD>(nd[i + u], dx, dy, dz, o);
-    }
-    for (; i < n; ++i) node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o);
+    for_nodes<NN>(n, [&](int i) { node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o); });
 }
 
 // Element sums for the nodes [o, o + n) of element j of the tile: FP64, or FP32 on offsets
@@ -515,15 +512,14 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) f[k] = 0.0;
                 const double4* nd = reinterpret_cast<const double4*>(s.node) + j * nn;
-#pragma unroll 4
-                for (int i = 0; i < nn; ++i) {
+                for_nodes<NN>(nn, [&](int i) {
                     const double4 Q = nd[i];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
                         const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
                         f[k] = fma(Q.w, rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz))), f[k]);
                     }
-                }
+                });
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) sum[k] = f[k];
             } else {
@@ -536,15 +532,14 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                     fz[k] = (float)dz[k];
                 }
                 const float4* nd = reinterpret_cast<const float4*>(s.node) + j * nn;
-#pragma unroll 4
-                for (int i = 0; i < nn; ++i) {
+                for_nodes<NN>(nn, [&](int i) {
                     const float4 Q = nd[i];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
                         const float rx = fx[k] - Q.x, ry = fy[k] - Q.y, rz = fz[k] - Q.z;
                         f[k] = fmaf(Q.w, rsqrt32(fmaf(rx, rx, fmaf(ry, ry, rz * rz))), f[k]);
                     }
-                }
+                });
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) sum[k] = (double)f[k];
             }
