@@ -329,7 +329,7 @@ def solver_bench(torch, bemc, W):
     pot[w.tri.shape[0]:w.tri.shape[0] + n_in_r] = 1.0
     V = torch.tensor(pot, device="cuda:0")
     res = {}
-    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6), ("refine", 1e-10)):
         sig, info = ctx.solve(V, tol=tol, max_iter=600, restart=60, precision=prec)
         torch.cuda.synchronize()
         s = sig.cpu().numpy()
@@ -339,6 +339,11 @@ def solver_bench(torch, bemc, W):
         q = s * a
         inner = np.concatenate([np.arange(n_in_t), w.tri.shape[0] + np.arange(n_in_r)])
         res[prec] = dict(info, tol=tol, inner_charge_C=float(q[inner].sum()), total_charge_C=float(q.sum()))
+        if prec == "fp64":
+            s64 = s
+        else:
+            res[prec]["rel_diff_to_fp64_solution"] = float(np.linalg.norm(s - s64) / np.linalg.norm(s64))
+    res["refine"]["note"] = "corrections by GMRES on mixed products, residuals by FP64 products"
     ctx.close()
     res["workload"] = "nested cylinders R=1 (z in [-5,5], 1 V) and R=2 (z in [-6,6], 0 V), 25k triangles + 25k rectangles"
     return res

@@ -67,6 +67,9 @@ extern "C" {
                         the element charge and accumulated per field point in FP64; the
                         distance-ratio classification, the near field and on-element
                         integrals stay FP64 */
+#define BEMC_MIXED_REFINE 2 /* bemc_solve_densities only: corrections solved with mixed
+                               products, residuals formed with FP64 products (iterative
+                               refinement), so FP64 tolerances are reachable */
 
 typedef struct bemc_context* bemc_handle;
 
@@ -178,10 +181,11 @@ int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int p
 
 /* Result of bemc_solve_densities. */
 typedef struct {
-    int iterations;       /* collocation products used */
+    int iterations;       /* collocation products used (all precisions) */
     int converged;        /* 1 if the relative residual reached tol */
     double rel_residual;  /* |potential - A sigma| / |potential|, from a final product */
     double seconds;
+    int refinements;      /* BEMC_MIXED_REFINE: FP64 residual products (outer steps) */
 } bemc_solve_info;
 
 /* Charge densities from electrode potentials (the BEM linear-algebra step, Sec. 5): find
@@ -189,9 +193,12 @@ typedef struct {
  * element i), A the operator of bemc_collocation_matvec.  Restarted GMRES (restart
  * 1..200) right-preconditioned by the diagonal of A (exact on-element potentials), started
  * from zero, stopped when the residual falls below tol * |potential| or after max_iter
- * products; precision applies to the far pairs of each product.  Allocates (restart + 4)
- * n_E doubles of workspace.  Synchronous.  Errors: NO_GEOMETRY, INVALID_ARG,
- * OUT_OF_MEMORY, DEVICE. */
+ * products; precision BEMC_FP64 or BEMC_MIXED applies to the far pairs of each product
+ * (BEMC_MIXED stalls near 1e-7, the accuracy of its products).  BEMC_MIXED_REFINE:
+ * iterative refinement, r = potential - A sigma with FP64 products, each correction from
+ * GMRES on mixed products to 1e-6 of |r|, until |r| <= tol |potential|.  Allocates
+ * (restart + 7) n_E doubles of workspace.  Synchronous.  Errors: NO_GEOMETRY,
+ * INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
                          int restart, int precision, bemc_solve_info* info, void* stream);
 

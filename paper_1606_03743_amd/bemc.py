@@ -28,7 +28,10 @@ W_ON_SURFACE = 1
 
 FP64 = 0
 MIXED = 1
+MIXED_REFINE = 2  # solver only
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+_SOLVE_PREC = dict(_PREC, refine=MIXED_REFINE)
+_SOLVE_PREC[MIXED_REFINE] = MIXED_REFINE
 
 EXPORTED = ["bemc_last_error", "bemc_create", "bemc_destroy", "bemc_set_rules", "bemc_upload_geometry",
             "bemc_upload_densities", "bemc_eval", "bemc_eval_gradient", "bemc_collocation_matvec", "bemc_query_stats",
@@ -52,7 +55,7 @@ class Stats(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("refinements", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -252,7 +255,7 @@ class Context:
             sigma = torch.empty_like(potential)
         info = SolveInfo()
         _check(self.lib.bemc_solve_densities(self.h, _dev_f64(potential), _dev_f64(sigma, (self.n_elements,)),
-                                             float(tol), int(max_iter), int(restart), _PREC[precision],
+                                             float(tol), int(max_iter), int(restart), _SOLVE_PREC[precision],
                                              ctypes.byref(info), _stream_ptr()))
         return sigma, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 

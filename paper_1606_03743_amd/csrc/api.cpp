@@ -661,12 +661,17 @@ int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, 
     if (!potential || !sigma) return fail(BEMC_E_INVALID_ARG, "null pointer");
     if (!(tol > 0.0) || max_iter < 1 || restart < 1 || restart > 200)
         return fail(BEMC_E_INVALID_ARG, "tol > 0, max_iter >= 1, restart in 1..200 required");
-    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED && precision != BEMC_MIXED_REFINE)
+        return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (info) *info = bemc_solve_info{};
     if (h->ne == 0) return ok();
     HIP_TRY(hipSetDevice(h->device));
     std::string err;
-    const int rc = bemc::solve_gmres(h, h->elements(), potential, sigma, tol, max_iter, restart, precision, info,
-                                     reinterpret_cast<hipStream_t>(stream), err);
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int rc = precision == BEMC_MIXED_REFINE
+                       ? bemc::solve_refined(h, h->elements(), potential, sigma, tol, max_iter, restart, info, s, err)
+                       : bemc::solve_gmres(h, h->elements(), potential, sigma, tol, max_iter, restart, precision, info,
+                                           s, err);
     if (rc) return fail(rc, "%s", err.c_str());
     return ok();
 }

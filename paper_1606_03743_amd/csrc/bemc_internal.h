@@ -154,6 +154,8 @@ constexpr int kMaxSplit = 64;
 double coulomb_constant();
 int solve_gmres(bemc_handle h, const Elements& el, const double* b, double* x, double tol, int max_iter, int m,
                 int precision, bemc_solve_info* info, hipStream_t s, std::string& err);
+int solve_refined(bemc_handle h, const Elements& el, const double* b, double* x, double tol, int max_iter, int m,
+                  bemc_solve_info* info, hipStream_t s, std::string& err);
 
 // Morton ordering of field points (order.hip).  Buffers sized for n points.
 struct OrderWork {

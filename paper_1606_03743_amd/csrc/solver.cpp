@@ -3,7 +3,9 @@
 // The paper computes the charge densities with KEMField's iterative methods on matrices
 // that are never stored (Sec. 5); here: restarted GMRES, right-preconditioned by the
 // diagonal of the collocation matrix (the exact on-element potentials), with classical
-// Gram-Schmidt and one reorthogonalisation.  Each product is bemc_collocation_matvec.
+// Gram-Schmidt and one reorthogonalisation, and optionally mixed-precision iterative
+// refinement around it.  Each product is bemc_collocation_matvec.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -169,6 +171,106 @@ int solve_gmres(bemc_handle h, const Elements& el, const double* b, double* x, d
     if (diag) (void)hipFree(diag);
     if (partial) (void)hipFree(partial);
     if (coef) (void)hipFree(coef);
+    if (h_partial) (void)hipHostFree(h_partial);
+    return rc;
+}
+
+// Mixed-precision iterative refinement: the residual r = b - A x is formed with FP64
+// products, each correction A d = r is solved by GMRES on mixed products to kInnerTol of
+// |r| (their accuracy is ~1e-7), and x += d, until |r| <= tol |b|.  Stops early when an
+// outer step no longer reduces |r| tenfold.
+int solve_refined(bemc_handle h, const Elements& el, const double* b, double* x, double tol, int max_iter, int m,
+                  bemc_solve_info* info, hipStream_t s, std::string& err)
+{
+    using clock = std::chrono::steady_clock;
+    const auto t_start = clock::now();
+    constexpr double kInnerTol = 1e-6;
+    constexpr int kMaxOuter = 20;
+    const int64_t n = el.ne;
+    const int kDotBlocks = 256;
+    double *r = nullptr, *d = nullptr, *ax = nullptr, *coef = nullptr, *partial = nullptr, *h_partial = nullptr;
+    int rc = BEMC_OK;
+    auto check = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == BEMC_OK) {
+            err = std::string(what) + ": " + hipGetErrorString(e);
+            rc = BEMC_E_DEVICE;
+        }
+        return rc == BEMC_OK;
+    };
+    if (hipMalloc(reinterpret_cast<void**>(&r), sizeof(double) * n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&d), sizeof(double) * n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&ax), sizeof(double) * n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&coef), sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&partial), sizeof(double) * kDotBlocks) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h_partial), sizeof(double) * kDotBlocks, hipHostMallocDefault) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        err = "refinement workspace";
+        rc = BEMC_E_OUT_OF_MEMORY;
+    }
+    // |v|, partial sums added on the host in fixed order
+    auto norm = [&](const double* v, double* out) {
+        if (!check(launch_multi_dot(v, 1, n, v, partial, kDotBlocks, s), "dot") ||
+            !check(hipMemcpyAsync(h_partial, partial, sizeof(double) * kDotBlocks, hipMemcpyDeviceToHost, s), "copy") ||
+            !check(hipStreamSynchronize(s), "sync"))
+            return false;
+        double acc = 0.0;
+        for (int i = 0; i < kDotBlocks; ++i) acc += h_partial[i];
+        *out = std::sqrt(acc);
+        return true;
+    };
+    // y = y + c v
+    auto axpy = [&](double* y, double c, const double* v) {
+        return check(hipMemcpyAsync(coef, &c, sizeof(double), hipMemcpyHostToDevice, s), "copy") &&
+               check(hipStreamSynchronize(s), "sync") && check(launch_combine(y, 1.0, v, coef, 1, n, nullptr, s), "axpy");
+    };
+    int products = 0, outer = 0;
+    double bnorm = 0.0, rnorm = 0.0;
+    bool converged = false;
+    if (rc == BEMC_OK && check(hipMemsetAsync(x, 0, sizeof(double) * n, s), "memset") &&
+        check(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy") && norm(b, &bnorm)) {
+        rnorm = bnorm;
+        converged = bnorm == 0.0;
+        while (!converged && products < max_iter && outer < kMaxOuter) {
+            bemc_solve_info inner{};
+            const double inner_tol = std::max(kInnerTol, tol * bnorm / rnorm);
+            const int r2 = solve_gmres(h, el, r, d, inner_tol, max_iter - products, m, BEMC_MIXED, &inner, s, err);
+            products += inner.iterations;
+            if (r2 != BEMC_OK) {
+                rc = r2;
+                break;
+            }
+            if (!axpy(x, 1.0, d)) break;
+            // r = b - A x with an FP64 product
+            const int r3 = bemc_collocation_matvec(h, x, 1, BEMC_FP64, ax, s);
+            ++products;
+            ++outer;
+            if (r3 != BEMC_OK) {
+                err = std::string("collocation product: ") + bemc_last_error();
+                rc = r3;
+                break;
+            }
+            if (!check(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy") ||
+                !axpy(r, -1.0, ax))
+                break;
+            const double prev = rnorm;
+            if (!norm(r, &rnorm)) break;
+            converged = rnorm <= tol * bnorm;
+            if (!converged && rnorm > 0.1 * prev) break;  // no longer converging
+        }
+    }
+    if (info) {
+        info->iterations = products;
+        info->converged = converged ? 1 : 0;
+        info->rel_residual = bnorm > 0 ? rnorm / bnorm : 0.0;
+        info->seconds = std::chrono::duration<double>(clock::now() - t_start).count();
+        info->refinements = outer;
+    }
+    if (r) (void)hipFree(r);
+    if (d) (void)hipFree(d);
+    if (ax) (void)hipFree(ax);
+    if (coef) (void)hipFree(coef);
+    if (partial) (void)hipFree(partial);
     if (h_partial) (void)hipHostFree(h_partial);
     return rc;
 }

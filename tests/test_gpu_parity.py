@@ -222,6 +222,13 @@ def test_empty_and_errors():
     assert ei.value.code == bemc.E_INVALID_ARG
     with pytest.raises(bemc.BemcError):
         ctx.set_rules(tri_rule=5)
+    # index range: n >= 2^31 is rejected before any pointer is read or kernel launched
+    small = torch.zeros((3, 4), dtype=torch.float64, device="cuda:0")
+    out = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    rc = ctx.lib.bemc_eval(ctx.h, small.data_ptr(), 1 << 31, 0, 0, out.data_ptr(), None, None)
+    assert rc == bemc.E_LIMIT
+    rc = ctx.lib.bemc_eval_gradient(ctx.h, small.data_ptr(), 1 << 31, 0, 0, out.data_ptr(), None)
+    assert rc == bemc.E_LIMIT
     ctx.close()
 
 

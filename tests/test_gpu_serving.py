@@ -96,6 +96,10 @@ def test_admission_and_latency_fields(setup):
     with pytest.raises(bemc.BemcError) as ei:
         ctx.server_submit(big, np.empty(1025))
     assert ei.value.code == bemc.E_ADMISSION
+    edge = np.ascontiguousarray(queries[6][:1024])  # exactly max_batch_points: admitted
+    phi_edge = np.full(1024, np.nan)
+    assert ctx.server_wait(ctx.server_submit(edge, phi_edge), 60.0)["status"] == 0
+    assert np.all(np.isfinite(phi_edge))
     q = queries[4]  # 513 points
     phi = np.empty(len(q))
     t = ctx.server_submit(q, phi)  # field not requested

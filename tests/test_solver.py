@@ -90,9 +90,10 @@ def test_gpu_gmres_matches_dense_solve(sphere_systems, sub):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "refine"])
 def test_gpu_gmres_mixed_geometry(orc, precision):
-    """Nested triangles + rectangles (two coaxial cylinders at 1 V and 0 V)."""
+    """Nested triangles + rectangles (two coaxial cylinders at 1 V and 0 V).  "refine":
+    FP64 residuals with corrections from mixed products reach the FP64 solution."""
     import torch
 
     from paper_1606_03743_amd import bemc
@@ -109,7 +110,7 @@ def test_gpu_gmres_mixed_geometry(orc, precision):
     ref = np.linalg.solve(A, pot)
     ctx = bemc.Context(0)
     ctx.upload_geometry(tri, rect)
-    sig, info = ctx.solve(torch.tensor(pot, device="cuda:0"), tol=1e-12 if precision == "fp64" else 1e-7,
+    sig, info = ctx.solve(torch.tensor(pot, device="cuda:0"), tol=1e-7 if precision == "mixed" else 1e-12,
                           max_iter=400, restart=60, precision=precision)
     torch.cuda.synchronize()
     ctx.close()
@@ -117,4 +118,6 @@ def test_gpu_gmres_mixed_geometry(orc, precision):
     err = np.linalg.norm(s - ref) / np.linalg.norm(ref)
     print(f"nested {precision}: {info}, error {err:.2e}")
     assert info["converged"] == 1
-    assert err < (1e-9 if precision == "fp64" else 1e-5)
+    assert err < (1e-5 if precision == "mixed" else 1e-9)
+    if precision == "refine":
+        assert info["refinements"] >= 2 and info["rel_residual"] <= 1e-12
