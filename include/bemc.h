@@ -20,8 +20,8 @@
  * coordinates about the point (principal value for the in-plane field, zero normal part).
  *
  * Conventions.
- *   * All entry points return BEMC_OK (0), a negative BEMC_E_* error, or (bemc_eval
- *     only) the positive warning BEMC_W_ON_SURFACE.  On error, bemc_last_error() gives a
+ *   * All entry points return BEMC_OK (0), a negative BEMC_E_* error, or (bemc_eval and
+ *     bemc_eval_gradient only) the positive warning BEMC_W_ON_SURFACE.  On error, bemc_last_error() gives a
  *     message for the calling thread.  No entry point aborts the process.
  *   * "device" pointers are GPU memory of the context's device (e.g. torch tensors on
  *     cuda:N); "host" pointers are ordinary CPU memory.  The caller owns every buffer it
@@ -73,11 +73,13 @@ extern "C" {
 
 typedef struct bemc_context* bemc_handle;
 
-/* Counters of the last bemc_eval / bemc_collocation_matvec on a context. */
+/* Counters of the last bemc_eval / bemc_eval_gradient / bemc_collocation_matvec on a
+ * context (a solve leaves those of its last product). */
 typedef struct {
     int64_t pairs;          /* field points x elements */
-    int64_t node_interactions; /* point-charge terms of the far-field sums (far pairs only
-                                  when the rule is chosen by distance ratio) */
+    int64_t node_interactions; /* point-charge terms of the far-field sums: all pairs x the
+                                  rule size with one rule per kind; with the rule chosen by
+                                  distance ratio, the terms the far pairs really summed */
     int64_t near_pairs;     /* pairs with D < near_dr * L (handled in FP64) */
     int64_t leaves;         /* rule applications made by the subdivision */
     int64_t cap_hits;       /* leaves still near at the depth cap */
