@@ -62,3 +62,19 @@ def test_null_argument_errors(lib):
 
     assert abs(lib.bemc_coulomb_constant() * 4 * math.pi * sc.epsilon_0 - 1) < 1e-15
     assert lib.bemc_rule_size(33) == 33 and lib.bemc_rule_size(7) == 7 and lib.bemc_rule_size(5) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No silent fallback: without the built library the binding raises."""
+    from paper_1606_03743_amd import bemc
+
+    monkeypatch.setattr(bemc, "_lib", None)
+    monkeypatch.setattr(bemc, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libbemc.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        bemc.load_library()
+
+
+def test_null_argument_errors_of_newer_entry_points(lib):
+    assert lib.bemc_eval_gradient(None, None, 0, 0, 0, None, None) == -1
+    assert lib.bemc_set_dr_rules(None, 1, None, None) == -1
+    assert lib.bemc_solve_densities(None, None, None, ctypes.c_double(1e-10), 10, 10, 0, None, None) == -1
