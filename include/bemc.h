@@ -116,9 +116,9 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_rule, double near_dr, i
  * tri_dr[1] / tri_dr[2], else the triangle rule of bemc_set_rules; a far rectangle pair
  * uses Tables B2 / B3 / B4 for DR >= rect_dr[0..2], else the rectangle rule.  NULL
  * arrays select the defaults {100, 25, 10} and {150, 40, 15} (the paper's triangle
- * potential limits x 1.25; the rectangle tables' field-accuracy limits).  bemc_eval then
- * orders the field points along a Morton curve internally, and for each element a
- * wavefront of 128 neighbouring points uses the finest of the rules its pairs need (never
+ * potential limits x 1.25; the rectangle tables' field-accuracy limits).  For each
+ * element a wavefront of 128 neighbouring points (bemc_eval works on the points in Morton
+ * order) uses the finest of the rules its pairs need (never
  * a coarser rule than a pair's own distance ratio asks for); results are returned in the
  * caller's order.  Near pairs and collocation are unaffected.  The rules of
  * bemc_set_rules must be at least as fine as the third level (>= 19 triangle points,
@@ -147,6 +147,9 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
 /* Potential phi[n] (device) and, if E is not NULL, field E[3][n] (device) at the n field
  * points pts[3][n] (device), from density vector `rhs` (0 <= rhs < n_rhs).  Outputs are
  * overwritten.  precision = BEMC_FP64 or BEMC_MIXED.  n = 0 is a no-op.
+ * The points are processed in Morton (Z-curve) order, which keeps the points of a
+ * wavefront close together; results are returned in the caller's order and do not depend
+ * on that order.  The ordering workspace (about 110 bytes per point) is kept by the context.
  * The call enqueues the far-field kernel (classification, near-pair compaction and the
  * point-charge sums) and the FP64 near-field kernel on `stream` and returns after both
  * have finished (it waits on the host for the near-pair count: when the near-pair list

@@ -260,8 +260,12 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     HIP_TRY(hipSetDevice(device));
     const bool colloc = mode == kNearColloc;
     const bool grad = mode == kNearGrad;
-    // rule choice by distance ratio: evaluate on Morton-ordered points, scatter back at the end
-    const bool ordered = dr_rules && !colloc;
+    // Evaluate on Morton-ordered points and scatter the results back at the end: the points
+    // of a wavefront then lie close together, so they mostly need the same rule level (rule
+    // choice by distance ratio) and are near the same elements, which turns the near-pair
+    // records of a wavefront into few contiguous runs.  Per-point results do not depend on
+    // the order.  Collocation points (centroids in element order) are already coherent.
+    const bool ordered = !colloc;
     double* user_phi = phi;
     double* user_E = E;
     if (ordered) {
