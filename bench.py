@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 128 FP32 FMA lanes x 2 (packed)
+PEAK_HBM_GBPS = 8000.0    # HBM3E
 FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
 FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
 GRAD_FLOP_PER_NODE_INT = 30  # field gradient (six components) per point-charge term
@@ -205,7 +206,9 @@ def main():
                      "kernel": "far_eval_kernel<33,49,fp64>",
                      "flops_per_launch": alg_flops, "avg_launch_ms": 1e3 * far_avg_s,
                      "counted_fp64_tflops": None if counted is None else counted / far_avg_s / 1e12,
-                     "counted_frac": None if counted is None else counted / far_avg_s / 1e12 / PEAK_FP64_TFLOPS},
+                     "counted_frac": None if counted is None else counted / far_avg_s / 1e12 / PEAK_FP64_TFLOPS,
+                     "hbm_gbps": None if traffic is None else traffic / far_avg_s / 1e9,
+                     "hbm_frac": None if traffic is None else traffic / far_avg_s / 1e9 / PEAK_HBM_GBPS},
         "node_interactions_per_s": node_int * args.steps / dt64,
         "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
                  "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},
