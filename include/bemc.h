@@ -153,7 +153,9 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
  * The call enqueues the far-field kernel (classification, near-pair compaction and the
  * point-charge sums) and the FP64 near-field kernel on `stream` and returns after both
  * have finished (it waits on the host for the near-pair count: when the near-pair list
- * overflowed, the list is grown and the evaluation repeated).  Returns BEMC_W_ON_SURFACE
+ * overflowed, the list is grown and the evaluation repeated).  Results are reproducible
+ * bit for bit: far-field chunks are added in fixed order, and each point's near pairs
+ * are summed in element order.  Returns BEMC_W_ON_SURFACE
  * when a field point lies on an element (its field there is the principal value).
  * Errors: NO_GEOMETRY, INVALID_ARG, LIMIT (n >= 2^31, or a near pair needed more than
  * 2^22 subdivision steps), OUT_OF_MEMORY, DEVICE. */
@@ -207,9 +209,11 @@ typedef struct {
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
                          int restart, int precision, bemc_solve_info* info, void* stream);
 
-/* Pre-size the near-pair list (entries of 8 bytes).  The list also grows by itself when an
- * evaluation finds more near pairs than it holds (the evaluation is then repeated), so
- * this only avoids that repetition.  Errors: INVALID_ARG, OUT_OF_MEMORY. */
+/* Pre-size the near-pair list (8 bytes per pair, plus 8 for its sorted copy and 8 per
+ * result row -- 4 for the field, 6 for the gradient -- allocated at the next evaluation;
+ * at most 2^32 - 1 pairs).  The list also grows by itself when an evaluation finds more
+ * near pairs than it holds (the evaluation is then repeated), so this only avoids that
+ * repetition.  Errors: INVALID_ARG, LIMIT, OUT_OF_MEMORY. */
 int bemc_set_near_capacity(bemc_handle h, int64_t pairs);
 
 /* Counters of the last evaluation.  Errors: INVALID_ARG. */
@@ -231,8 +235,10 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
  * at least two streams, queries of at most that many points wait in a queue of their
  * own, and one stream serves only that queue, so that short queries do not wait behind
  * long batches; the other streams take the long queue first and the short one when the
- * long one is empty.  A query's result does not depend on the other queries in its
- * batch beyond the order of floating-point atomic additions in the near field.
+ * long one is empty.  A query's result depends on the other queries in its batch only
+ * through the number of element chunks of the far-field launch (the summation grouping,
+ * a rounding-level difference); with the rule choice by distance ratio also through the
+ * rule each wavefront of neighbouring points picks (an accuracy-level difference).
  * --------------------------------------------------------------------------------- */
 
 typedef struct {

@@ -94,6 +94,13 @@ struct bemc_context {
     // near-pair list and counters
     NearPair* d_near = nullptr;
     unsigned long long near_cap = 0;
+    // deterministic near-field accumulation: per-point segments and per-pair results
+    NearWork nw{};
+    int64_t nw_pts = 0;
+    unsigned long long nw_pairs = 0;
+    int nw_rows = 0;
+    int ensure_near_work(int64_t n, int rows);
+    void free_near_work();
     double* d_partial = nullptr;  // element-chunk partial sums
     size_t partial_cap = 0;       // doubles
     DevCounters* d_ctr = nullptr;
@@ -239,11 +246,35 @@ int bemc_context::ensure_order(int64_t n)
     return ok();
 }
 
+void bemc_context::free_near_work()
+{
+    near_work_free(nw);
+    nw_pts = 0;
+    nw_pairs = 0;
+    nw_rows = 0;
+}
+
+int bemc_context::ensure_near_work(int64_t n, int rows)
+{
+    if (n <= nw_pts && near_cap <= nw_pairs && rows <= nw_rows && near_scan_temp_bytes(n) <= nw.temp_bytes) return ok();
+    const int64_t np = std::max(n, nw_pts);
+    const unsigned long long pairs = std::max(near_cap, nw_pairs);
+    const int nr = std::max(rows, nw_rows);
+    free_near_work();
+    if (near_work_alloc(nw, np, pairs, nr) != hipSuccess)
+        return fail(BEMC_E_OUT_OF_MEMORY, "near-field work buffers for %llu pairs", pairs);
+    nw_pts = np;
+    nw_pairs = pairs;
+    nw_rows = nr;
+    return ok();
+}
+
 int bemc_context::ensure_near_capacity(unsigned long long need)
 {
     if (need <= near_cap) return ok();
+    if (need > kMaxNearPairs) return fail(BEMC_E_LIMIT, "%llu near pairs exceed the 2^32 - 1 limit", need);
     unsigned long long cap = std::max<unsigned long long>(need, 1ull << 20);
-    cap = cap + cap / 4;
+    cap = std::min(cap + cap / 4, kMaxNearPairs);
     dev_free(d_near);
     if (dev_alloc(&d_near, (size_t)cap) != hipSuccess) {
         near_cap = 0;
@@ -293,8 +324,17 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
         fa.lv = levels();
         NearArgs na{};
         na.el = fa.el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = fa.n; na.rhs = rhs;
-        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_list = d_near; na.near_cap = near_cap;
+        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_cap = near_cap;
         na.ctr = d_ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
+        const int near_rows = colloc ? 1 : (grad ? 6 : 4);
+        {
+            const int64_t np = colloc ? ne : n;
+            int rc = ensure_near_work(np, near_rows);
+            if (rc) return rc;
+        }
+        na.near_list = nw.sorted;
+        na.res = nw.res;
+        na.res_stride = nw_pairs;
 
         // Split the element range over blockIdx.y so that the launch has many more
         // workgroups than resident slots: the dispatcher then balances the tail.  The chunk
@@ -330,7 +370,9 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
             else HIP_TRY(launch_reduce_split(d_partial, n_split, npts, fa.K, phi, E, s));
         }
         HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(near_order(d_near, d_ctr, near_cap, npts, nw, s));
         HIP_TRY(launch_near(na, mode, s));
+        HIP_TRY(near_reduce(nw, npts, nw_pairs, mode, phi, E, G, fa.el.q, ne, n_rhs_colloc, fa.K, s));
         HIP_TRY(hipEventRecord(ev[2], s));
         if (ordered) {
             if (grad) {
@@ -430,6 +472,7 @@ int bemc_destroy(bemc_handle h)
     dev_free(h->d_lv_tri); dev_free(h->d_lv_rect); dev_free(h->d_lv_tri32); dev_free(h->d_lv_rect32);
     h->free_order();
     dev_free(h->d_near); dev_free(h->d_ctr); dev_free(h->d_partial);
+    h->free_near_work();
     if (h->h_ctr) (void)hipHostFree(h->h_ctr);
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);
@@ -705,6 +748,7 @@ int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const dou
 int bemc_set_near_capacity(bemc_handle h, int64_t pairs)
 {
     if (!h || pairs < 1) return fail(BEMC_E_INVALID_ARG, "invalid capacity");
+    if ((unsigned long long)pairs > kMaxNearPairs) return fail(BEMC_E_LIMIT, "capacity above 2^32 - 1 pairs");
     HIP_TRY(hipSetDevice(h->device));
     HIP_TRY(hipDeviceSynchronize());
     dev_free(h->d_near);

@@ -120,8 +120,10 @@ struct NearArgs {
     double* phi;        // eval: phi[n]; collocation: out[n_rhs][ne]
     double* E;          // eval only, may be null
     double* G;          // gradient mode: [6][n]
-    const NearPair* near_list;
+    const NearPair* near_list;   // in (point, element) order
     unsigned long long near_cap;
+    double* res;                 // per-pair results [rows][res_stride] (rows 4, 6 or 1)
+    unsigned long long res_stride;
     DevCounters* ctr;
     double near_dr2;    // near_dr^2
     int max_depth;
@@ -156,6 +158,26 @@ int solve_gmres(bemc_handle h, const Elements& el, const double* b, double* x, d
                 int precision, bemc_solve_info* info, hipStream_t s, std::string& err);
 int solve_refined(bemc_handle h, const Elements& el, const double* b, double* x, double tol, int max_iter, int m,
                   bemc_solve_info* info, hipStream_t s, std::string& err);
+
+// Deterministic near-field accumulation (near_order.hip).  Per-point arrays hold n entries,
+// the pair arrays the near-list capacity (< 2^32 pairs).
+struct NearWork {
+    uint32_t *count, *start, *cursor;  // [n] near pairs per point, segment starts, scatter cursors
+    NearPair* sorted;                  // [capacity] pairs in (point, element) order
+    double* res;                       // [rows][capacity] per-pair results of the near kernel
+    void* temp;                        // scan workspace
+    size_t temp_bytes;
+};
+size_t near_scan_temp_bytes(int64_t n);
+hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int rows);  // frees w first
+void near_work_free(NearWork& w);
+// regroup the list (length read from ctr) into per-point segments sorted by element
+hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
+                      const NearWork& w, hipStream_t s);
+// add each point's segment of per-pair results (row stride `stride`) to its outputs
+hipError_t near_reduce(const NearWork& w, int64_t n, unsigned long long stride, int mode, double* phi, double* E,
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
+constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 
 // Morton ordering of field points (order.hip).  Buffers sized for n points.
 struct OrderWork {

@@ -15,7 +15,10 @@
 //                      children; rectangle: 2 x 2) using lattice coordinates instead of a
 //                      stack; a child at DR >= near_dr of its own (or at the depth cap) gets
 //                      the element's rule; a point lying on its element gets the exact
-//                      polar integral.  Results are added with FP64 atomics.
+//                      polar integral.  The list is in (point, element) order and each
+//                      pair's result goes to its own slot; the per-point sums are formed
+//                      in that order afterwards (near_order.hip), so results are
+//                      reproducible bit for bit.
 #include "bemc_internal.h"
 
 namespace bemc {
@@ -724,6 +727,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     bool active = false;
     NearState st{ 0, 0, 0, 0, true };
     uint32_t p = 0, e = 0;
+    unsigned long long cur = 0;  // list index of the pair in hand
     double P[3] = { 0, 0, 0 }, g0[3] = { 0, 0, 0 }, g1[3] = { 0, 0, 0 }, g2[3] = { 0, 0, 0 };
     double thr2 = 0.0, acc[6] = { 0, 0, 0, 0, 0, 0 };
     int64_t visits = 0;
@@ -739,6 +743,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
             if (!active) {
                 const unsigned long long w = b + lanes_below(need);
                 if (w >= total) break;
+                cur = w;
                 const NearPair pr = a.near_list[w];
                 p = pr.point;
                 e = pr.elem;
@@ -927,24 +932,15 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         }
 
         if (finished) {
-            const double K = a.K;
+            // the pair's own result slot(s); collocation keeps the unit-density potential
+            // (the densities are applied per right-hand side when the sums are formed)
+            const unsigned long long S = a.res_stride;
             if (COLLOC) {
-                for (int r = 0; r < a.n_rhs; ++r) {
-                    const double q = el.q[(int64_t)r * ne + e];
-                    unsafeAtomicAdd(&a.phi[(int64_t)r * ne + p], K * q * acc[0]);
-                }
-            } else if (GRAD) {
-                const double q = el.q[(int64_t)a.rhs * ne + e];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&a.G[c * a.n + p], K * q * acc[c]);
+                a.res[cur] = acc[0];
             } else {
-                const double q = el.q[(int64_t)a.rhs * ne + e];
-                unsafeAtomicAdd(&a.phi[p], K * q * acc[0]);
-                if (a.E) {
-                    unsafeAtomicAdd(&a.E[p], K * q * acc[1]);
-                    unsafeAtomicAdd(&a.E[a.n + p], K * q * acc[2]);
-                    unsafeAtomicAdd(&a.E[2 * a.n + p], K * q * acc[3]);
-                }
+                const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
+#pragma unroll
+                for (int c = 0; c < (GRAD ? 6 : 4); ++c) a.res[c * S + cur] = Kq * acc[c];
             }
             active = false;
             st.level = 0;

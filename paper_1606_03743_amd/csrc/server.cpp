@@ -56,7 +56,10 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
     const int64_t blocks = (M + kPointsPerBlock - 1) / kPointsPerBlock;
     max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(kSlotSplit, kWavesTarget / std::max<int64_t>(1, blocks)));
     const unsigned long long near0 = (unsigned long long)std::max<int64_t>(1 << 16, 16 * M);
-    const size_t slot_bytes = (size_t)M * 8 * (3 + 1 + 3 + 4 * (size_t)max_split_) + near0 * sizeof(NearPair) + 4096;
+    // points, results, partial sums, near list (+ its sorted copy and 4 result rows) and
+    // the per-point near-field segments
+    const size_t slot_bytes = (size_t)M * 8 * (3 + 1 + 3 + 4 * (size_t)max_split_) + (size_t)M * 12 +
+                              near0 * (2 * sizeof(NearPair) + 4 * sizeof(double)) + 4096;
     int n_slots = (int)std::min<size_t>((size_t)cfg.n_streams, cfg.mem_budget_bytes / slot_bytes);
     if (n_slots < 1) {
         err = "memory budget too small for one batch slot";
@@ -75,7 +78,8 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
                    hipMalloc(reinterpret_cast<void**>(&s.d_ctr), sizeof(DevCounters)) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_pts), (size_t)M * 3 * 8, hipHostMallocDefault) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_out), (size_t)M * 4 * 8, hipHostMallocDefault) == hipSuccess &&
-                   hipHostMalloc(reinterpret_cast<void**>(&s.h_ctr), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess;
+                   hipHostMalloc(reinterpret_cast<void**>(&s.h_ctr), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess &&
+                   near_work_alloc(s.nw, M, near0, 4) == hipSuccess;
         if (!okk) {
             (void)hipGetLastError();
             err = "out of device or pinned memory for the batch slots";
@@ -164,6 +168,7 @@ void Server::stop()
         if (s.d_E) (void)hipFree(s.d_E);
         if (s.d_partial) (void)hipFree(s.d_partial);
         if (s.d_near) (void)hipFree(s.d_near);
+        near_work_free(s.nw);
         if (s.d_ctr) (void)hipFree(s.d_ctr);
         if (s.h_pts) (void)hipHostFree(s.h_pts);
         if (s.h_out) (void)hipHostFree(s.h_out);
@@ -179,6 +184,10 @@ void Server::stop()
 bool Server::launch(Slot& s, std::string& err)
 {
     const int64_t n = s.n;
+    if (s.near_cap == 0 || !s.d_near || !s.nw.count) {  // a failed regrowth left no near-field buffers
+        err = "batch slot has no near-pair buffers";
+        return false;
+    }
     // pack points SoA into pinned staging
     int64_t off = 0;
     for (uint64_t id : s.queries) {
@@ -235,13 +244,18 @@ bool Server::launch(Slot& s, std::string& err)
     na.K = K;
     na.phi = s.d_phi;
     na.E = s.d_E;
-    na.near_list = s.d_near;
+    na.near_list = s.nw.sorted;
     na.near_cap = s.near_cap;
+    na.res = s.nw.res;
+    na.res_stride = s.near_cap;
     na.ctr = s.d_ctr;
     na.near_dr2 = env_.near_dr * env_.near_dr;
     na.max_depth = env_.max_depth;
     na.visit_limit = 1ll << 22;
+    if (e == hipSuccess) e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.nw, s.stream);
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
+    if (e == hipSuccess)
+        e = near_reduce(s.nw, n, s.near_cap, kNearEval, s.d_phi, s.d_E, nullptr, env_.el.q, ne, 1, K, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_phi, (size_t)n * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out + n, s.d_E, (size_t)n * 3 * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
@@ -261,7 +275,8 @@ void Server::complete(Slot& s)
         const unsigned long long cap = s.h_ctr->near_count + s.h_ctr->near_count / 4;
         (void)hipFree(s.d_near);
         s.d_near = nullptr;
-        if (hipMalloc(reinterpret_cast<void**>(&s.d_near), cap * sizeof(NearPair)) != hipSuccess) {
+        if (cap > kMaxNearPairs || hipMalloc(reinterpret_cast<void**>(&s.d_near), cap * sizeof(NearPair)) != hipSuccess ||
+            near_work_alloc(s.nw, cfg_.max_batch_points, cap, 4) != hipSuccess) {
             (void)hipGetLastError();
             s.near_cap = 0;
         } else {

@@ -53,6 +53,7 @@ private:
         double *h_pts = nullptr, *h_out = nullptr;  // pinned staging: [3][M] in, [4][M] out
         NearPair* d_near = nullptr;
         unsigned long long near_cap = 0;
+        NearWork nw{};  // per-point segments and per-pair results (near_cap pairs, 4 rows)
         DevCounters *d_ctr = nullptr, *h_ctr = nullptr;
         bool busy = false;
         bool small_only = false;  // serves the short-query class only

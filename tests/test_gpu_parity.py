@@ -241,6 +241,32 @@ def test_far_field_is_deterministic(sphere):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_results_are_reproducible_bit_for_bit(cyl, precision):
+    """With near pairs: the near-field sums are formed per point in element order, so two
+    runs, and a run whose near-pair list overflowed and was regrown, agree bit for bit --
+    for the field, the gradient and the collocation product."""
+    torch = torch_mod()
+    w, _ = cyl
+    ctx = make_ctx(w)
+    a = run_gpu(ctx, w.points, precision)
+    b = run_gpu(ctx, w.points, precision)
+    ctx.set_near_capacity(8)  # forces an overflow, a larger list and a repeated evaluation
+    c = run_gpu(ctx, w.points, precision)
+    assert ctx.stats()["near_pairs"] > 8
+    for x, y in ((a, b), (a, c)):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    g1 = ctx.eval_gradient(pts, precision)[0].cpu().numpy()
+    g2 = ctx.eval_gradient(pts, precision)[0].cpu().numpy()
+    assert np.array_equal(g1, g2)
+    sig = torch.tensor(np.stack([w.sigma[0], -w.sigma[0] ** 2]), device="cuda:0")
+    o1 = ctx.collocation(sig, precision).cpu().numpy()
+    o2 = ctx.collocation(sig, precision).cpu().numpy()
+    assert np.array_equal(o1, o2)
+    ctx.close()
+
+
 # --------------------------------------------------------------- collocation -----
 @pytest.fixture(scope="module")
 def nested():

@@ -72,8 +72,9 @@ def test_alone_equals_mix_and_oracle(setup, precision, tol, dr, small):
     for q, a, b, ea, eb in zip(queries, pa, pm, Ea, Em):
         sl = slice(off, off + len(q))
         off += len(q)
-        # alone vs mix: same computation up to the element-split summation order and the
-        # order of the near-field atomic additions
+        # alone vs mix: same computation up to the grouping of the element-chunk sums
+        # (chunk count follows the batch size) and, with the distance-ratio rules, the
+        # level each wavefront picks
         d_ab = np.abs(a - b) / ref["abs_phi"][sl]
         d_e = np.sum(np.abs(ea - eb), axis=1) / ref["abs_E"][sl]
         assert d_ab.max() <= tol and d_e.max() <= tol
