@@ -209,7 +209,7 @@ typedef struct {
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
                          int restart, int precision, bemc_solve_info* info, void* stream);
 
-/* Pre-size the near-pair list (8 bytes per pair, plus 8 for its sorted copy and 8 per
+/* Pre-size the near-pair list (8 bytes per pair, plus 24 for its regrouping and 8 per
  * result row -- 4 for the field, 6 for the gradient -- allocated at the next evaluation;
  * at most 2^32 - 1 pairs).  The list also grows by itself when an evaluation finds more
  * near pairs than it holds (the evaluation is then repeated), so this only avoids that

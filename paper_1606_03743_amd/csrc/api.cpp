@@ -332,7 +332,8 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
             int rc = ensure_near_work(np, near_rows);
             if (rc) return rc;
         }
-        na.near_list = nw.sorted;
+        na.near_list = d_near;
+        na.slot = nw.slot;
         na.res = nw.res;
         na.res_stride = nw_pairs;
 

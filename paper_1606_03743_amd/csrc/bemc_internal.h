@@ -120,8 +120,9 @@ struct NearArgs {
     double* phi;        // eval: phi[n]; collocation: out[n_rhs][ne]
     double* E;          // eval only, may be null
     double* G;          // gradient mode: [6][n]
-    const NearPair* near_list;   // in (point, element) order
+    const NearPair* near_list;   // as the far kernel appended it
     unsigned long long near_cap;
+    const uint32_t* slot;        // result slot of each list entry
     double* res;                 // per-pair results [rows][res_stride] (rows 4, 6 or 1)
     unsigned long long res_stride;
     DevCounters* ctr;
@@ -163,7 +164,10 @@ int solve_refined(bemc_handle h, const Elements& el, const double* b, double* x,
 // the pair arrays the near-list capacity (< 2^32 pairs).
 struct NearWork {
     uint32_t *count, *start, *cursor;  // [n] near pairs per point, segment starts, scatter cursors
+    NearPair* grouped;                 // [capacity] pairs grouped by point, unordered within a point
+    uint32_t* origin;                  // [capacity] list index of each grouped pair
     NearPair* sorted;                  // [capacity] pairs in (point, element) order
+    uint32_t* slot;                    // [capacity] result slot (sorted position) of each list index
     double* res;                       // [rows][capacity] per-pair results of the near kernel
     void* temp;                        // scan workspace
     size_t temp_bytes;

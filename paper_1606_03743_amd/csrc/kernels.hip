@@ -15,10 +15,9 @@
 //                      children; rectangle: 2 x 2) using lattice coordinates instead of a
 //                      stack; a child at DR >= near_dr of its own (or at the depth cap) gets
 //                      the element's rule; a point lying on its element gets the exact
-//                      polar integral.  The list is in (point, element) order and each
-//                      pair's result goes to its own slot; the per-point sums are formed
-//                      in that order afterwards (near_order.hip), so results are
-//                      reproducible bit for bit.
+//                      polar integral.  Each pair's result goes to its own slot in
+//                      (point, element) order; the per-point sums are formed in that order
+//                      afterwards (near_order.hip), so results are reproducible bit for bit.
 #include "bemc_internal.h"
 
 namespace bemc {
@@ -727,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     bool active = false;
     NearState st{ 0, 0, 0, 0, true };
     uint32_t p = 0, e = 0;
-    unsigned long long cur = 0;  // list index of the pair in hand
+    unsigned long long cur = 0;  // result slot of the pair in hand
     double P[3] = { 0, 0, 0 }, g0[3] = { 0, 0, 0 }, g1[3] = { 0, 0, 0 }, g2[3] = { 0, 0, 0 };
     double thr2 = 0.0, acc[6] = { 0, 0, 0, 0, 0, 0 };
     int64_t visits = 0;
@@ -743,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
             if (!active) {
                 const unsigned long long w = b + lanes_below(need);
                 if (w >= total) break;
-                cur = w;
+                cur = a.slot[w];
                 const NearPair pr = a.near_list[w];
                 p = pr.point;
                 e = pr.elem;

@@ -1,12 +1,14 @@
 // Deterministic near-field accumulation.
 //
 // The far kernel appends near pairs to a list in an order that depends on scheduling.
-// Before the near kernel runs, the pairs are regrouped by field point (counts per point,
-// an exclusive scan, a scatter) and each point's segment is sorted by element index, so
-// the list is in (point, element) order.  The near kernel writes each pair's result to
-// the pair's slot, and one thread per point adds its segment in that order to the point's
-// far-field result.  The outcome does not depend on how the GPU scheduled the work.
-// No step needs the pair count on the host: the kernels read it from the device counters.
+// Before the near kernel runs, each pair gets a result slot in (point, element) order:
+// pairs are regrouped by field point (counts per point, an exclusive scan, a scatter) and
+// each point's segment is ordered by element index.  The near kernel walks the pairs in
+// the far kernel's list order (neighbouring points and the same element: similar
+// subdivision trees side by side) and writes each result to the pair's slot; one thread
+// per point then adds its segment in element order to the point's far-field result.  The
+// outcome does not depend on how the GPU scheduled the work.  No step needs the pair count
+// on the host: the kernels read it from the device counters.
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"
@@ -39,34 +41,38 @@ __global__ void count_kernel(const NearPair* __restrict__ list, const DevCounter
 
 __global__ void scatter_pairs_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
                                      unsigned long long cap, const uint32_t* __restrict__ start,
-                                     uint32_t* __restrict__ cursor, NearPair* __restrict__ sorted)
+                                     uint32_t* __restrict__ cursor, NearPair* __restrict__ grouped,
+                                     uint32_t* __restrict__ origin)
 {
     const unsigned long long total = pair_total(ctr, cap);
     for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (unsigned long long)gridDim.x * kBlock) {
         const NearPair pr = list[i];
         const uint32_t pos = start[pr.point] + atomicAdd(&cursor[pr.point], 1u);
-        sorted[pos] = pr;
+        grouped[pos] = pr;
+        origin[pos] = (uint32_t)i;
     }
 }
 
-// Insertion sort of each point's segment by element index (segments hold the elements
-// within near_dr L of the point: tens, rarely thousands).
-__global__ void sort_segments_kernel(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
-                                     int64_t n, NearPair* __restrict__ sorted)
+// Sorts each point's segment by element index, one wavefront per point: every entry's
+// place is the number of entries of the segment with a smaller element index (the
+// elements of a segment are distinct).  Segments hold the elements within near_dr L of
+// the point: tens of entries, rarely thousands.
+constexpr int kWavesPerBlock = kBlock / 64;
+
+__global__ void rank_sort_kernel(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
+                                 const NearPair* __restrict__ in, const uint32_t* __restrict__ origin,
+                                 NearPair* __restrict__ out, uint32_t* __restrict__ slot)
 {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / 64;  // same for the whole wavefront
     if (p >= n) return;
-    NearPair* seg = sorted + start[p];
-    const uint32_t k = count[p];
-    for (uint32_t i = 1; i < k; ++i) {
-        const NearPair v = seg[i];
-        uint32_t j = i;
-        while (j > 0 && seg[j - 1].elem > v.elem) {
-            seg[j] = seg[j - 1];
-            --j;
-        }
-        seg[j] = v;
+    const uint32_t s = start[p], k = count[p];
+    for (uint32_t i = threadIdx.x % 64; i < k; i += 64) {
+        const NearPair v = in[s + i];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < k; ++j) rank += in[s + j].elem < v.elem ? 1u : 0u;
+        out[s + rank] = v;
+        slot[origin[s + i]] = s + rank;  // where the pair at this list index puts its result
     }
 }
 
@@ -111,7 +117,8 @@ unsigned grid_for(int64_t n)
 
 void near_work_free(NearWork& w)
 {
-    for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.sorted, (void*)w.res, w.temp })
+    for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
+                       (void*)w.sorted, (void*)w.slot, (void*)w.res, w.temp })
         if (ptr) (void)hipFree(ptr);
     w = NearWork{};
 }
@@ -124,7 +131,10 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&w.count), np * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.start), np * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.cursor), np * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.grouped), npairs * sizeof(NearPair));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.origin), npairs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&w.temp, std::max<size_t>(w.temp_bytes, 1));
     if (e != hipSuccess) {
@@ -157,8 +167,10 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
     e = hipcub::DeviceScan::ExclusiveSum(w.temp, bytes, w.count, w.start, (int)n, s);
     if (e != hipSuccess) return e;
     scatter_pairs_kernel<<<grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40)), kBlock, 0, s>>>(
-        list, ctr, cap, w.start, w.cursor, w.sorted);
-    sort_segments_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(w.start, w.count, n, w.sorted);
+        list, ctr, cap, w.start, w.cursor, w.grouped, w.origin);
+    const int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    rank_sort_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(w.start, w.count, n, w.grouped, w.origin, w.sorted, w.slot);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
-// Field-point ordering for the distance-ratio rule choice: points are sorted along a
-// Morton (Z-order) curve so that the points of one wavefront lie close together and
-// mostly choose the same rule level for a given element.  Results are scattered back to
-// the caller's order afterwards.
+// Field-point ordering: points are sorted along a Morton (Z-order) curve so that the
+// points of one wavefront lie close together, mostly choose the same rule level for a
+// given element (rule choice by distance ratio) and are near the same elements.  Results
+// are scattered back to the caller's order afterwards.
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"

@@ -56,10 +56,10 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
     const int64_t blocks = (M + kPointsPerBlock - 1) / kPointsPerBlock;
     max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(kSlotSplit, kWavesTarget / std::max<int64_t>(1, blocks)));
     const unsigned long long near0 = (unsigned long long)std::max<int64_t>(1 << 16, 16 * M);
-    // points, results, partial sums, near list (+ its sorted copy and 4 result rows) and
+    // points, results, partial sums, near list (+ its regrouping and 4 result rows) and
     // the per-point near-field segments
     const size_t slot_bytes = (size_t)M * 8 * (3 + 1 + 3 + 4 * (size_t)max_split_) + (size_t)M * 12 +
-                              near0 * (2 * sizeof(NearPair) + 4 * sizeof(double)) + 4096;
+                              near0 * (3 * sizeof(NearPair) + 8 + 4 * sizeof(double)) + 4096;
     int n_slots = (int)std::min<size_t>((size_t)cfg.n_streams, cfg.mem_budget_bytes / slot_bytes);
     if (n_slots < 1) {
         err = "memory budget too small for one batch slot";
@@ -244,8 +244,9 @@ bool Server::launch(Slot& s, std::string& err)
     na.K = K;
     na.phi = s.d_phi;
     na.E = s.d_E;
-    na.near_list = s.nw.sorted;
+    na.near_list = s.d_near;
     na.near_cap = s.near_cap;
+    na.slot = s.nw.slot;
     na.res = s.nw.res;
     na.res_stride = s.near_cap;
     na.ctr = s.d_ctr;
