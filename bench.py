@@ -275,6 +275,21 @@ def main():
             out["gradient"][prec]["max_norm_err"] = float(e.max())
             out["gradient"][prec]["median_norm_err"] = float(np.median(e))
         out["mixed"]["within_1e-6"] = acc["mixed"]["max_norm_err_phi"] <= 1e-6 and acc["mixed"]["max_norm_err_E"] <= 1e-6
+        # the paper's plain relative error where it is well conditioned: sigma = 1 on every
+        # element (no cancellation between elements), same sampled points
+        log("plain relative error with sigma = 1")
+        ones = np.ones(w.n_elements)
+        ref1 = oracle.evaluate(w.tri, w.rect, ones, w.points[idx], oracle.params(33, 7))
+        ctx.upload_densities(ones)
+        sub = torch.tensor(np.ascontiguousarray(w.points[idx].T), dtype=torch.float64, device=dev)
+        plain = {}
+        for prec in ("fp64", "mixed"):
+            p1, _, _ = ctx.eval(sub, prec)
+            r = np.abs(p1.cpu().numpy() - ref1["phi"]) / np.abs(ref1["phi"])
+            plain[prec] = {"max_rel_err_phi": float(r.max()), "median_rel_err_phi": float(np.median(r))}
+        ctx.upload_densities(w.sigma)
+        acc["sigma_one_plain"] = plain
+        out["mixed"]["plain_rel_err_sigma_one_within_1e-6"] = plain["mixed"]["max_rel_err_phi"] <= 1e-6
 
         # collocation product: nested cylinders, 200,000 elements, 8 right-hand sides
         log("collocation: nested cylinders, 200,000 elements, 8 right-hand sides")
