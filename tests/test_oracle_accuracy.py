@@ -61,7 +61,7 @@ def test_triangle_rules_reach_paper_accuracy_at_their_dr_limit(orc, n):
     prm = orc.params(tri_rule=n)
     ep, ee = mean_errors(orc, 0, prm, dr, 60, 100 + n)
     assert ep < 3.0 * GOLD["level"], ep
-    # the field limits are "slightly higher": at twice the potential's limit the field
+    # the field limits lie a little above the potential's: at twice the potential's limit the field
     # error is at the few-1e-15 level as well
     _, ee2 = mean_errors(orc, 0, prm, 2 * dr, 60, 200 + n)
     assert ee2 < 1e-14, ee2
@@ -131,7 +131,7 @@ LEVELS_RECT = [(7, 0), (12, 1), (17, 2)]
 
 @pytest.mark.parametrize("n,lv", LEVELS_TRI)
 def test_dr_rule_levels_triangles(orc, n, lv):
-    """Sec. 4: pick the rule by distance ratio, with the field's (slightly higher) limits.
+    """Sec. 4: pick the rule by distance ratio, with the field's limits (a little above the potential's).
     At each level's lower limit the chosen rule is at the rounding floor for phi and E."""
     dr = orc.TRI_DR[lv]
     prm = orc.params(dr_rules=True)
