@@ -78,3 +78,34 @@ def test_null_argument_errors_of_newer_entry_points(lib):
     assert lib.bemc_eval_gradient(None, None, 0, 0, 0, None, None) == -1
     assert lib.bemc_set_dr_rules(None, 1, None, None) == -1
     assert lib.bemc_solve_densities(None, None, None, ctypes.c_double(1e-10), 10, 10, 0, None, None) == -1
+
+
+@pytest.mark.parametrize("lang,std", [("c", "c99"), ("c++", "c++17")])
+def test_header_is_plain_c_and_cxx(lang, std):
+    """The boundary header needs no HIP or torch include and compiles as C99 and C++."""
+    compiler = "gcc" if lang == "c" else "g++"
+    r = subprocess.run([compiler, f"-std={std}", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", lang, HEADER],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_c_program_links_against_the_library(tmp_path, lib):
+    """A plain C caller: declares nothing itself, links libbemc.so, and gets errors (not
+    crashes) for invalid calls on a machine without a GPU."""
+    src = tmp_path / "caller.c"
+    src.write_text(
+        '#include "bemc.h"\n#include <stdio.h>\n'
+        "int main(void) {\n"
+        "    bemc_handle h = 0;\n"
+        "    int rc = bemc_create(0, 0);\n"
+        '    printf("%d %d %s\\n", rc, bemc_rule_size(12), bemc_last_error());\n'
+        "    (void)h;\n"
+        "    return rc == BEMC_E_INVALID_ARG && bemc_rule_size(12) == 12 ? 0 : 1;\n"
+        "}\n")
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L", libdir, "-lbemc", f"-Wl,-rpath,{libdir}"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
