@@ -270,11 +270,14 @@ int bemc_server_start(bemc_handle h, const bemc_server_config* cfg);
 int bemc_server_submit(bemc_handle h, const double* pts_host, int64_t n, double* phi_host,
                        double* E_host, uint64_t* ticket);
 
-/* Non-blocking status of a query.  Errors: INVALID_ARG (unknown ticket). */
+/* Non-blocking status of a query.  Errors: INVALID_ARG (unknown ticket, or a ticket whose
+ * completion bemc_server_wait has already returned). */
 int bemc_server_poll(bemc_handle h, uint64_t ticket, bemc_query_info* info);
 
 /* Block until the query is done (timeout_s < 0: no limit).  Returns its status, or
- * BEMC_E_INVALID_ARG for an unknown ticket or when the timeout expired. */
+ * BEMC_E_INVALID_ARG for an unknown ticket or when the timeout expired.  Once it has
+ * returned a completed query, the server forgets the ticket (its record is released, so a
+ * long-running server does not accumulate finished queries). */
 int bemc_server_wait(bemc_handle h, uint64_t ticket, double timeout_s, bemc_query_info* info);
 
 /* Finish all submitted queries, stop the scheduler and free the batch buffers. */

@@ -149,6 +149,7 @@ int Server::wait(uint64_t ticket, double timeout_s, bemc_query_info* info)
         return 2;
     }
     *info = queries_[ticket].info;
+    queries_.erase(ticket);  // delivered: the record is released
     return 0;
 }
 

@@ -105,6 +105,8 @@ def test_admission_and_latency_fields(setup):
     phi = np.empty(len(q))
     t = ctx.server_submit(q, phi)  # field not requested
     info = ctx.server_wait(t, 60.0)
+    with pytest.raises(bemc.BemcError):  # delivered: the server has released the ticket
+        ctx.server_poll(t)
     assert info["done"] == 1 and info["end_s"] >= info["start_s"] >= info["submit_s"] >= 0
     assert np.all(np.isfinite(phi))
     t0 = ctx.server_submit(np.zeros((0, 3)), np.empty(0))  # empty query
