@@ -414,3 +414,28 @@ def test_dr_rules_full_size_sampled():
         print(f"dr full-size {prec}: phi {ep.max():.2e} E {ee.max():.2e}; terms {st['node_interactions']:.3e}, "
               f"far {st['far_ms']:.1f} ms")
         assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_translation_far_from_the_origin(cyl, precision):
+    """The same geometry and points moved by (1e3, -2e3, 5e2), i.e. coordinates 1e5 times the
+    element size: offsets are formed relative to element centroids (far field) and first
+    vertices (near field), so parity with the oracle on the same moved inputs holds at the
+    usual tolerance.  (Against the unmoved run the inputs themselves differ: rounding the
+    coordinates at 2e3 moves a point by ~2e-13, which is 1e-8 of its height above an element
+    at 1e-3 L.)"""
+    w, _ = cyl
+    shift = np.array([1e3, -2e3, 5e2])
+    tri = w.tri + np.tile(shift, 3)
+    rect = w.rect.copy()
+    rect[:, 0:3] += shift
+    pts = w.points + shift
+    ref = oracle.evaluate(tri, rect, w.sigma[0], pts, oracle.params(33, 7), with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(w.sigma)
+    phi, E, _ = run_gpu(ctx, pts, precision)
+    ctx.close()
+    ep, ee = nerr(phi, E, ref)
+    print(f"translated {precision}: phi {ep.max():.2e} E {ee.max():.2e}")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
