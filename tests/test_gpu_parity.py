@@ -439,3 +439,36 @@ def test_translation_far_from_the_origin(cyl, precision):
     ep, ee = nerr(phi, E, ref)
     print(f"translated {precision}: phi {ep.max():.2e} E {ee.max():.2e}")
     assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+
+
+def test_million_elements_sampled():
+    """1,000,000 elements (the serving geometry) and 200,000 points on particle tracks
+    inside it, plus points near its elements: FP64 and mixed, a sample checked against the
+    oracle (element indices, chunking and the near-list regrouping at a million elements)."""
+    torch = torch_mod()
+    g = W.serving_geometry()
+    rng = np.random.default_rng(61)
+    tracks = np.concatenate([W.serving_query(i, 20_000) for i in range(9)])
+    near, _ = W.near_points(g.tri, g.rect, 20_000, rng)
+    pts = np.concatenate([tracks, near])
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(g.tri, g.rect)
+    ctx.upload_densities(g.sigma)
+    tp = torch.tensor(np.ascontiguousarray(pts.T), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        phi, E, _ = ctx.eval(tp, prec)
+        torch.cuda.synchronize()
+        res[prec] = (phi.cpu().numpy(), E.cpu().numpy().T.copy(), ctx.stats())
+    ctx.close()
+    idx = np.concatenate([rng.choice(tracks.shape[0], 24, replace=False),
+                          tracks.shape[0] + rng.choice(near.shape[0], 24, replace=False)])
+    ref = oracle.evaluate(g.tri, g.rect, g.sigma[0], pts[idx], oracle.params(33, 7), with_abs=True)
+    for prec in ("fp64", "mixed"):
+        phi, E, st = res[prec]
+        assert st["pairs"] == pts.shape[0] * 1_000_000 and st["near_pairs"] > 0
+        ep, ee = nerr(phi[idx], E[idx], ref)
+        print(f"1M elements {prec}: phi {ep.max():.2e} E {ee.max():.2e}; near pairs {st['near_pairs']}, "
+              f"far {st['far_ms']:.0f} ms")
+        assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
+        assert np.all(np.isfinite(phi)) and np.all(np.isfinite(E))
