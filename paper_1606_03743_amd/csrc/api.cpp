@@ -67,13 +67,11 @@ struct bemc_context {
 
     // rule tables (device)
     double *d_tri = nullptr, *d_rect = nullptr;
-    float *d_tri32 = nullptr, *d_rect32 = nullptr;
     int nt = 0, nr = 0;
     // rule choice by distance ratio: level tables and limits
     bool dr_rules = false;
     double tri_dr[3] = { 100.0, 25.0, 10.0 }, rect_dr[3] = { 150.0, 40.0, 15.0 };
     double *d_lv_tri = nullptr, *d_lv_rect = nullptr;
-    float *d_lv_tri32 = nullptr, *d_lv_rect32 = nullptr;
     int lv_tri_off[5] = { 0, 0, 0, 0, 0 }, lv_rect_off[5] = { 0, 0, 0, 0, 0 };
     // Morton ordering workspace
     OrderWork ow{};
@@ -85,9 +83,8 @@ struct bemc_context {
     // elements (device)
     int64_t n_tri = 0, n_rect = 0, ne = 0;
     std::vector<double> h_area, h_L;  // host copies
-    double *d_geom = nullptr, *d_cen = nullptr, *d_thr2 = nullptr, *d_off = nullptr, *d_L = nullptr,
-           *d_area = nullptr, *d_nrm = nullptr, *d_q = nullptr, *d_qc = nullptr;
-    float* d_off32 = nullptr;
+    double *d_geom = nullptr, *d_cen = nullptr, *d_thr2 = nullptr, *d_frame = nullptr, *d_loc = nullptr,
+           *d_L = nullptr, *d_area = nullptr, *d_nrm = nullptr, *d_q = nullptr, *d_qc = nullptr;
     int n_rhs = 0;
     bool have_geometry = false;
 
@@ -123,7 +120,7 @@ struct bemc_context {
 Elements bemc_context::elements() const
 {
     Elements e{};
-    e.geom = d_geom; e.cen = d_cen; e.thr2 = d_thr2; e.off = d_off; e.off32 = d_off32; e.L = d_L;
+    e.geom = d_geom; e.cen = d_cen; e.thr2 = d_thr2; e.frame = d_frame; e.loc = d_loc; e.L = d_L;
     e.area = d_area; e.nrm = d_nrm; e.q = d_q; e.ne = ne; e.n_tri = (int)n_tri; e.n_rhs = n_rhs;
     return e;
 }
@@ -131,7 +128,7 @@ Elements bemc_context::elements() const
 RuleTables bemc_context::rules() const
 {
     RuleTables r{};
-    r.tri = d_tri; r.rect = d_rect; r.tri32 = d_tri32; r.rect32 = d_rect32; r.nt = nt; r.nr = nr;
+    r.tri = d_tri; r.rect = d_rect; r.nt = nt; r.nr = nr;
     return r;
 }
 
@@ -152,17 +149,12 @@ bool rect_rule_nodes(int spec, std::vector<RectNode>& rn)
 {
     return spec > 0 ? rectangle_gauss_rule(spec, rn) : rectangle_table_rule(-spec, rn);
 }
-// FP64 and FP32 copies of a node table on the device
-int upload_table(const std::vector<double>& t64, double** d64, float** d32)
+// a node table on the device
+int upload_table(const std::vector<double>& t64, double** d64)
 {
-    std::vector<float> t32(t64.size());
-    for (size_t i = 0; i < t64.size(); ++i) t32[i] = (float)t64[i];
     dev_free(*d64);
-    dev_free(*d32);
     HIP_TRY(dev_alloc(d64, t64.size()));
-    HIP_TRY(dev_alloc(d32, t32.size()));
     HIP_TRY(hipMemcpy(*d64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(*d32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
     return BEMC_OK;
 }
 }  // namespace
@@ -177,9 +169,9 @@ int bemc_context::set_rules_tables()
     std::vector<double> t64, r64;
     pack_tri(tn, t64);
     pack_rect(rn, r64);
-    int rc = upload_table(t64, &d_tri, &d_tri32);
+    int rc = upload_table(t64, &d_tri);
     if (rc) return rc;
-    if ((rc = upload_table(r64, &d_rect, &d_rect32))) return rc;
+    if ((rc = upload_table(r64, &d_rect))) return rc;
     nt = (int)tn.size();
     nr = (int)rn.size();
     // levels of the distance-ratio rule choice: 7 / 12 / 19 / tri_rule and B2 / B3 / B4 / rect rule
@@ -201,15 +193,15 @@ int bemc_context::set_rules_tables()
         lv_tri_off[l + 1] = lv_tri_off[l] + (int)a.size();
         lv_rect_off[l + 1] = lv_rect_off[l] + (int)b.size();
     }
-    if ((rc = upload_table(lt, &d_lv_tri, &d_lv_tri32))) return rc;
-    if ((rc = upload_table(lr, &d_lv_rect, &d_lv_rect32))) return rc;
+    if ((rc = upload_table(lt, &d_lv_tri))) return rc;
+    if ((rc = upload_table(lr, &d_lv_rect))) return rc;
     return ok();
 }
 
 LevelRules bemc_context::levels() const
 {
     LevelRules L{};
-    L.tab.tri = d_lv_tri; L.tab.rect = d_lv_rect; L.tab.tri32 = d_lv_tri32; L.tab.rect32 = d_lv_rect32;
+    L.tab.tri = d_lv_tri; L.tab.rect = d_lv_rect;
     L.tab.nt = lv_tri_off[4]; L.tab.nr = lv_rect_off[4];
     for (int i = 0; i < 5; ++i) { L.tri_off[i] = lv_tri_off[i]; L.rect_off[i] = lv_rect_off[i]; }
     for (int i = 0; i < 3; ++i) {
@@ -456,7 +448,7 @@ int bemc_create(int device, bemc_handle* out)
 
 static void free_elements(bemc_context* h)
 {
-    dev_free(h->d_geom); dev_free(h->d_cen); dev_free(h->d_thr2); dev_free(h->d_off); dev_free(h->d_off32);
+    dev_free(h->d_geom); dev_free(h->d_cen); dev_free(h->d_thr2); dev_free(h->d_frame); dev_free(h->d_loc);
     dev_free(h->d_L); dev_free(h->d_area); dev_free(h->d_nrm); dev_free(h->d_q); dev_free(h->d_qc);
     h->n_rhs = 0;
     h->have_geometry = false;
@@ -469,8 +461,8 @@ int bemc_destroy(bemc_handle h)
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     free_elements(h);
-    dev_free(h->d_tri); dev_free(h->d_rect); dev_free(h->d_tri32); dev_free(h->d_rect32);
-    dev_free(h->d_lv_tri); dev_free(h->d_lv_rect); dev_free(h->d_lv_tri32); dev_free(h->d_lv_rect32);
+    dev_free(h->d_tri); dev_free(h->d_rect);
+    dev_free(h->d_lv_tri); dev_free(h->d_lv_rect);
     h->free_order();
     dev_free(h->d_near); dev_free(h->d_ctr); dev_free(h->d_partial);
     h->free_near_work();
@@ -526,9 +518,8 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     if (ne >= (1ll << 31)) return fail(BEMC_E_LIMIT, "too many elements (%lld)", (long long)ne);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
-    std::vector<double> geom(9 * (size_t)ne), cen(3 * (size_t)ne), thr2((size_t)ne), off(9 * (size_t)ne, 0.0),
-        L((size_t)ne), area((size_t)ne), nrm(3 * (size_t)ne);
-    std::vector<float> off32(9 * (size_t)ne, 0.0f);
+    std::vector<double> geom(9 * (size_t)ne), cen(3 * (size_t)ne), thr2((size_t)ne), frame(9 * (size_t)ne),
+        loc(6 * (size_t)ne, 0.0), L((size_t)ne), area((size_t)ne), nrm(3 * (size_t)ne);
     auto at = [ne](std::vector<double>& v, int comp, int64_t e) -> double& { return v[(size_t)comp * ne + e]; };
     for (int64_t e = 0; e < ne; ++e) {
         const bool is_tri = e < n_tri;
@@ -537,7 +528,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
             if (!std::isfinite(g[c])) return fail(BEMC_E_NONFINITE, "element %lld has a non-finite coordinate", (long long)e);
             at(geom, c, e) = g[c];
         }
-        double C[3], N[3], a, Lh;
+        double C[3], N[3], F1[3], a, Lh;  // F1: first in-plane axis of the element frame
         if (is_tri) {
             const double *A = g, *B = g + 3, *Cv = g + 6;
             const double u[3] = { B[0] - A[0], B[1] - A[1], B[2] - A[2] };
@@ -557,11 +548,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
             for (int c = 0; c < 3; ++c) {
                 C[c] = (A[c] + B[c] + Cv[c]) / 3.0;
                 N[c] /= n2;
-            }
-            for (int c = 0; c < 3; ++c) {
-                at(off, c, e) = A[c] - C[c];
-                at(off, 3 + c, e) = B[c] - C[c];
-                at(off, 6 + c, e) = Cv[c] - C[c];
+                F1[c] = u[c] / lc;  // along B - A
             }
         } else {
             const double *P0 = g, *e1 = g + 3, *e2 = g + 6;
@@ -580,19 +567,35 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
             for (int c = 0; c < 3; ++c) {
                 C[c] = P0[c] + 0.5 * e1[c] + 0.5 * e2[c];  // Eq. 3.2: Q_cen
                 N[c] /= n2;
-                at(off, c, e) = 0.5 * e1[c];      // (a/2) u_x
-                at(off, 3 + c, e) = 0.5 * e2[c];  // (b/2) u_y
+                F1[c] = e2[c] / lb;  // along the second side
             }
         }
+        // element frame: F1, F2 = N x F1 in the plane, N the normal
+        const double F2[3] = { N[1] * F1[2] - N[2] * F1[1], N[2] * F1[0] - N[0] * F1[2], N[0] * F1[1] - N[1] * F1[0] };
         for (int c = 0; c < 3; ++c) {
             at(cen, c, e) = C[c];
             at(nrm, c, e) = N[c];
+            at(frame, c, e) = F1[c];
+            at(frame, 3 + c, e) = F2[c];
+            at(frame, 6 + c, e) = N[c];
+        }
+        auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+        if (is_tri) {  // in-plane coordinates of the vertices relative to the centroid
+            for (int m = 0; m < 3; ++m) {
+                const double d[3] = { g[3 * m] - C[0], g[3 * m + 1] - C[1], g[3 * m + 2] - C[2] };
+                at(loc, 2 * m, e) = dot(d, F1);
+                at(loc, 2 * m + 1, e) = dot(d, F2);
+            }
+        } else {  // half sides: e1 / 2 = gamma F1 + beta F2, e2 / 2 = alpha F1
+            const double h1[3] = { 0.5 * g[3], 0.5 * g[4], 0.5 * g[5] };
+            at(loc, 0, e) = dot(h1, F1);
+            at(loc, 1, e) = dot(h1, F2);
+            at(loc, 2, e) = 0.5 * std::sqrt(dot(g + 6, g + 6));
         }
         area[(size_t)e] = a;
         L[(size_t)e] = Lh;
         thr2[(size_t)e] = (h->near_dr * Lh) * (h->near_dr * Lh);
     }
-    for (size_t i = 0; i < off.size(); ++i) off32[i] = (float)off[i];
 
     HIP_TRY(hipSetDevice(h->device));
     HIP_TRY(hipStreamSynchronize(s));
@@ -601,7 +604,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     h->n_rect = n_rect;
     h->ne = ne;
     if (dev_alloc(&h->d_geom, geom.size()) || dev_alloc(&h->d_cen, cen.size()) || dev_alloc(&h->d_thr2, thr2.size()) ||
-        dev_alloc(&h->d_off, off.size()) || dev_alloc(&h->d_off32, off32.size()) || dev_alloc(&h->d_L, L.size()) ||
+        dev_alloc(&h->d_frame, frame.size()) || dev_alloc(&h->d_loc, loc.size()) || dev_alloc(&h->d_L, L.size()) ||
         dev_alloc(&h->d_area, area.size()) || dev_alloc(&h->d_nrm, nrm.size())) {
         (void)hipGetLastError();
         free_elements(h);
@@ -610,8 +613,8 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     HIP_TRY(hipMemcpyAsync(h->d_geom, geom.data(), geom.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_cen, cen.data(), cen.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_thr2, thr2.data(), thr2.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(h->d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(h->d_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_frame, frame.data(), frame.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->d_loc, loc.data(), loc.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_L, L.data(), L.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_area, area.data(), area.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_nrm, nrm.data(), nrm.size() * 8, hipMemcpyHostToDevice, s));

@@ -35,10 +35,8 @@ constexpr int kMinDrRectNodes = 17;
 // Rule tables in device memory: triangle nodes as (la, lb, lc, w), rectangle nodes as
 // (x, y, w, 0); FP32 copies for the mixed path.
 struct RuleTables {
-    const double* tri;    // [nt][4]
-    const double* rect;   // [nr][4]
-    const float* tri32;   // [nt][4]
-    const float* rect32;  // [nr][4]
+    const double* tri;    // [nt][4]  la, lb, lc, w
+    const double* rect;   // [nr][4]  x, y, w, 0  (Gauss-Legendre n x n: node i n + j = (x_i, x_j))
     int nt, nr;
 };
 
@@ -47,8 +45,10 @@ struct Elements {
     const double* geom;  // [9][ne]  input geometry: A,B,C  or  P0,e1,e2
     const double* cen;   // [3][ne]  centroid
     const double* thr2;  // [ne]     (near_dr * L)^2
-    const double* off;   // [9][ne]  tri: A-c, B-c, C-c;  rect: e1/2, e2/2, 0
-    const float* off32;  // [9][ne]  same, FP32
+    const double* frame; // [9][ne]  orthonormal frame f1, f2 (in the plane), f3 (normal);
+                         //          rectangles: f1 along e2
+    const double* loc;   // [6][ne]  tri: in-plane coordinates (f1, f2) of A-c, B-c, C-c;
+                         //          rect: gamma = f1.e1/2, beta = f2.e1/2, alpha = |e2|/2, 0, 0, 0
     const double* L;     // [ne]     average side length
     const double* area;  // [ne]
     const double* nrm;   // [3][ne]  unit normal

@@ -2,8 +2,8 @@
 // BEM triangles and rectangles (Glueck & Hilk, arXiv:1606.03743).
 //
 //  far_eval_kernel     PPT field points per lane; element tiles are staged in LDS with
-//                      their Gaussian points generated on the fly from the centroid offsets
-//                      (Eq. 3.2 / 3.3); FP64 distance-ratio test per pair (Sec. 2), near
+//                      their Gaussian points generated on the fly in each element's own
+//                      frame (Eq. 3.2 / 3.3); FP64 distance-ratio test per pair (Sec. 2), near
 //                      pairs compacted per wavefront into a dense list; far pairs summed as
 //                      point charges (Sec. 4, Eq. 4.1), potential and field from the same
 //                      nodes.  FP64 or mixed (FP32 node sums); one rule per element kind or
@@ -77,21 +77,42 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 }
 
 // ---------------------------------------------------------------- LDS staging ------
-struct TileLds64 {
-    double4 node[kTileNodes];  // centroid offset (x, y, z) and weight
-    double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
-    double q[kMaxRhs][kMaxTileElems];
+// Each element is summed in its own orthonormal frame: origin at the centroid, f1 and f2
+// in its plane, f3 its unit normal.  A Gaussian point has in-plane coordinates (a, b) and
+// a field point the coordinates (p1, p2, p3), so r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2: two
+// differences per node instead of three, with p3^2 formed once per pair.  The sums are
+// rotated back to the global axes once per pair.  For rectangles f1 runs along the second
+// side, so the nodes of a tensor Gauss-Legendre rule that share their first coordinate
+// share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is then formed once per group of seven.
+template <bool MIXED>
+struct NodeTile;
+template <>
+struct NodeTile<false> {
+    double2 ab[kTileNodes];  // (a, b)
+    double w[kTileNodes];    // weight (unit element charge)
 };
-struct TileLds32 {
-    float4 node[kTileNodes];
-    double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
-    double q[kMaxRhs][kMaxTileElems];
+template <>
+struct NodeTile<true> {
+    float4 n[kTileNodes];  // a, b, weight, unused
 };
 
-// Gaussian points of elements [t0, t0 + te) relative to their centroids.
-template <bool TRI, bool MIXED, typename Lds>
-__device__ __forceinline__ void stage_tile(Lds& s, const Elements& el, const RuleTables& R, int nn, int64_t t0,
-                                           int te, int rhs0, int nrhs)
+template <bool MIXED, int NRHS>
+struct TileLds {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    NodeTile<MIXED> nd;
+    double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
+    T f[9][kMaxTileElems];  // f1, f2, f3 (x, y, z each), in the precision of the node sums
+    double q[NRHS][kMaxTileElems];
+};
+
+// Gaussian points of elements [t0, t0 + te) in their frames (Eq. 3.2 / 3.3): triangle
+// (a, b) = la A' + lb B' + lc C' from the in-plane coordinates of the vertices relative to
+// the centroid; rectangle a = x gamma + y alpha, b = x beta for the rule point (x, y) in
+// [-1, 1]^2 (alpha = |e2| / 2; beta, gamma the components of e1 / 2 across and along e2).
+// FP32 tiles hold the FP64 values rounded once; the mixed path also rotates in FP32.
+template <bool TRI, bool MIXED, int NRHS>
+__device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elements& el, const RuleTables& R, int nn,
+                                           int64_t t0, int te, int rhs0, int nrhs)
 {
     const int64_t ne = el.ne;
     for (int k = threadIdx.x; k < te; k += kBlock) {
@@ -100,63 +121,59 @@ __device__ __forceinline__ void stage_tile(Lds& s, const Elements& el, const Rul
         s.cy[k] = el.cen[ne + e];
         s.cz[k] = el.cen[2 * ne + e];
         s.thr2[k] = el.thr2[e];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s.f[c][k] = (typename TileLds<MIXED, NRHS>::T)el.frame[(int64_t)c * ne + e];
         for (int r = 0; r < nrhs; ++r) s.q[r][k] = el.q[(int64_t)(rhs0 + r) * ne + e];
     }
     for (int k = threadIdx.x; k < te * nn; k += kBlock) {
         const int j = k / nn;
         const int i = k - j * nn;
         const int64_t e = t0 + j;
-        if (!MIXED) {
-            double x, y, z, w;
-            if (TRI) {
-                const double la = R.tri[4 * i], lb = R.tri[4 * i + 1], lc = R.tri[4 * i + 2];
-                w = R.tri[4 * i + 3];
-                x = la * el.off[e] + lb * el.off[3 * ne + e] + lc * el.off[6 * ne + e];
-                y = la * el.off[ne + e] + lb * el.off[4 * ne + e] + lc * el.off[7 * ne + e];
-                z = la * el.off[2 * ne + e] + lb * el.off[5 * ne + e] + lc * el.off[8 * ne + e];
-            } else {
-                const double u = R.rect[4 * i], v = R.rect[4 * i + 1];
-                w = R.rect[4 * i + 2];
-                x = u * el.off[e] + v * el.off[3 * ne + e];
-                y = u * el.off[ne + e] + v * el.off[4 * ne + e];
-                z = u * el.off[2 * ne + e] + v * el.off[5 * ne + e];
-            }
-            reinterpret_cast<double4*>(s.node)[k] = make_double4(x, y, z, w);
+        double a, b, w;
+        if (TRI) {
+            const double la = R.tri[4 * i], lb = R.tri[4 * i + 1], lc = R.tri[4 * i + 2];
+            w = R.tri[4 * i + 3];
+            a = la * el.loc[e] + lb * el.loc[2 * ne + e] + lc * el.loc[4 * ne + e];
+            b = la * el.loc[ne + e] + lb * el.loc[3 * ne + e] + lc * el.loc[5 * ne + e];
         } else {
-            float x, y, z, w;
-            if (TRI) {
-                const float la = R.tri32[4 * i], lb = R.tri32[4 * i + 1], lc = R.tri32[4 * i + 2];
-                w = R.tri32[4 * i + 3];
-                x = la * el.off32[e] + lb * el.off32[3 * ne + e] + lc * el.off32[6 * ne + e];
-                y = la * el.off32[ne + e] + lb * el.off32[4 * ne + e] + lc * el.off32[7 * ne + e];
-                z = la * el.off32[2 * ne + e] + lb * el.off32[5 * ne + e] + lc * el.off32[8 * ne + e];
-            } else {
-                const float u = R.rect32[4 * i], v = R.rect32[4 * i + 1];
-                w = R.rect32[4 * i + 2];
-                x = u * el.off32[e] + v * el.off32[3 * ne + e];
-                y = u * el.off32[ne + e] + v * el.off32[4 * ne + e];
-                z = u * el.off32[2 * ne + e] + v * el.off32[5 * ne + e];
-            }
-            reinterpret_cast<float4*>(s.node)[k] = make_float4(x, y, z, w);
+            const double x = R.rect[4 * i], y = R.rect[4 * i + 1];
+            w = R.rect[4 * i + 2];
+            a = x * el.loc[e] + y * el.loc[2 * ne + e];
+            b = x * el.loc[ne + e];
+        }
+        if constexpr (MIXED) {
+            s.nd.n[k] = make_float4((float)a, (float)b, (float)w, 0.0f);
+        } else {
+            s.nd.ab[k] = make_double2(a, b);
+            s.nd.w[k] = w;
         }
     }
 }
 
-// ------------------------------------------------------------ far field: eval -------
-// GRAD == false: per point phi, Ex, Ey, Ez.  GRAD == true: the field gradient dE_i/dx_j as
-// xx, yy, zz, xy, xz, yz (each point charge contributes q (delta_ij r^2 - 3 d_i d_j) / r^5).
-template <bool GRAD>
+// ------------------------------------------------------------ far field: sums -------
+// kFarField: per point phi, Ex, Ey, Ez.  kFarGrad: the field gradient dE_i/dx_j as xx, yy,
+// zz, xy, xz, yz (each point charge contributes q (delta_ij r^2 - 3 d_i d_j) / r^5).
+// kFarPhi: the potential only (collocation).
+enum FarMode { kFarField = 0, kFarGrad = 1, kFarPhi = 2 };
+
+template <int MODE>
 struct Sums {
-    static constexpr int kOut = GRAD ? 6 : 4;  // accumulated outputs per point
-    static constexpr int kNode = GRAD ? 7 : 4; // per-element node sums per point
+    static constexpr int kOut = MODE == kFarGrad ? 6 : (MODE == kFarField ? 4 : 1);   // outputs per point
+    static constexpr int kNode = MODE == kFarGrad ? 7 : (MODE == kFarField ? 4 : 1);  // element sums per point
 };
 
-template <int PPT, bool GRAD>
+// Field points of one lane, and their offsets from the element in hand in its frame.
+template <int PPT, int MODE>
 struct PointSet {
     double x[PPT], y[PPT], z[PPT];
     bool valid[PPT];
     uint32_t idx[PPT];
-    double acc[Sums<GRAD>::kOut][PPT];
+    double acc[Sums<MODE>::kOut][PPT];
+};
+
+template <int PPT, typename T>
+struct Local {
+    T p1[PPT], p2[PPT], p3[PPT], h[PPT];  // h = p3^2
 };
 
 // Runs term(i) for the nodes i = 0 .. n-1 of one element.  Long rules (and run-time
@@ -180,149 +197,291 @@ __device__ __forceinline__ void for_nodes(int n, Term term)
     for (; i < n; ++i) term(i);
 }
 
-// Terms of one Gaussian point Q (offset and weight) for PPT field points.
-template <int PPT, bool GRAD>
-__device__ __forceinline__ void node_term64(const double4 Q, const double (&dx)[PPT], const double (&dy)[PPT],
-                                            const double (&dz)[PPT], double (&o)[Sums<GRAD>::kNode][PPT])
+// Element sums in the frame, per field point (unit element charge):
+//   kFarField  (sum w/r, sum w da/r^3, sum w db/r^3, sum w/r^3), with da = p1 - a, db = p2 - b;
+//   kFarGrad   FP64: (sum w/r^3, sum w/r^5, sum w da/r^5, sum w db/r^5, sum w da^2/r^5,
+//              sum w db^2/r^5, sum w da db/r^5), turned into the local tensor after the loop;
+//              FP32: the local tensor itself, sum w/r^3 and sum w u_i u_j / r^3 over the unit
+//              offset u = (da, db, p3)/r (xx, yy, zz, xy, xz, yz), so that no power of 1/r
+//              above the third is formed in single precision;
+//   kFarPhi    sum w/r.
+template <int PPT, int MODE>
+__device__ __forceinline__ void node_term64(double a, double b, double w, const Local<PPT, double>& L,
+                                            double (&o)[Sums<MODE>::kNode][PPT])
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double ri = rsqrt64(r2);
-        const double wr = Q.w * ri;
-        if (!GRAD) {
-            o[0][k] += wr;
+        const double da = L.p1[k] - a, db = L.p2[k] - b;
+        const double ri = rsqrt64(fma(da, da, fma(db, db, L.h[k])));
+        if constexpr (MODE == kFarPhi) {
+            o[0][k] = fma(w, ri, o[0][k]);
+        } else if constexpr (MODE == kFarField) {
+            const double wr = w * ri;
             const double w3 = wr * (ri * ri);
-            o[1][k] = fma(w3, rx, o[1][k]);
-            o[2][k] = fma(w3, ry, o[2][k]);
-            o[3][k] = fma(w3, rz, o[3][k]);
+            o[0][k] += wr;
+            o[1][k] = fma(w3, da, o[1][k]);
+            o[2][k] = fma(w3, db, o[2][k]);
+            o[3][k] += w3;
         } else {
             const double ri2 = ri * ri;
-            const double w3 = wr * ri2;
+            const double w3 = (w * ri) * ri2;
             const double w5 = w3 * ri2;
+            const double ua = w5 * da, ub = w5 * db;
             o[0][k] += w3;
-            const double ux = w5 * rx, uy = w5 * ry, uz = w5 * rz;
-            o[1][k] = fma(ux, rx, o[1][k]);
-            o[2][k] = fma(uy, ry, o[2][k]);
-            o[3][k] = fma(uz, rz, o[3][k]);
-            o[4][k] = fma(ux, ry, o[4][k]);
-            o[5][k] = fma(ux, rz, o[5][k]);
-            o[6][k] = fma(uy, rz, o[6][k]);
+            o[1][k] += w5;
+            o[2][k] += ua;
+            o[3][k] += ub;
+            o[4][k] = fma(ua, da, o[4][k]);
+            o[5][k] = fma(ub, db, o[5][k]);
+            o[6][k] = fma(ua, db, o[6][k]);
         }
     }
 }
 
-// Point-charge sums of one element (Eq. 4.1) over its Gaussian points nd[0 .. n) for PPT
-// field points given by their offsets from the element centroid; unit element charge.
-// Field: o = (sum w/r, sum w d/r^3).  Gradient: o = (sum w/r^3, sum w d_i d_j / r^5 for
-// xx, yy, zz, xy, xz, yz).  NN > 0: compile-time node count.
-template <int NN, int PPT, bool GRAD>
-__device__ __forceinline__ void node_sum64(const double4* __restrict__ nd, int nn, const double (&dx)[PPT],
-                                           const double (&dy)[PPT], const double (&dz)[PPT],
-                                           double (&o)[Sums<GRAD>::kNode][PPT])
-{
-    const int n = NN > 0 ? NN : nn;
-#pragma unroll
-    for (int c = 0; c < Sums<GRAD>::kNode; ++c)
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) o[c][k] = 0.0;
-    for_nodes<NN>(n, [&](int i) { node_term64<PPT, GRAD>(nd[i], dx, dy, dz, o); });
-}
-
-// FP32 versions.  The gradient uses unit vectors (d / r) so that no power of 1/r above the
-// third is formed in single precision.
-template <int PPT, bool GRAD>
-__device__ __forceinline__ void node_term32(const float4 Q, const float (&dx)[PPT], const float (&dy)[PPT],
-                                            const float (&dz)[PPT], float (&o)[Sums<GRAD>::kNode][PPT])
+template <int PPT, int MODE>
+__device__ __forceinline__ void node_term32(float a, float b, float w, const Local<PPT, float>& L,
+                                            float (&o)[Sums<MODE>::kNode][PPT])
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const float rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-        const float ri = rsqrt32(r2);
-        const float wr = Q.w * ri;
-        const float w3 = wr * (ri * ri);
-        if (!GRAD) {
+        const float da = L.p1[k] - a, db = L.p2[k] - b;
+        const float ri = rsqrt32(fmaf(da, da, fmaf(db, db, L.h[k])));
+        if constexpr (MODE == kFarPhi) {
+            o[0][k] = fmaf(w, ri, o[0][k]);
+        } else if constexpr (MODE == kFarField) {
+            const float wr = w * ri;
+            const float w3 = wr * (ri * ri);
             o[0][k] += wr;
-            o[1][k] = fmaf(w3, rx, o[1][k]);
-            o[2][k] = fmaf(w3, ry, o[2][k]);
-            o[3][k] = fmaf(w3, rz, o[3][k]);
+            o[1][k] = fmaf(w3, da, o[1][k]);
+            o[2][k] = fmaf(w3, db, o[2][k]);
+            o[3][k] += w3;
         } else {
+            const float w3 = (w * ri) * (ri * ri);
+            const float va = da * ri, vb = db * ri, vc = L.p3[k] * ri;
+            const float ua = w3 * va, ub = w3 * vb, uc = w3 * vc;
             o[0][k] += w3;
-            const float vx = rx * ri, vy = ry * ri, vz = rz * ri;
-            const float ux = w3 * vx, uy = w3 * vy, uz = w3 * vz;
-            o[1][k] = fmaf(ux, vx, o[1][k]);
-            o[2][k] = fmaf(uy, vy, o[2][k]);
-            o[3][k] = fmaf(uz, vz, o[3][k]);
-            o[4][k] = fmaf(ux, vy, o[4][k]);
-            o[5][k] = fmaf(ux, vz, o[5][k]);
-            o[6][k] = fmaf(uy, vz, o[6][k]);
+            o[1][k] = fmaf(ua, va, o[1][k]);
+            o[2][k] = fmaf(ub, vb, o[2][k]);
+            o[3][k] = fmaf(uc, vc, o[3][k]);
+            o[4][k] = fmaf(ua, vb, o[4][k]);
+            o[5][k] = fmaf(ua, vc, o[5][k]);
+            o[6][k] = fmaf(ub, vc, o[6][k]);
         }
     }
 }
 
-template <int NN, int PPT, bool GRAD>
-__device__ __forceinline__ void node_sum32(const float4* __restrict__ nd, int nn, const float (&dx)[PPT],
-                                           const float (&dy)[PPT], const float (&dz)[PPT],
-                                           float (&o)[Sums<GRAD>::kNode][PPT])
+// Tensor rule in groups of G nodes with the same b (kFarField and kFarPhi): per group the
+// lane forms db and (p2 - b)^2 + p3^2 once; per node one difference remains.  The
+// field's b-component and sum w/r^3 are gathered per group.
+template <int G, int PPT, int MODE>
+__device__ __forceinline__ void group_sum64(const NodeTile<false>& t, int base, const Local<PPT, double>& L,
+                                            double (&o)[Sums<MODE>::kNode][PPT])
 {
-    const int n = NN > 0 ? NN : nn;
-#pragma unroll
-    for (int c = 0; c < Sums<GRAD>::kNode; ++c)
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) o[c][k] = 0.0f;
-    for_nodes<NN>(n, [&](int i) { node_term32<PPT, GRAD>(nd[i], dx, dy, dz, o); });
-}
-
-// Element sums for the nodes [o, o + n) of element j of the tile: FP64, or FP32 on offsets
-// from the centroid with the result widened to FP64.
-template <int NN, bool MIXED, int PPT, bool GRAD, typename Lds>
-__device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const double (&dx)[PPT],
-                                            const double (&dy)[PPT], const double (&dz)[PPT],
-                                            double (&o)[Sums<GRAD>::kNode][PPT])
-{
-    if (!MIXED) {
-        node_sum64<NN, PPT, GRAD>(reinterpret_cast<const double4*>(s.node) + base, n, dx, dy, dz, o);
-    } else {
-        float fx[PPT], fy[PPT], fz[PPT], fo[Sums<GRAD>::kNode][PPT];
+    static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        const int n0 = base + g * G;
+        const double b = t.ab[n0].y;
+        double db[PPT], B[PPT], sg[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            fx[k] = (float)dx[k];
-            fy[k] = (float)dy[k];
-            fz[k] = (float)dz[k];
+            db[k] = L.p2[k] - b;
+            B[k] = fma(db[k], db[k], L.h[k]);
+            sg[k] = 0.0;
         }
-        node_sum32<NN, PPT, GRAD>(reinterpret_cast<const float4*>(s.node) + base, n, fx, fy, fz, fo);
 #pragma unroll
-        for (int c = 0; c < Sums<GRAD>::kNode; ++c)
+        for (int i = 0; i < G; ++i) {
+            const double a = t.ab[n0 + i].x, w = t.w[n0 + i];
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) o[c][k] = (double)fo[c][k];
+            for (int k = 0; k < PPT; ++k) {
+                const double da = L.p1[k] - a;
+                const double ri = rsqrt64(fma(da, da, B[k]));
+                if constexpr (MODE == kFarPhi) {
+                    o[0][k] = fma(w, ri, o[0][k]);
+                } else {
+                    const double wr = w * ri;
+                    const double w3 = wr * (ri * ri);
+                    o[0][k] += wr;
+                    o[1][k] = fma(w3, da, o[1][k]);
+                    sg[k] += w3;
+                }
+            }
+        }
+        if constexpr (MODE == kFarField) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                o[2][k] = fma(sg[k], db[k], o[2][k]);
+                o[3][k] += sg[k];
+            }
+        }
     }
 }
 
-// acc += q * (element sums of point k), in the output form
-template <int PPT, bool GRAD>
-__device__ __forceinline__ void add_element(PointSet<PPT, GRAD>& P, int k, double q,
-                                            const double (&o)[Sums<GRAD>::kNode][PPT])
+template <int G, int PPT, int MODE>
+__device__ __forceinline__ void group_sum32(const NodeTile<true>& t, int base, const Local<PPT, float>& L,
+                                            float (&o)[Sums<MODE>::kNode][PPT])
 {
-    if (!GRAD) {
+    static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        const int n0 = base + g * G;
+        const float b = t.n[n0].y;
+        float db[PPT], B[PPT], sg[PPT];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) P.acc[c][k] = fma(q, o[c][k], P.acc[c][k]);
-    } else {
-        // dE_i/dx_j = sum w (delta_ij / r^3 - 3 d_i d_j / r^5)
+        for (int k = 0; k < PPT; ++k) {
+            db[k] = L.p2[k] - b;
+            B[k] = fmaf(db[k], db[k], L.h[k]);
+            sg[k] = 0.0f;
+        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) P.acc[c][k] = fma(q, fma(-3.0, o[1 + c][k], o[0][k]), P.acc[c][k]);
+        for (int i = 0; i < G; ++i) {
+            const float4 Q = t.n[n0 + i];
 #pragma unroll
-        for (int c = 3; c < 6; ++c) P.acc[c][k] = fma(-3.0 * q, o[1 + c][k], P.acc[c][k]);
+            for (int k = 0; k < PPT; ++k) {
+                const float da = L.p1[k] - Q.x;
+                const float ri = rsqrt32(fmaf(da, da, B[k]));
+                if constexpr (MODE == kFarPhi) {
+                    o[0][k] = fmaf(Q.z, ri, o[0][k]);
+                } else {
+                    const float wr = Q.z * ri;
+                    const float w3 = wr * (ri * ri);
+                    o[0][k] += wr;
+                    o[1][k] = fmaf(w3, da, o[1][k]);
+                    sg[k] += w3;
+                }
+            }
+        }
+        if constexpr (MODE == kFarField) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                o[2][k] = fmaf(sg[k], db[k], o[2][k]);
+                o[3][k] += sg[k];
+            }
+        }
     }
 }
+
+// Sums of one element over its nodes [base, base + n) of the tile (Eq. 4.1, unit element
+// charge) in the precision T of the tile (FP64, or FP32 for the mixed path).  NN > 0:
+// compile-time node count; G > 0: tensor rule in groups of G.  Gradient: the result is the
+// local tensor (sum w/r^3; sum w d_i d_j / r^5 for xx, yy, zz, xy, xz, yz, d = (da, db, p3)).
+template <int NN, int G, bool MIXED, int PPT, int MODE, typename Lds, typename T>
+__device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const Local<PPT, T>& L,
+                                            T (&o)[Sums<MODE>::kNode][PPT])
+{
+    constexpr int S = Sums<MODE>::kNode;
+    T r[S][PPT];
+#pragma unroll
+    for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) r[c][k] = T(0);
+    const int nn = NN > 0 ? NN : n;
+    if constexpr (!MIXED) {
+        if constexpr (G > 0 && MODE != kFarGrad) {
+            group_sum64<G, PPT, MODE>(s.nd, base, L, r);
+        } else {
+            for_nodes<NN>(nn, [&](int i) {
+                const double2 ab = s.nd.ab[base + i];
+                node_term64<PPT, MODE>(ab.x, ab.y, s.nd.w[base + i], L, r);
+            });
+        }
+    } else {
+        if constexpr (G > 0 && MODE != kFarGrad) {
+            group_sum32<G, PPT, MODE>(s.nd, base, L, r);
+        } else {
+            for_nodes<NN>(nn, [&](int i) {
+                const float4 Q = s.nd.n[base + i];
+                node_term32<PPT, MODE>(Q.x, Q.y, Q.z, L, r);
+            });
+        }
+    }
+    if constexpr (MODE == kFarGrad && !MIXED) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            o[0][k] = r[0][k];
+            o[1][k] = r[4][k];
+            o[2][k] = r[5][k];
+            o[3][k] = L.h[k] * r[1][k];
+            o[4][k] = r[6][k];
+            o[5][k] = L.p3[k] * r[2][k];
+            o[6][k] = L.p3[k] * r[3][k];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) o[c][k] = r[c][k];
+    }
+}
+
+// Offsets of the lane's points from element j of the tile: D^2 in FP64 (the distance test,
+// Sec. 2) and the coordinates in the element's frame, in the precision of the node sums.
+template <int PPT, typename Lds, typename T>
+__device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[PPT], const double (&y)[PPT],
+                                         const double (&z)[PPT], double (&D2)[PPT], Local<PPT, T>& L)
+{
+    const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
+        D2[k] = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T u = (T)dx, v = (T)dy, w = (T)dz;
+        L.p1[k] = fma(u, s.f[0][j], fma(v, s.f[1][j], w * s.f[2][j]));
+        L.p2[k] = fma(u, s.f[3][j], fma(v, s.f[4][j], w * s.f[5][j]));
+        L.p3[k] = fma(u, s.f[6][j], fma(v, s.f[7][j], w * s.f[8][j]));
+        L.h[k] = L.p3[k] * L.p3[k];
+    }
+}
+
+// acc += q * (element sums of point k), rotated to the global axes in the precision of the
+// sums and accumulated in FP64
+template <int PPT, int MODE, typename Lds, typename T>
+__device__ __forceinline__ void add_element(PointSet<PPT, MODE>& P, int k, double q, const Lds& s, int j,
+                                            const Local<PPT, T>& L, const T (&o)[Sums<MODE>::kNode][PPT])
+{
+    if constexpr (MODE == kFarField) {
+        P.acc[0][k] = fma(q, (double)o[0][k], P.acc[0][k]);
+        const T t3 = L.p3[k] * o[3][k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T e = fma(s.f[c][j], o[1][k], fma(s.f[3 + c][j], o[2][k], s.f[6 + c][j] * t3));
+            P.acc[1 + c][k] = fma(q, (double)e, P.acc[1 + c][k]);
+        }
+    } else {
+        // global tensor M = F m F^T of the local one m (F: the frame vectors as columns);
+        // dE_i/dx_j = q (delta_ij sum w/r^3 - 3 M_ij)
+        const T m[3][3] = { { o[1][k], o[4][k], o[5][k] },
+                            { o[4][k], o[2][k], o[6][k] },
+                            { o[5][k], o[6][k], o[3][k] } };
+        T U[3][3];  // U[a][c] = sum_b m[a][b] f_b[c]
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                U[a][c] = fma(m[a][0], s.f[c][j], fma(m[a][1], s.f[3 + c][j], m[a][2] * s.f[6 + c][j]));
+        auto M = [&](int u, int v) -> double {
+            return (double)fma(s.f[u][j], U[0][v], fma(s.f[3 + u][j], U[1][v], s.f[6 + u][j] * U[2][v]));
+        };
+        const double s3 = (double)o[0][k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P.acc[c][k] = fma(q, fma(-3.0, M(c, c), s3), P.acc[c][k]);
+        P.acc[3][k] = fma(-3.0 * q, M(0, 1), P.acc[3][k]);
+        P.acc[4][k] = fma(-3.0 * q, M(0, 2), P.acc[4][k]);
+        P.acc[5][k] = fma(-3.0 * q, M(1, 2), P.acc[5][k]);
+    }
+}
+
+// group size of the tensor path for a rectangle rule of NN nodes (7 x 7 only)
+template <bool TRI, int NN>
+constexpr int tensor_group() { return (!TRI && NN == 49) ? 7 : 0; }
 
 // One element kind over [e_begin, e_end) with one rule; NN > 0 is the compile-time node
 // count, NN == 0 reads it at run time.
-template <int NN, bool TRI, bool MIXED, int PPT, bool GRAD, typename Lds>
-__device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT, GRAD>& P, int64_t e_begin,
+template <int NN, bool TRI, bool MIXED, int PPT, int MODE, typename Lds>
+__device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT, MODE>& P, int64_t e_begin,
                                                int64_t e_end)
 {
+    using T = typename Lds::T;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
@@ -331,23 +490,21 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
         stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, a.rhs, 1);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
-            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j], q = s.q[0][j];
-            double dx[PPT], dy[PPT], dz[PPT];
+            const double thr2 = s.thr2[j], q = s.q[0][j];
+            double D2[PPT];
+            Local<PPT, T> L;
+            to_frame(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                dx[k] = P.x[k] - cx;
-                dy[k] = P.y[k] - cy;
-                dz[k] = P.z[k] - cz;
-                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
-                nr[k] = P.valid[k] && (D2 < thr2);
+                nr[k] = P.valid[k] && (D2[k] < thr2);
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
-            double o[Sums<GRAD>::kNode][PPT];
-            element_sum<NN, MIXED, PPT, GRAD>(s, j * nn, nn, dx, dy, dz, o);
+            T o[Sums<MODE>::kNode][PPT];
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (!nr[k]) add_element<PPT, GRAD>(P, k, q, o);
+                if (!nr[k]) add_element<PPT, MODE>(P, k, q, s, j, L, o);
         }
     }
 }
@@ -358,10 +515,11 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
 // pairs needs, once, for all its lanes: a finer rule is at least as accurate at a larger
 // distance ratio, and one level per wavefront costs less than each level a lane needs.
 // N0..N3 > 0: compile-time counts.
-template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, bool GRAD, typename Lds>
-__device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, GRAD>& P, int64_t e_begin,
+template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, int MODE, typename Lds>
+__device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, MODE>& P, int64_t e_begin,
                                                   int64_t e_end, unsigned long long& terms)
 {
+    using T = typename Lds::T;
     const int* off = TRI ? a.lv.tri_off : a.lv.rect_off;
     const double* c = TRI ? a.lv.tri_c : a.lv.rect_c;
     const int o1 = off[1], o2 = off[2], o3 = off[3], nn = off[4];
@@ -373,19 +531,17 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
         stage_tile<TRI, MIXED>(s, a.el, a.lv.tab, nn, t0, te, a.rhs, 1);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
-            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j], q = s.q[0][j];
-            double dx[PPT], dy[PPT], dz[PPT];
+            const double thr2 = s.thr2[j], q = s.q[0][j];
+            double D2[PPT];
+            Local<PPT, T> L;
+            to_frame(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
             int lvl[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                dx[k] = P.x[k] - cx;
-                dy[k] = P.y[k] - cy;
-                dz[k] = P.z[k] - cz;
-                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
-                nr[k] = P.valid[k] && (D2 < thr2);
+                nr[k] = P.valid[k] && (D2[k] < thr2);
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
-                lvl[k] = D2 >= c0 * thr2 ? 0 : (D2 >= c1 * thr2 ? 1 : (D2 >= c2 * thr2 ? 2 : 3));
+                lvl[k] = D2[k] >= c0 * thr2 ? 0 : (D2[k] >= c1 * thr2 ? 1 : (D2[k] >= c2 * thr2 ? 2 : 3));
                 if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
             }
             // the finest level any lane of the wavefront needs
@@ -394,17 +550,17 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             for (int k = 0; k < PPT; ++k) mx = max(mx, lvl[k]);
             const int wl = __ballot(mx >= 3) ? 3 : (__ballot(mx >= 2) ? 2 : (__ballot(mx >= 1) ? 1 : (__ballot(mx >= 0) ? 0 : -1)));
             if (wl < 0) continue;
-            double o[Sums<GRAD>::kNode][PPT];
+            T o[Sums<MODE>::kNode][PPT];
             const int b = j * nn;
             int nw;
-            if (wl == 0) { element_sum<N0, MIXED, PPT, GRAD>(s, b, o1, dx, dy, dz, o); nw = o1; }
-            else if (wl == 1) { element_sum<N1, MIXED, PPT, GRAD>(s, b + o1, o2 - o1, dx, dy, dz, o); nw = o2 - o1; }
-            else if (wl == 2) { element_sum<N2, MIXED, PPT, GRAD>(s, b + o2, o3 - o2, dx, dy, dz, o); nw = o3 - o2; }
-            else { element_sum<N3, MIXED, PPT, GRAD>(s, b + o3, nn - o3, dx, dy, dz, o); nw = nn - o3; }
+            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE>(s, b, o1, L, o); nw = o1; }
+            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
+            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
+            else { element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE>(s, b + o3, nn - o3, L, o); nw = nn - o3; }
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (lvl[k] >= 0) {
-                    add_element<PPT, GRAD>(P, k, q, o);
+                    add_element<PPT, MODE>(P, k, q, s, j, L, o);
                     terms += (unsigned)nw;
                 }
         }
@@ -427,10 +583,10 @@ __device__ __forceinline__ void add_terms(unsigned long long terms, DevCounters*
 template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT, bool GRAD>
 __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
 {
-    using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
-    constexpr int NO = Sums<GRAD>::kOut;
-    __shared__ Lds s;
-    PointSet<PPT, GRAD> P;
+    constexpr int MODE = GRAD ? kFarGrad : kFarField;
+    constexpr int NO = Sums<MODE>::kOut;
+    __shared__ TileLds<MIXED, 1> s;
+    PointSet<PPT, MODE> P;
     const int64_t base = (int64_t)blockIdx.x * (kBlock * PPT) + threadIdx.x;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -452,12 +608,12 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
     const int64_t nr_begin = max((int64_t)a.el.n_tri, e_lo);
     if (DR) {
         unsigned long long terms = 0;
-        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, GRAD>(a, s, P, e_lo, nt_end, terms);
-        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, GRAD>(a, s, P, nr_begin, e_hi, terms);
+        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end, terms);
+        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi, terms);
         add_terms(terms, a.ctr);
     } else {
-        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, GRAD>(a, s, P, e_lo, nt_end);
-        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, GRAD>(a, s, P, nr_begin, e_hi);
+        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end);
+        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi);
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -488,6 +644,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                                                  const bool (&valid)[PPT], const uint32_t (&idx)[PPT],
                                                  double (&acc)[PPT][kMaxRhs], int64_t e_begin, int64_t e_end)
 {
+    using T = typename Lds::T;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
     const int nrhs = a.n_rhs;
@@ -497,60 +654,25 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
         stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, 0, nrhs);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
-            const double cx = s.cx[j], cy = s.cy[j], cz = s.cz[j], thr2 = s.thr2[j];
-            double dx[PPT], dy[PPT], dz[PPT], sum[PPT];
+            const double thr2 = s.thr2[j];
+            double D2[PPT];
+            Local<PPT, T> L;
+            to_frame(s, j, px, py, pz, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                dx[k] = px[k] - cx;
-                dy[k] = py[k] - cy;
-                dz[k] = pz[k] - cz;
-                const double D2 = fma(dx[k], dx[k], fma(dy[k], dy[k], dz[k] * dz[k]));
-                nr[k] = valid[k] && (D2 < thr2);
+                nr[k] = valid[k] && (D2[k] < thr2);
                 record_near(nr[k], idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
-            if (!MIXED) {
-                double f[PPT];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) f[k] = 0.0;
-                const double4* nd = reinterpret_cast<const double4*>(s.node) + j * nn;
-                for_nodes<NN>(nn, [&](int i) {
-                    const double4 Q = nd[i];
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const double rx = dx[k] - Q.x, ry = dy[k] - Q.y, rz = dz[k] - Q.z;
-                        f[k] = fma(Q.w, rsqrt64(fma(rx, rx, fma(ry, ry, rz * rz))), f[k]);
-                    }
-                });
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) sum[k] = f[k];
-            } else {
-                float f[PPT], fx[PPT], fy[PPT], fz[PPT];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    f[k] = 0.0f;
-                    fx[k] = (float)dx[k];
-                    fy[k] = (float)dy[k];
-                    fz[k] = (float)dz[k];
-                }
-                const float4* nd = reinterpret_cast<const float4*>(s.node) + j * nn;
-                for_nodes<NN>(nn, [&](int i) {
-                    const float4 Q = nd[i];
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const float rx = fx[k] - Q.x, ry = fy[k] - Q.y, rz = fz[k] - Q.z;
-                        f[k] = fmaf(Q.w, rsqrt32(fmaf(rx, rx, fmaf(ry, ry, rz * rz))), f[k]);
-                    }
-                });
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) sum[k] = (double)f[k];
-            }
+            T o[1][PPT];
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!nr[k]) {
+                    const double v = (double)o[0][k];
 #pragma unroll
                     for (int r = 0; r < kMaxRhs; ++r)
-                        if (r < nrhs) acc[k][r] = fma(s.q[r][j], sum[k], acc[k][r]);
+                        if (r < nrhs) acc[k][r] = fma(s.q[r][j], v, acc[k][r]);
                 }
             }
         }
@@ -560,8 +682,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
 template <int NT, int NR, bool MIXED, int PPT>
 __global__ __launch_bounds__(kBlock) void far_colloc_kernel(FarArgs a)
 {
-    using Lds = typename std::conditional<MIXED, TileLds32, TileLds64>::type;
-    __shared__ Lds s;
+    __shared__ TileLds<MIXED, kMaxRhs> s;
     const int64_t ne = a.el.ne;
     const int64_t base = (int64_t)blockIdx.x * (kBlock * PPT) + threadIdx.x;
     double px[PPT], py[PPT], pz[PPT];
