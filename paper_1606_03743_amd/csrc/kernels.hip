@@ -79,27 +79,19 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 // ---------------------------------------------------------------- LDS staging ------
 // Each element is summed in its own orthonormal frame: origin at the centroid, f1 and f2
 // in its plane, f3 its unit normal.  A Gaussian point has in-plane coordinates (a, b) and
-// a field point the coordinates (p1, p2, p3), so r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2: two
-// differences per node instead of three, with p3^2 formed once per pair.  The sums are
-// rotated back to the global axes once per pair.  For rectangles f1 runs along the second
-// side, so the nodes of a tensor Gauss-Legendre rule that share their first coordinate
-// share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is then formed once per group of seven.
-template <bool MIXED>
-struct NodeTile;
-template <>
-struct NodeTile<false> {
-    double2 ab[kTileNodes];  // (a, b)
-    double w[kTileNodes];    // weight (unit element charge)
-};
-template <>
-struct NodeTile<true> {
-    float4 n[kTileNodes];  // a, b, weight, unused
-};
-
+// a field point the coordinates (p1, p2, p3), so
+//   r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2 = |p|^2 + (a^2 + b^2) - 2 (p1 a + p2 b):
+// with a^2 + b^2 staged per node and |p|^2 formed once per pair, r^2 takes one addition and
+// two FMAs per node (for DR >= 3 the expansion adds about a tenth of an ulp to the rounding
+// of 1/r).  The sums are rotated back to the global axes once per pair.  For rectangles f1
+// runs along the second side, so the nodes of a tensor Gauss-Legendre rule that share their
+// first coordinate share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is formed once per group of
+// seven and r^2 takes one difference and one FMA per node.
 template <bool MIXED, int NRHS>
 struct TileLds {
     using T = typename std::conditional<MIXED, float, double>::type;
-    NodeTile<MIXED> nd;
+    using T4 = typename std::conditional<MIXED, float4, double4>::type;
+    T4 nd[kTileNodes];  // a, b, a^2 + b^2, weight (unit element charge)
     double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
     T f[9][kMaxTileElems];  // f1, f2, f3 (x, y, z each), in the precision of the node sums
     double q[NRHS][kMaxTileElems];
@@ -141,12 +133,9 @@ __device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elemen
             a = x * el.loc[e] + y * el.loc[2 * ne + e];
             b = x * el.loc[ne + e];
         }
-        if constexpr (MIXED) {
-            s.nd.n[k] = make_float4((float)a, (float)b, (float)w, 0.0f);
-        } else {
-            s.nd.ab[k] = make_double2(a, b);
-            s.nd.w[k] = w;
-        }
+        const double g = fma(a, a, b * b);
+        if constexpr (MIXED) s.nd[k] = make_float4((float)a, (float)b, (float)g, (float)w);
+        else s.nd[k] = make_double4(a, b, g, w);
     }
 }
 
@@ -174,6 +163,7 @@ struct PointSet {
 template <int PPT, typename T>
 struct Local {
     T p1[PPT], p2[PPT], p3[PPT], h[PPT];  // h = p3^2
+    T q1[PPT], q2[PPT], H[PPT];           // -2 p1, -2 p2, |p|^2 (expanded r^2 only)
 };
 
 // Runs term(i) for the nodes i = 0 .. n-1 of one element.  Long rules (and run-time
@@ -197,32 +187,49 @@ __device__ __forceinline__ void for_nodes(int n, Term term)
     for (; i < n; ++i) term(i);
 }
 
-// Element sums in the frame, per field point (unit element charge):
-//   kFarField  (sum w/r, sum w da/r^3, sum w db/r^3, sum w/r^3), with da = p1 - a, db = p2 - b;
+// Element sums in the frame, per field point (unit element charge).  EXP: r^2 expanded
+// (long rules); otherwise from the differences da = p1 - a, db = p2 - b (the short rules
+// of the distance-ratio levels, where the per-pair set-up of the expansion does not pay).
+//   kFarField  (sum w/r, sum w a/r^3, sum w b/r^3, sum w/r^3) expanded, the field's in-plane
+//              parts following as p1 sum w/r^3 - sum w a/r^3 and likewise for b;
+//              (sum w/r, sum w da/r^3, sum w db/r^3, sum w/r^3) from differences;
 //   kFarGrad   FP64: (sum w/r^3, sum w/r^5, sum w da/r^5, sum w db/r^5, sum w da^2/r^5,
 //              sum w db^2/r^5, sum w da db/r^5), turned into the local tensor after the loop;
 //              FP32: the local tensor itself, sum w/r^3 and sum w u_i u_j / r^3 over the unit
 //              offset u = (da, db, p3)/r (xx, yy, zz, xy, xz, yz), so that no power of 1/r
 //              above the third is formed in single precision;
 //   kFarPhi    sum w/r.
-template <int PPT, int MODE>
-__device__ __forceinline__ void node_term64(double a, double b, double w, const Local<PPT, double>& L,
+template <int PPT, int MODE, bool EXP>
+__device__ __forceinline__ void node_term64(const double4 Q, const Local<PPT, double>& L,
                                             double (&o)[Sums<MODE>::kNode][PPT])
 {
+    const double a = Q.x, b = Q.y, g = Q.z, w = Q.w;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const double da = L.p1[k] - a, db = L.p2[k] - b;
-        const double ri = rsqrt64(fma(da, da, fma(db, db, L.h[k])));
-        if constexpr (MODE == kFarPhi) {
-            o[0][k] = fma(w, ri, o[0][k]);
-        } else if constexpr (MODE == kFarField) {
-            const double wr = w * ri;
-            const double w3 = wr * (ri * ri);
-            o[0][k] += wr;
-            o[1][k] = fma(w3, da, o[1][k]);
-            o[2][k] = fma(w3, db, o[2][k]);
-            o[3][k] += w3;
+        if constexpr (MODE != kFarGrad) {
+            double ri, ca, cb;  // ca, cb: a, b (expanded) or da, db
+            if constexpr (EXP) {
+                ri = rsqrt64(fma(L.q1[k], a, fma(L.q2[k], b, L.H[k] + g)));
+                ca = a;
+                cb = b;
+            } else {
+                ca = L.p1[k] - a;
+                cb = L.p2[k] - b;
+                ri = rsqrt64(fma(ca, ca, fma(cb, cb, L.h[k])));
+            }
+            if constexpr (MODE == kFarPhi) {
+                o[0][k] = fma(w, ri, o[0][k]);
+            } else {
+                const double wr = w * ri;
+                const double w3 = wr * (ri * ri);
+                o[0][k] += wr;
+                o[1][k] = fma(w3, ca, o[1][k]);
+                o[2][k] = fma(w3, cb, o[2][k]);
+                o[3][k] += w3;
+            }
         } else {
+            const double da = L.p1[k] - a, db = L.p2[k] - b;
+            const double ri = rsqrt64(fma(da, da, fma(db, db, L.h[k])));
             const double ri2 = ri * ri;
             const double w3 = (w * ri) * ri2;
             const double w5 = w3 * ri2;
@@ -238,24 +245,37 @@ __device__ __forceinline__ void node_term64(double a, double b, double w, const 
     }
 }
 
-template <int PPT, int MODE>
-__device__ __forceinline__ void node_term32(float a, float b, float w, const Local<PPT, float>& L,
+template <int PPT, int MODE, bool EXP>
+__device__ __forceinline__ void node_term32(const float4 Q, const Local<PPT, float>& L,
                                             float (&o)[Sums<MODE>::kNode][PPT])
 {
+    const float a = Q.x, b = Q.y, g = Q.z, w = Q.w;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const float da = L.p1[k] - a, db = L.p2[k] - b;
-        const float ri = rsqrt32(fmaf(da, da, fmaf(db, db, L.h[k])));
-        if constexpr (MODE == kFarPhi) {
-            o[0][k] = fmaf(w, ri, o[0][k]);
-        } else if constexpr (MODE == kFarField) {
-            const float wr = w * ri;
-            const float w3 = wr * (ri * ri);
-            o[0][k] += wr;
-            o[1][k] = fmaf(w3, da, o[1][k]);
-            o[2][k] = fmaf(w3, db, o[2][k]);
-            o[3][k] += w3;
+        if constexpr (MODE != kFarGrad) {
+            float ri, ca, cb;
+            if constexpr (EXP) {
+                ri = rsqrt32(fmaf(L.q1[k], a, fmaf(L.q2[k], b, L.H[k] + g)));
+                ca = a;
+                cb = b;
+            } else {
+                ca = L.p1[k] - a;
+                cb = L.p2[k] - b;
+                ri = rsqrt32(fmaf(ca, ca, fmaf(cb, cb, L.h[k])));
+            }
+            if constexpr (MODE == kFarPhi) {
+                o[0][k] = fmaf(w, ri, o[0][k]);
+            } else {
+                const float wr = w * ri;
+                const float w3 = wr * (ri * ri);
+                o[0][k] += wr;
+                o[1][k] = fmaf(w3, ca, o[1][k]);
+                o[2][k] = fmaf(w3, cb, o[2][k]);
+                o[3][k] += w3;
+            }
         } else {
+            const float da = L.p1[k] - a, db = L.p2[k] - b;
+            const float ri = rsqrt32(fmaf(da, da, fmaf(db, db, L.h[k])));
             const float w3 = (w * ri) * (ri * ri);
             const float va = da * ri, vb = db * ri, vc = L.p3[k] * ri;
             const float ua = w3 * va, ub = w3 * vb, uc = w3 * vc;
@@ -274,14 +294,14 @@ __device__ __forceinline__ void node_term32(float a, float b, float w, const Loc
 // lane forms db and (p2 - b)^2 + p3^2 once; per node one difference remains.  The
 // field's b-component and sum w/r^3 are gathered per group.
 template <int G, int PPT, int MODE>
-__device__ __forceinline__ void group_sum64(const NodeTile<false>& t, int base, const Local<PPT, double>& L,
+__device__ __forceinline__ void group_sum64(const double4* t, int base, const Local<PPT, double>& L,
                                             double (&o)[Sums<MODE>::kNode][PPT])
 {
     static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         const int n0 = base + g * G;
-        const double b = t.ab[n0].y;
+        const double b = t[n0].y;
         double db[PPT], B[PPT], sg[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -291,7 +311,7 @@ __device__ __forceinline__ void group_sum64(const NodeTile<false>& t, int base, 
         }
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            const double a = t.ab[n0 + i].x, w = t.w[n0 + i];
+            const double a = t[n0 + i].x, w = t[n0 + i].w;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const double da = L.p1[k] - a;
@@ -318,14 +338,14 @@ __device__ __forceinline__ void group_sum64(const NodeTile<false>& t, int base, 
 }
 
 template <int G, int PPT, int MODE>
-__device__ __forceinline__ void group_sum32(const NodeTile<true>& t, int base, const Local<PPT, float>& L,
+__device__ __forceinline__ void group_sum32(const float4* t, int base, const Local<PPT, float>& L,
                                             float (&o)[Sums<MODE>::kNode][PPT])
 {
     static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         const int n0 = base + g * G;
-        const float b = t.n[n0].y;
+        const float b = t[n0].y;
         float db[PPT], B[PPT], sg[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -335,15 +355,15 @@ __device__ __forceinline__ void group_sum32(const NodeTile<true>& t, int base, c
         }
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            const float4 Q = t.n[n0 + i];
+            const float4 Q = t[n0 + i];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float da = L.p1[k] - Q.x;
                 const float ri = rsqrt32(fmaf(da, da, B[k]));
                 if constexpr (MODE == kFarPhi) {
-                    o[0][k] = fmaf(Q.z, ri, o[0][k]);
+                    o[0][k] = fmaf(Q.w, ri, o[0][k]);
                 } else {
-                    const float wr = Q.z * ri;
+                    const float wr = Q.w * ri;
                     const float w3 = wr * (ri * ri);
                     o[0][k] += wr;
                     o[1][k] = fmaf(w3, da, o[1][k]);
@@ -365,7 +385,7 @@ __device__ __forceinline__ void group_sum32(const NodeTile<true>& t, int base, c
 // charge) in the precision T of the tile (FP64, or FP32 for the mixed path).  NN > 0:
 // compile-time node count; G > 0: tensor rule in groups of G.  Gradient: the result is the
 // local tensor (sum w/r^3; sum w d_i d_j / r^5 for xx, yy, zz, xy, xz, yz, d = (da, db, p3)).
-template <int NN, int G, bool MIXED, int PPT, int MODE, typename Lds, typename T>
+template <int NN, int G, bool MIXED, int PPT, int MODE, bool EXP, typename Lds, typename T>
 __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const Local<PPT, T>& L,
                                             T (&o)[Sums<MODE>::kNode][PPT])
 {
@@ -376,26 +396,23 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
 #pragma unroll
         for (int k = 0; k < PPT; ++k) r[c][k] = T(0);
     const int nn = NN > 0 ? NN : n;
+    constexpr bool GROUPS = G > 0 && MODE != kFarGrad;
     if constexpr (!MIXED) {
-        if constexpr (G > 0 && MODE != kFarGrad) {
-            group_sum64<G, PPT, MODE>(s.nd, base, L, r);
-        } else {
-            for_nodes<NN>(nn, [&](int i) {
-                const double2 ab = s.nd.ab[base + i];
-                node_term64<PPT, MODE>(ab.x, ab.y, s.nd.w[base + i], L, r);
-            });
-        }
+        if constexpr (GROUPS) group_sum64<G, PPT, MODE>(s.nd, base, L, r);
+        else for_nodes<NN>(nn, [&](int i) { node_term64<PPT, MODE, EXP>(s.nd[base + i], L, r); });
     } else {
-        if constexpr (G > 0 && MODE != kFarGrad) {
-            group_sum32<G, PPT, MODE>(s.nd, base, L, r);
-        } else {
-            for_nodes<NN>(nn, [&](int i) {
-                const float4 Q = s.nd.n[base + i];
-                node_term32<PPT, MODE>(Q.x, Q.y, Q.z, L, r);
-            });
-        }
+        if constexpr (GROUPS) group_sum32<G, PPT, MODE>(s.nd, base, L, r);
+        else for_nodes<NN>(nn, [&](int i) { node_term32<PPT, MODE, EXP>(s.nd[base + i], L, r); });
     }
-    if constexpr (MODE == kFarGrad && !MIXED) {
+    if constexpr (MODE == kFarField && EXP && !GROUPS) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            o[0][k] = r[0][k];
+            o[1][k] = fma(L.p1[k], r[3][k], -r[1][k]);
+            o[2][k] = fma(L.p2[k], r[3][k], -r[2][k]);
+            o[3][k] = r[3][k];
+        }
+    } else if constexpr (MODE == kFarGrad && !MIXED) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             o[0][k] = r[0][k];
@@ -416,7 +433,7 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
 
 // Offsets of the lane's points from element j of the tile: D^2 in FP64 (the distance test,
 // Sec. 2) and the coordinates in the element's frame, in the precision of the node sums.
-template <int PPT, typename Lds, typename T>
+template <bool EXP, int PPT, typename Lds, typename T>
 __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[PPT], const double (&y)[PPT],
                                          const double (&z)[PPT], double (&D2)[PPT], Local<PPT, T>& L)
 {
@@ -430,6 +447,11 @@ __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[
         L.p2[k] = fma(u, s.f[3][j], fma(v, s.f[4][j], w * s.f[5][j]));
         L.p3[k] = fma(u, s.f[6][j], fma(v, s.f[7][j], w * s.f[8][j]));
         L.h[k] = L.p3[k] * L.p3[k];
+        if constexpr (EXP) {
+            L.q1[k] = T(-2) * L.p1[k];
+            L.q2[k] = T(-2) * L.p2[k];
+            L.H[k] = fma(L.p1[k], L.p1[k], fma(L.p2[k], L.p2[k], L.h[k]));
+        }
     }
 }
 
@@ -493,7 +515,7 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<true>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -501,7 +523,7 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
             T o[Sums<MODE>::kNode][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE, true>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (!nr[k]) add_element<PPT, MODE>(P, k, q, s, j, L, o);
@@ -534,7 +556,7 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<false>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
             int lvl[PPT];
 #pragma unroll
@@ -553,10 +575,13 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             T o[Sums<MODE>::kNode][PPT];
             const int b = j * nn;
             int nw;
-            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE>(s, b, o1, L, o); nw = o1; }
-            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
-            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
-            else { element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE>(s, b + o3, nn - o3, L, o); nw = nn - o3; }
+            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE, false>(s, b, o1, L, o); nw = o1; }
+            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE, false>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
+            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE, false>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
+            else {
+                element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE, false>(s, b + o3, nn - o3, L, o);
+                nw = nn - o3;
+            }
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (lvl[k] >= 0) {
@@ -657,7 +682,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
             const double thr2 = s.thr2[j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame(s, j, px, py, pz, D2, L);
+            to_frame<true>(s, j, px, py, pz, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -665,7 +690,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                 record_near(nr[k], idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
             T o[1][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi, true>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!nr[k]) {
