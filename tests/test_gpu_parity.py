@@ -472,3 +472,69 @@ def test_million_elements_sampled():
               f"far {st['far_ms']:.0f} ms")
         assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
         assert np.all(np.isfinite(phi)) and np.all(np.isfinite(E))
+
+
+def rotated_skewed(w, seed=71, skew=5e-11):
+    """The workload under a random rotation, with every other rectangle made a parallelogram:
+    e2 gains a component of relative size `skew` along e1 (inside the upload's orthogonality
+    tolerance of 1e-10, so the element is accepted and evaluated as the parallelogram it is)."""
+    rng = np.random.default_rng(seed)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    tri = (w.tri.reshape(-1, 3, 3) @ R.T).reshape(-1, 9)
+    rect = (w.rect.reshape(-1, 3, 3) @ R.T).reshape(-1, 9)
+    e1, e2 = rect[:, 3:6], rect[:, 6:9]
+    f = skew * np.linalg.norm(e2, axis=1) / np.linalg.norm(e1, axis=1)
+    f[1::2] = 0.0
+    rect[:, 6:9] = e2 + f[:, None] * e1
+    return tri, rect, w.points @ R.T
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dr", [False, True])
+def test_rotated_geometry_and_parallelograms(cyl, precision, dr):
+    """Elements in general orientation (every element frame has nonzero components on all
+    axes) and rectangles skewed at 5e-11: parity with the oracle on the same inputs, fixed
+    rules and rules by distance ratio (the 7 x 7 rows and the Table B levels)."""
+    w, _ = cyl
+    tri, rect, pts = rotated_skewed(w)
+    ref = oracle.evaluate(tri, rect, w.sigma[0], pts, oracle.params(33, 7, dr_rules=dr), with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(w.sigma)
+    ctx.set_dr_rules(dr)
+    phi, E, _ = run_gpu(ctx, pts, precision)
+    st = ctx.stats()
+    ctx.close()
+    assert st["near_pairs"] == ref["stats"]["near_pairs"]
+    ep, ee = nerr(phi, E, ref)
+    print(f"rotated, skewed, dr={dr} {precision}: phi {ep.max():.2e} E {ee.max():.2e}")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rotated_gradient_and_collocation(cyl, precision):
+    """Field gradient and collocation product on the rotated, skewed geometry: the tensor's
+    rotation from the element frames and the potential-only sums."""
+    torch = torch_mod()
+    w, _ = cyl
+    tri, rect, pts = rotated_skewed(w, seed=72)
+    pts = pts[::3]
+    ref = oracle.gradient(tri, rect, w.sigma[0], pts, oracle.params(33, 7))
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(w.sigma)
+    tp = torch.tensor(np.ascontiguousarray(pts.T), dtype=torch.float64, device="cuda:0")
+    G, rc = ctx.eval_gradient(tp, precision=precision)
+    torch.cuda.synchronize()
+    G = G.cpu().numpy().T
+    eg = np.abs(G - ref["G"]).max(axis=1) / ref["abs_T"]
+    print(f"rotated gradient {precision}: {eg.max():.2e}")
+    assert rc == 0 and eg.max() <= TOL[precision]
+    sig = np.random.default_rng(9).standard_normal(tri.shape[0] + rect.shape[0])
+    refc = oracle.collocation(tri, rect, sig)
+    out = ctx.collocation(torch.tensor(sig[None, :], dtype=torch.float64, device="cuda:0"), precision=precision)
+    torch.cuda.synchronize()
+    ctx.close()
+    ec = np.abs(out.cpu().numpy()[0] - refc["out"][0]) / refc["abs"]
+    print(f"rotated collocation {precision}: {ec.max():.2e}")
+    assert ec.max() <= TOL[precision]
