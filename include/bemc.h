@@ -62,8 +62,9 @@ extern "C" {
 
 /* precision of the bulk point-charge sums */
 #define BEMC_FP64 0  /* everything in FP64 */
-#define BEMC_MIXED 1 /* far-field node sums in FP32 (offsets from the element centroid,
-                        FP32 reciprocal square root), per-element partial sums scaled by
+#define BEMC_MIXED 1 /* far-field node sums in FP32 (coordinates relative to the element
+                        centroid in the element's own frame, FP32 reciprocal square
+                        root), per-element partial sums scaled by
                         the element charge and accumulated per field point in FP64; the
                         distance-ratio classification, the near field and on-element
                         integrals stay FP64 */
@@ -128,9 +129,11 @@ int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const dou
 
 /* Upload the electrode geometry (host arrays in the element input format; either count
  * may be 0, n_tri + n_rect < 2^31).  Validates every element (finite, positive area,
- * orthogonal rectangle sides), computes centroids, areas, average side lengths L
- * (triangle (a + b + c)/3, Sec. 2; rectangle (a + b)/2), normals and the centroid
- * offsets used for node generation, and keeps them resident on the device.  Previously
+ * orthogonal rectangle sides: |e1.e2| <= 1e-10 |e1||e2|; within that tolerance the element
+ * is the parallelogram its sides span), computes centroids, areas, average side lengths L
+ * (triangle (a + b + c)/3, Sec. 2; rectangle (a + b)/2), normals and an orthonormal frame
+ * per element with the in-plane coordinates used for node generation, and keeps them
+ * resident on the device.  Previously
  * uploaded densities are discarded.  Synchronous with respect to `stream`.
  * Errors: INVALID_ARG, NONFINITE, DEGENERATE_ELEMENT (index in the message),
  * NOT_RECTANGLE, LIMIT, OUT_OF_MEMORY, DEVICE. */
