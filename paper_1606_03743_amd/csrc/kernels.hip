@@ -83,7 +83,8 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 //   r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2 = |p|^2 + (a^2 + b^2) - 2 (p1 a + p2 b):
 // with a^2 + b^2 staged per node and |p|^2 formed once per pair, r^2 takes one addition and
 // two FMAs per node (for DR >= 3 the expansion adds about a tenth of an ulp to the rounding
-// of 1/r).  The sums are rotated back to the global axes once per pair.  For rectangles f1
+// of 1/r; the short rules of the distance-ratio levels and the gradient keep the two
+// differences).  The sums are rotated back to the global axes once per pair.  For rectangles f1
 // runs along the second side, so the nodes of a tensor Gauss-Legendre rule that share their
 // first coordinate share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is formed once per group of
 // seven and r^2 takes one difference and one FMA per node.
@@ -151,7 +152,7 @@ struct Sums {
     static constexpr int kNode = MODE == kFarGrad ? 7 : (MODE == kFarField ? 4 : 1);  // element sums per point
 };
 
-// Field points of one lane, and their offsets from the element in hand in its frame.
+// Field points of one lane and their FP64 accumulators.
 template <int PPT, int MODE>
 struct PointSet {
     double x[PPT], y[PPT], z[PPT];
@@ -160,6 +161,7 @@ struct PointSet {
     double acc[Sums<MODE>::kOut][PPT];
 };
 
+// Offsets of the lane's points from the element in hand, in its frame.
 template <int PPT, typename T>
 struct Local {
     T p1[PPT], p2[PPT], p3[PPT], h[PPT];  // h = p3^2
