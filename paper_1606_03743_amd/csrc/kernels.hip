@@ -1155,10 +1155,14 @@ hipError_t far_eval_launch(const FarArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Field points per lane: two for the distance-ratio levels and the run-time rules; for the
+// compiled long rules three in FP64 and one in the mixed path (on the 150k-element cylinder
+// 1 % and 2 % faster than two; four was slower in both).
 template <bool MIXED>
 hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
 {
     constexpr int PPT = 2;
+    constexpr int PPT_LONG = MIXED ? 1 : 3;
     if (a.dr_rules) {
         const int* t = a.lv.tri_off;
         const int* r = a.lv.rect_off;
@@ -1169,10 +1173,10 @@ hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
     }
     const int nt = a.rules.nt, nr = a.rules.nr;
     if (nr == 49) {
-        if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
-        if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
-        if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
-        if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
+        if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
+        if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
+        if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
+        if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
     }
     return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
 }
