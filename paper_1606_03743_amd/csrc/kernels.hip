@@ -1181,11 +1181,14 @@ hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
     return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
 }
 
-// Gradient: compile-time node counts for the default rules only.
+// Gradient: compile-time node counts for the default rules only; one point per lane for
+// those in the mixed path (7 % faster than two on the 150k-element cylinder; FP64 is
+// fastest with two).
 template <bool MIXED>
 hipError_t far_grad_dispatch(const FarArgs& a, hipStream_t s)
 {
     constexpr int PPT = 2;
+    constexpr int PPT_LONG = MIXED ? 1 : 2;
     if (a.dr_rules) {
         const int* t = a.lv.tri_off;
         const int* r = a.lv.rect_off;
@@ -1194,7 +1197,8 @@ hipError_t far_grad_dispatch(const FarArgs& a, hipStream_t s)
             return far_eval_launch<true, 7, 7, 12, 19, 33, 12, 17, 49, MIXED, PPT, true>(a, s);
         return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
     }
-    if (a.rules.nt == 33 && a.rules.nr == 49) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
+    if (a.rules.nt == 33 && a.rules.nr == 49)
+        return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, true>(a, s);
     return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, true>(a, s);
 }
 
