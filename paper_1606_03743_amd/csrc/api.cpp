@@ -563,6 +563,8 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
             N[2] = e1[0] * e2[1] - e1[1] * e2[0];
             const double n2 = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
             a = la * lb;
+            if (!(a > 0.0) || !(n2 > 0.0))  // sides so short that the area or the normal underflows
+                return fail(BEMC_E_DEGENERATE_ELEMENT, "rectangle %lld has zero area", (long long)e);
             Lh = 0.5 * (la + lb);  // mean of the four sides
             for (int c = 0; c < 3; ++c) {
                 C[c] = P0[c] + 0.5 * e1[c] + 0.5 * e2[c];  // Eq. 3.2: Q_cen

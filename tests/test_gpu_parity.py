@@ -208,6 +208,11 @@ def test_empty_and_errors():
     with pytest.raises(bemc.BemcError) as ei:
         ctx.upload_geometry(w.tri, skew)
     assert ei.value.code == bemc.E_NOT_RECTANGLE
+    tiny = w.rect.copy()
+    tiny[0, 3:9] *= 1e-170  # sides of 1e-172: the area underflows
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.upload_geometry(w.tri, tiny)
+    assert ei.value.code == bemc.E_DEGENERATE_ELEMENT
     nan = w.tri.copy()
     nan[0, 0] = np.nan
     with pytest.raises(bemc.BemcError) as ei:
