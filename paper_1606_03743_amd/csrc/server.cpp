@@ -21,7 +21,8 @@ namespace {
 constexpr int kWavesTarget = 16 * 1024;
 constexpr int kMaxServeSplit = 1024;  // element chunks of one serving launch
 constexpr int kSlotSplit = 256;       // partial-sum rows of a slot: kSlotSplit x max_batch_points
-constexpr int kPointsPerBlock = 512;
+constexpr int kPointsPerBlock = 512;  // nominal points per workgroup for sizing the split (the
+                                       // far kernels hold 256-768, by precision and rule)
 }  // namespace
 
 double Server::now() const
