@@ -292,24 +292,25 @@ __device__ __forceinline__ void node_term32(const float4 Q, const Local<PPT, flo
     }
 }
 
-// Tensor rule in groups of G nodes with the same b (kFarField and kFarPhi): per group the
-// lane forms db and (p2 - b)^2 + p3^2 once; per node one difference remains.  The
-// field's b-component and sum w/r^3 are gathered per group.
+// Tensor rule in groups of G nodes with the same b: per group the lane forms db and
+// (p2 - b)^2 + p3^2 once; per node one difference remains.  Field: the b-component and
+// sum w/r^3 are gathered per group.  Gradient (the FP64 sums of node_term64): sum w/r^5
+// and sum w da/r^5 are gathered per group, and the sums with db follow from them.
 template <int G, int PPT, int MODE>
 __device__ __forceinline__ void group_sum64(const double4* t, int base, const Local<PPT, double>& L,
                                             double (&o)[Sums<MODE>::kNode][PPT])
 {
-    static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         const int n0 = base + g * G;
         const double b = t[n0].y;
-        double db[PPT], B[PPT], sg[PPT];
+        double db[PPT], B[PPT], sg[PPT], xg[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             db[k] = L.p2[k] - b;
             B[k] = fma(db[k], db[k], L.h[k]);
             sg[k] = 0.0;
+            xg[k] = 0.0;
         }
 #pragma unroll
         for (int i = 0; i < G; ++i) {
@@ -320,12 +321,21 @@ __device__ __forceinline__ void group_sum64(const double4* t, int base, const Lo
                 const double ri = rsqrt64(fma(da, da, B[k]));
                 if constexpr (MODE == kFarPhi) {
                     o[0][k] = fma(w, ri, o[0][k]);
-                } else {
+                } else if constexpr (MODE == kFarField) {
                     const double wr = w * ri;
                     const double w3 = wr * (ri * ri);
                     o[0][k] += wr;
                     o[1][k] = fma(w3, da, o[1][k]);
                     sg[k] += w3;
+                } else {
+                    const double ri2 = ri * ri;
+                    const double w3 = (w * ri) * ri2;
+                    const double w5 = w3 * ri2;
+                    const double ua = w5 * da;
+                    o[0][k] += w3;
+                    sg[k] += w5;
+                    xg[k] += ua;
+                    o[4][k] = fma(ua, da, o[4][k]);
                 }
             }
         }
@@ -334,6 +344,16 @@ __device__ __forceinline__ void group_sum64(const double4* t, int base, const Lo
             for (int k = 0; k < PPT; ++k) {
                 o[2][k] = fma(sg[k], db[k], o[2][k]);
                 o[3][k] += sg[k];
+            }
+        } else if constexpr (MODE == kFarGrad) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const double u = sg[k] * db[k];  // sum w db / r^5 of the group
+                o[1][k] += sg[k];
+                o[2][k] += xg[k];
+                o[3][k] += u;
+                o[5][k] = fma(u, db[k], o[5][k]);
+                o[6][k] = fma(xg[k], db[k], o[6][k]);
             }
         }
     }
@@ -398,7 +418,7 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
 #pragma unroll
         for (int k = 0; k < PPT; ++k) r[c][k] = T(0);
     const int nn = NN > 0 ? NN : n;
-    constexpr bool GROUPS = G > 0 && MODE != kFarGrad;
+    constexpr bool GROUPS = G > 0 && (MODE != kFarGrad || !MIXED);
     if constexpr (!MIXED) {
         if constexpr (GROUPS) group_sum64<G, PPT, MODE>(s.nd, base, L, r);
         else for_nodes<NN>(nn, [&](int i) { node_term64<PPT, MODE, EXP>(s.nd[base + i], L, r); });
