@@ -78,3 +78,33 @@ def test_random_soup(seed, dr):
         assert st["near_pairs"] == ref["stats"]["near_pairs"]
         assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
     ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_soup_gradient_and_collocation(seed):
+    """The field gradient (per-term scale abs_T) and the collocation product (self terms on
+    every row) on the same kind of soups."""
+    import torch
+
+    assert torch.cuda.is_available()
+    tri, rect, sigma, pts, rng = soup(2000 + seed, n_far=600, n_near=300)
+    tri_rule, rect_rule = rules_for(rng, False)
+    prm = oracle_params(tri_rule, rect_rule, False)
+    refg = oracle.gradient(tri, rect, sigma, pts, prm)
+    refc = oracle.collocation(tri, rect, sigma, prm=prm)
+    ctx = bemc.Context(0)
+    ctx.set_rules(tri_rule, rect_rule)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(sigma)
+    tp = torch.tensor(np.ascontiguousarray(pts.T), dtype=torch.float64, device="cuda:0")
+    s = torch.tensor(sigma[None, :], dtype=torch.float64, device="cuda:0")
+    for precision in ("fp64", "mixed"):
+        G, rc = ctx.eval_gradient(tp, precision=precision)
+        out = ctx.collocation(s, precision=precision)
+        torch.cuda.synchronize()
+        eg = np.abs(G.cpu().numpy().T - refg["G"]).max(axis=1) / refg["abs_T"]
+        ec = np.abs(out.cpu().numpy()[0] - refc["out"][0]) / refc["abs"]
+        print(f"soup {seed} rules {tri_rule}/{rect_rule} {precision}: gradient {eg.max():.2e} "
+              f"collocation {ec.max():.2e}")
+        assert rc == 0 and eg.max() <= TOL[precision] and ec.max() <= TOL[precision]
+    ctx.close()
