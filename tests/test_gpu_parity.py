@@ -543,3 +543,30 @@ def test_rotated_gradient_and_collocation(cyl, precision):
     ec = np.abs(out.cpu().numpy()[0] - refc["out"][0]) / refc["abs"]
     print(f"rotated collocation {precision}: {ec.max():.2e}")
     assert ec.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("scale", [1e-7, 1e4])
+def test_scaled_geometry(cyl, scale):
+    """The cylinder workload scaled to nanometre elements (1e-7) and to 250 m elements (1e4):
+    field and gradient in both precisions against the oracle on the same inputs (no overflow
+    or underflow in the FP32 sums; the gradient's FP32 products use unit vectors)."""
+    torch = torch_mod()
+    w, _ = cyl
+    tri, rect, pts = w.tri * scale, w.rect.copy(), w.points[::2] * scale
+    rect[:, 0:3] *= scale
+    rect[:, 3:9] *= scale
+    ref = oracle.evaluate(tri, rect, w.sigma[0], pts, oracle.params(33, 7), with_abs=True)
+    refg = oracle.gradient(tri, rect, w.sigma[0], pts, oracle.params(33, 7))
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(w.sigma)
+    tp = torch.tensor(np.ascontiguousarray(pts.T), dtype=torch.float64, device="cuda:0")
+    for precision in ("fp64", "mixed"):
+        phi, E, _ = ctx.eval(tp, precision=precision)
+        G, _ = ctx.eval_gradient(tp, precision=precision)
+        torch.cuda.synchronize()
+        ep, ee = nerr(phi.cpu().numpy(), E.cpu().numpy().T.copy(), ref)
+        eg = np.abs(G.cpu().numpy().T - refg["G"]).max(axis=1) / refg["abs_T"]
+        print(f"scale {scale:g} {precision}: phi {ep.max():.2e} E {ee.max():.2e} grad {eg.max():.2e}")
+        assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision] and eg.max() <= TOL[precision]
+    ctx.close()
