@@ -11,7 +11,7 @@
  * Gaussian points come from barycentric coordinates for triangles (Eq. 3.3, rules of
  * Tables A1-A5) and from natural coordinates for rectangles (Eq. 3.2, tensor
  * Gauss-Legendre n x n).  Contributions of all elements are summed per field point
- * (Sec. 5: "integrating field solver").  The distance ratio DR = D / L, D = |P - centroid|,
+ * (Sec. 5, the integrating field solver).  The distance ratio DR = D / L, D = |P - centroid|,
  * L = average side length (Sec. 2), selects the path: for DR >= near_dr (3 by default,
  * the limit below which the paper's rules are not accurate enough, Sec. 1 and Sec. 4) the
  * rule is applied directly; below it the element is subdivided recursively (triangle:
