@@ -160,6 +160,13 @@ def main():
     dtdrm, fardrm, stdrm = timed("mixed", args.steps, 1)
     phidrm, Edrm = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     ctx.set_dr_rules(False)
+    # Table B5 for the rectangles (33 points, degree 13) instead of 7 x 7 Gauss (49 points)
+    ctx.set_rules(w.tri_rule, -33)
+    dtb5, farb5, stb5 = timed("fp64", args.steps, 1)
+    phib5, Eb5 = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    dtb5m, farb5m, stb5m = timed("mixed", args.steps, 1)
+    phib5m, Eb5m = phi.cpu().numpy(), E.cpu().numpy().T.copy()
+    ctx.set_rules(w.tri_rule, w.rect_gl_n)
 
     # field gradient dE_i/dx_j (six rows) on the same workload
     G = torch.empty((6, n), dtype=torch.float64, device=dev)
@@ -237,6 +244,11 @@ def main():
                        "mixed_value": pairs * args.steps / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
                        "rules": "triangles 7/12/19/33 points for DR >= 100/25/10/3, rectangles Tables B2/B3/B4 "
                                 "and 7x7 Gauss for DR >= 150/40/15/3"}
+    out["rect_table_b5"] = {"value": pairs * args.steps / dtb5, "unit": "pairs/s", "precision": "fp64",
+                            "ms_per_step": 1e3 * dtb5 / args.steps, "far_kernel_ms": float(np.mean(farb5)),
+                            "node_interactions": stb5["node_interactions"],
+                            "mixed_value": pairs * args.steps / dtb5m, "mixed_far_kernel_ms": float(np.mean(farb5m)),
+                            "rules": "33-point triangles, Table B5 (33 points) rectangles"}
 
     if not args.quick:
         import oracle
@@ -267,6 +279,17 @@ def main():
             acc[name] = {"max_norm_err_phi": float(ep.max()), "max_norm_err_E": float(ee.max()),
                          "median_rel_err_phi": float(np.median(rp))}
         out["accuracy_vs_oracle"] = acc
+        # Table B5: parity with the oracle on the same rules, and its distance to the 7 x 7 Gauss result
+        log(f"oracle with Table B5 rectangles on {idx.size} sampled points")
+        refb5 = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points[idx],
+                                oracle.params(33, rect_gl_n=0, rect_table_n=33), with_abs=True)
+        for name, (p_, E_) in {"fp64": (phib5, Eb5), "mixed": (phib5m, Eb5m)}.items():
+            ep, ee, _ = nerr(p_[idx], E_[idx], refb5)
+            out["rect_table_b5"][f"{name}_max_norm_err_phi"] = float(ep.max())
+            out["rect_table_b5"][f"{name}_max_norm_err_E"] = float(ee.max())
+        ep, ee, _ = nerr(phib5[idx], Eb5[idx], ref)
+        out["rect_table_b5"]["fp64_vs_gauss7x7_max_norm_diff_phi"] = float(ep.max())
+        out["rect_table_b5"]["fp64_vs_gauss7x7_max_norm_diff_E"] = float(ee.max())
         gidx = idx[::10]
         log(f"oracle gradient on {gidx.size} sampled points")
         gref = oracle.gradient(w.tri, w.rect, w.sigma[0], w.points[gidx], oracle.params(33, 7))

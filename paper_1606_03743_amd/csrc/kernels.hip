@@ -1198,6 +1198,8 @@ hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
         if (nt == 19) return far_eval_launch<false, 19, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
         if (nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
     }
+    if (nr == 33 && nt == 33)  // Table B5 for the rectangles
+        return far_eval_launch<false, 33, 33, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
     return far_eval_launch<false, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
 }
 
