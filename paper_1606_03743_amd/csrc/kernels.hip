@@ -454,7 +454,8 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
 }
 
 // Offsets of the lane's points from element j of the tile: D^2 in FP64 (the distance test,
-// Sec. 2) and the coordinates in the element's frame, in the precision of the node sums.
+// Sec. 2) and the coordinates in the element's frame, in the precision of the node sums;
+// EXP: with -2 p and |p|^2 for the expanded r^2, else with p3^2.
 template <bool EXP, int PPT, typename Lds, typename T>
 __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[PPT], const double (&y)[PPT],
                                          const double (&z)[PPT], double (&D2)[PPT], Local<PPT, T>& L)
@@ -468,11 +469,12 @@ __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[
         L.p1[k] = fma(u, s.f[0][j], fma(v, s.f[1][j], w * s.f[2][j]));
         L.p2[k] = fma(u, s.f[3][j], fma(v, s.f[4][j], w * s.f[5][j]));
         L.p3[k] = fma(u, s.f[6][j], fma(v, s.f[7][j], w * s.f[8][j]));
-        L.h[k] = L.p3[k] * L.p3[k];
-        if constexpr (EXP) {
+        if constexpr (EXP) {  // |p|^2 = D^2: the rotation keeps the length (to rounding)
             L.q1[k] = T(-2) * L.p1[k];
             L.q2[k] = T(-2) * L.p2[k];
-            L.H[k] = fma(L.p1[k], L.p1[k], fma(L.p2[k], L.p2[k], L.h[k]));
+            L.H[k] = (T)D2[k];
+        } else {
+            L.h[k] = L.p3[k] * L.p3[k];
         }
     }
 }
@@ -526,6 +528,8 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
                                                int64_t e_end)
 {
     using T = typename Lds::T;
+    // the expanded r^2 (node loop without rows; the gradient keeps the differences)
+    constexpr bool EXPAND = MODE != kFarGrad && tensor_group<TRI, NN>() == 0;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
@@ -537,7 +541,7 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<true>(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<EXPAND>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -545,7 +549,7 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
                 record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
             T o[Sums<MODE>::kNode][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE, true>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE, EXPAND>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (!nr[k]) add_element<PPT, MODE>(P, k, q, s, j, L, o);
@@ -692,6 +696,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                                                  double (&acc)[PPT][kMaxRhs], int64_t e_begin, int64_t e_end)
 {
     using T = typename Lds::T;
+    constexpr bool EXPAND = tensor_group<TRI, NN>() == 0;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
     const int nrhs = a.n_rhs;
@@ -704,7 +709,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
             const double thr2 = s.thr2[j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<true>(s, j, px, py, pz, D2, L);
+            to_frame<EXPAND>(s, j, px, py, pz, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -712,7 +717,7 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                 record_near(nr[k], idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
             }
             T o[1][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi, true>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi, EXPAND>(s, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!nr[k]) {
