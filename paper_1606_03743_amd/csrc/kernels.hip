@@ -81,7 +81,7 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 // in its plane, f3 its unit normal.  A Gaussian point has in-plane coordinates (a, b) and
 // a field point the coordinates (p1, p2, p3), so
 //   r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2 = |p|^2 + (a^2 + b^2) - 2 (p1 a + p2 b):
-// with a^2 + b^2 staged per node and |p|^2 formed once per pair, r^2 takes one addition and
+// with a^2 + b^2 staged per node and |p|^2 = D^2 from the distance test, r^2 takes one addition and
 // two FMAs per node (for DR >= 3 the expansion adds about a tenth of an ulp to the rounding
 // of 1/r; the short rules of the distance-ratio levels and the gradient keep the two
 // differences).  The sums are rotated back to the global axes once per pair.  For rectangles f1
