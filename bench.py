@@ -107,8 +107,12 @@ def main():
     w = W.cylinder_150k()
     ctx = bemc.Context(0)
     ctx.set_rules(w.tri_rule, w.rect_gl_n, 3.0, 24)
-    ctx.upload_geometry(w.tri, w.rect)
+    t_up = time.perf_counter()
+    ctx.upload_geometry(w.tri, w.rect)  # validation, frames and copies (host arrays)
+    t_geom = time.perf_counter() - t_up
+    t_up = time.perf_counter()
     ctx.upload_densities(w.sigma)
+    t_dens = time.perf_counter() - t_up
     pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device=dev)
     n = pts.shape[1]
     phi = torch.empty(n, dtype=torch.float64, device=dev)
@@ -219,6 +223,8 @@ def main():
         "node_interactions_per_s": node_int * args.steps / dt64,
         "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
                  "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},
+        "upload": {"elements": w.n_elements, "geometry_s": t_geom, "densities_s": t_dens,
+                   "note": "host arrays: validation, centroids, frames, charges, copies to the device"},
     }
     mixed_ach = alg_flops / (1e-3 * float(np.mean(farmx))) / 1e12
     counted32 = counted_flops_from_profile("counted_fp32_flops_per_launch_mixed")
