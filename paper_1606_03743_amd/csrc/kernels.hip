@@ -83,8 +83,7 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 //   r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2 = |p|^2 + (a^2 + b^2) - 2 (p1 a + p2 b):
 // with a^2 + b^2 staged per node and |p|^2 = D^2 from the distance test, r^2 takes one addition and
 // two FMAs per node (for DR >= 3 the expansion adds about a tenth of an ulp to the rounding
-// of 1/r; the short rules of the distance-ratio levels and the gradient keep the two
-// differences).  The sums are rotated back to the global axes once per pair.  For rectangles f1
+// of 1/r; the gradient keeps the two differences).  The sums are rotated back to the global axes once per pair.  For rectangles f1
 // runs along the second side, so the nodes of a tensor Gauss-Legendre rule that share their
 // first coordinate share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is formed once per group of
 // seven and r^2 takes one difference and one FMA per node.
@@ -189,9 +188,8 @@ __device__ __forceinline__ void for_nodes(int n, Term term)
     for (; i < n; ++i) term(i);
 }
 
-// Element sums in the frame, per field point (unit element charge).  EXP: r^2 expanded
-// (long rules); otherwise from the differences da = p1 - a, db = p2 - b (the short rules
-// of the distance-ratio levels, where the per-pair set-up of the expansion does not pay).
+// Element sums in the frame, per field point (unit element charge).  EXP: r^2 expanded;
+// otherwise from the differences da = p1 - a, db = p2 - b (the gradient).
 //   kFarField  (sum w/r, sum w a/r^3, sum w b/r^3, sum w/r^3) expanded, the field's in-plane
 //              parts following as p1 sum w/r^3 - sum w a/r^3 and likewise for b;
 //              (sum w/r, sum w da/r^3, sum w db/r^3, sum w/r^3) from differences;
@@ -455,8 +453,8 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
 
 // Offsets of the lane's points from element j of the tile: D^2 in FP64 (the distance test,
 // Sec. 2) and the coordinates in the element's frame, in the precision of the node sums;
-// EXP: with -2 p and |p|^2 for the expanded r^2, else with p3^2.
-template <bool EXP, int PPT, typename Lds, typename T>
+// EXP: with -2 p and |p|^2 for the expanded r^2; H2: with p3^2 (differences, rows).
+template <bool EXP, bool H2 = !EXP, int PPT, typename Lds, typename T>
 __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[PPT], const double (&y)[PPT],
                                          const double (&z)[PPT], double (&D2)[PPT], Local<PPT, T>& L)
 {
@@ -473,9 +471,8 @@ __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[
             L.q1[k] = T(-2) * L.p1[k];
             L.q2[k] = T(-2) * L.p2[k];
             L.H[k] = (T)D2[k];
-        } else {
-            L.h[k] = L.p3[k] * L.p3[k];
         }
+        if constexpr (H2) L.h[k] = L.p3[k] * L.p3[k];
     }
 }
 
@@ -582,7 +579,7 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<false>(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<MODE != kFarGrad, true>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
             int lvl[PPT];
 #pragma unroll
@@ -601,11 +598,12 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             T o[Sums<MODE>::kNode][PPT];
             const int b = j * nn;
             int nw;
-            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE, false>(s, b, o1, L, o); nw = o1; }
-            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE, false>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
-            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE, false>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
+            constexpr bool X = MODE != kFarGrad;
+            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE, X>(s, b, o1, L, o); nw = o1; }
+            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE, X>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
+            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE, X>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
             else {
-                element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE, false>(s, b + o3, nn - o3, L, o);
+                element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE, X>(s, b + o3, nn - o3, L, o);
                 nw = nn - o3;
             }
 #pragma unroll
