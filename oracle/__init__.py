@@ -191,7 +191,8 @@ def gradient_matrix(g6):
 
 
 def collocation(tri, rect, sigma, rows=None, prm=None, nthreads=0):
-    """out[n_rhs, n_rows]: potential at element centroids (rows) from densities sigma[n_rhs, n_E]."""
+    """out[n_rhs, n_rows]: potential at element centroids (rows) from densities sigma[n_rhs, n_E];
+    abs[n_rhs, n_rows]: K sum_j |sigma_rj phi_j| per right-hand side (error normaliser)."""
     lib = _load()
     prm = prm or params()
     tri = _f64(tri if tri is not None else np.zeros((0, 9)), 9)
@@ -200,7 +201,7 @@ def collocation(tri, rect, sigma, rows=None, prm=None, nthreads=0):
     sigma = _f64(sigma).reshape(-1, ne)
     nrhs = sigma.shape[0]
     rows = np.arange(ne, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
-    out = np.zeros((nrhs, rows.size)); aout = np.zeros(rows.size)
+    out = np.zeros((nrhs, rows.size)); aout = np.zeros((nrhs, rows.size))
     st = _Stats()
     rc = lib.orc_collocation(_ptr(tri), tri.shape[0], _ptr(rect), rect.shape[0], _ptr(sigma), nrhs,
                              ctypes.byref(prm), rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

@@ -823,16 +823,21 @@ int orc_collocation(const double* tri, int64_t n_tri, const double* rect, int64_
 #pragma omp for schedule(dynamic, 4)
         for (int64_t k = 0; k < n_rows; ++k) {
             const double* P = el[rows[k]].cen;
-            for (int r = 0; r < n_rhs; ++r) { acc[r].s = 0.0; acc[r].c = 0.0; }
-            double a0 = 0.0;
+            double ab[64];
+            for (int r = 0; r < n_rhs; ++r) { acc[r].s = 0.0; acc[r].c = 0.0; ab[r] = 0.0; }
             for (int64_t j = 0; j < ne; ++j) {
                 double c[11];
                 element_contribution(P, &el[j], R, prm, c, &ls);
-                for (int r = 0; r < n_rhs; ++r) nadd(&acc[r], sigma[(int64_t)r * ne + j] * c[0]);
-                a0 += fabs(sigma[j] * c[0]);
+                for (int r = 0; r < n_rhs; ++r) {
+                    const double t = sigma[(int64_t)r * ne + j] * c[0];
+                    nadd(&acc[r], t);
+                    ab[r] += fabs(t);
+                }
             }
-            for (int r = 0; r < n_rhs; ++r) out[(int64_t)r * n_rows + k] = K * nval(&acc[r]);
-            if (abs_out) abs_out[k] = K * a0;
+            for (int r = 0; r < n_rhs; ++r) {
+                out[(int64_t)r * n_rows + k] = K * nval(&acc[r]);
+                if (abs_out) abs_out[(int64_t)r * n_rows + k] = K * ab[r];
+            }
         }
 #pragma omp critical
         merge_stats(&tot, &ls);

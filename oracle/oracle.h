@@ -88,8 +88,9 @@ int orc_eval_gradient(const double* tri, int64_t n_tri, const double* rect, int6
 
 /* Matrix-free collocation product: out[r][k] = potential at the centroid of element
  * rows[k] from all elements with density sigma[r][:], r < n_rhs.  The element's own
- * contribution is its on-element (self) integral.  abs_out[k] (optional) = sum over
- * elements of |phi_j| for the first right-hand side.  Returns threads used or < 0. */
+ * contribution is its on-element (self) integral.  abs_out[r][k] (optional) = K times the
+ * sum over elements j of |sigma[r][j] phi_j| (the row's own per-element potentials, the
+ * normaliser of errors of right-hand side r).  Returns threads used or < 0. */
 int orc_collocation(const double* tri, int64_t n_tri, const double* rect, int64_t n_rect,
                     const double* sigma, int n_rhs, const orc_params* prm,
                     const int64_t* rows, int64_t n_rows, double* out, double* abs_out,

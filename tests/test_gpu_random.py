@@ -103,7 +103,7 @@ def test_random_soup_gradient_and_collocation(seed):
         out = ctx.collocation(s, precision=precision)
         torch.cuda.synchronize()
         eg = np.abs(G.cpu().numpy().T - refg["G"]).max(axis=1) / refg["abs_T"]
-        ec = np.abs(out.cpu().numpy()[0] - refc["out"][0]) / refc["abs"]
+        ec = np.abs(out.cpu().numpy()[0] - refc["out"][0]) / refc["abs"][0]
         print(f"soup {seed} rules {tri_rule}/{rect_rule} {precision}: gradient {eg.max():.2e} "
               f"collocation {ec.max():.2e}")
         assert rc == 0 and eg.max() <= TOL[precision] and ec.max() <= TOL[precision]

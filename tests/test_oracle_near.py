@@ -205,7 +205,7 @@ def test_collocation_single_element_and_linearity(orc):
     col = orc.collocation(tri, rect, sig)
     assert col["stats"]["on_surface"] == ne
     col2 = orc.collocation(tri, rect, sig[0] + 2.0 * sig[1])
-    assert np.allclose(col2["out"][0], col["out"][0] + 2.0 * col["out"][1], rtol=0, atol=1e-13 * np.max(col["abs"]))
+    assert np.allclose(col2["out"][0], col["out"][0] + 2.0 * col["out"][1], rtol=0, atol=1e-13 * np.max(col["abs"][0]))
     rows = np.array([3, 0, ne - 1])
     sub = orc.collocation(tri, rect, sig, rows=rows)
     assert np.array_equal(sub["out"], col["out"][:, rows])
