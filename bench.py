@@ -32,6 +32,7 @@ PEAK_HBM_GBPS = 8000.0    # HBM3E
 FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
 FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
 GRAD_FLOP_PER_NODE_INT = 30  # field gradient (six components) per point-charge term
+COLLOC_FLOP_PER_NODE_INT = 11  # potential only (collocation product) per point-charge term
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_hbm.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_valu.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
@@ -84,11 +85,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--serving-queries", type=int, default=120)
+    ap.add_argument("--serving-queries", type=int, default=120, help="fixed-rule serving leg (queries)")
+    ap.add_argument("--serving-queries-dr", type=int, default=2000, help="distance-ratio serving leg (queries)")
+    ap.add_argument("--side-steps", type=int, default=5, help="timed steps of the side legs (at most --steps)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (points)")
     ap.add_argument("--quick", action="store_true", help="skip collocation, serving and the CPU baseline")
     ap.add_argument("--profile-only", action="store_true",
-                    help="one FP64 evaluation and nothing else (for counter runs)")
+                    help="calibration copies and one evaluation of each profiled kernel (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); every box in this setup "
@@ -117,7 +120,7 @@ def main():
     n = pts.shape[1]
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     E = torch.empty((3, n), dtype=torch.float64, device=dev)
-    ctx.set_near_capacity(40_000_000)
+    ctx.set_near_capacity(40_000_000)  # fixed: evaluations never wait on the host
     torch.cuda.synchronize()
 
     if args.profile_only:
@@ -130,12 +133,23 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        ctx.eval(pts, "fp64", phi=phi, E=E)
-        torch.cuda.synchronize()
-        log(f"profile run: FP64 evaluation done: {ctx.stats()}")
-        ctx.eval(pts, "mixed", phi=phi, E=E)
-        torch.cuda.synchronize()
-        log(f"profile run: mixed evaluation done: {ctx.stats()}")
+        for dr in (False, True):
+            ctx.set_dr_rules(dr)
+            for prec in ("fp64", "mixed"):
+                ctx.eval(pts, prec, phi=phi, E=E)
+                torch.cuda.synchronize()
+                log(f"profile run: {prec} evaluation (rule choice by DR {dr}) done: {ctx.stats()}")
+        ctx.set_dr_rules(False)
+        ctx.close()
+        wc = W.nested_cylinders_workload()
+        cctx = bemc.Context(0)
+        cctx.upload_geometry(wc.tri, wc.rect)
+        sig = torch.tensor(wc.sigma, dtype=torch.float64, device=dev)
+        for prec in ("fp64", "mixed"):
+            cctx.collocation(sig, prec)
+            torch.cuda.synchronize()
+            log(f"profile run: {prec} collocation product (200,000 elements, 8 densities) done: {cctx.stats()}")
+        cctx.close()
         return
 
     def timed(precision, steps, warmup):
@@ -155,20 +169,21 @@ def main():
 
     dt64, far64, st64 = timed("fp64", args.steps, args.warmup)
     phi64, E64 = phi.cpu().numpy(), E.cpu().numpy().T.copy()
-    dtmx, farmx, stmx = timed("mixed", args.steps, args.warmup)
+    side = max(1, min(args.steps, args.side_steps))
+    dtmx, farmx, stmx = timed("mixed", side, 1)
     phimx, Emx = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     # rule choice by distance ratio (fewest Gaussian points at the accuracy floor per pair)
     ctx.set_dr_rules(True)
-    dtdr, fardr, stdr = timed("fp64", args.steps, 1)
+    dtdr, fardr, stdr = timed("fp64", side, 1)
     phidr, Edr = phi.cpu().numpy(), E.cpu().numpy().T.copy()
-    dtdrm, fardrm, stdrm = timed("mixed", args.steps, 1)
+    dtdrm, fardrm, stdrm = timed("mixed", side, 1)
     phidrm, Edrm = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     ctx.set_dr_rules(False)
     # Table B5 for the rectangles (33 points, degree 13) instead of 7 x 7 Gauss (49 points)
     ctx.set_rules(w.tri_rule, -33)
-    dtb5, farb5, stb5 = timed("fp64", args.steps, 1)
+    dtb5, farb5, stb5 = timed("fp64", side, 1)
     phib5, Eb5 = phi.cpu().numpy(), E.cpu().numpy().T.copy()
-    dtb5m, farb5m, stb5m = timed("mixed", args.steps, 1)
+    dtb5m, farb5m, stb5m = timed("mixed", side, 1)
     phib5m, Eb5m = phi.cpu().numpy(), E.cpu().numpy().T.copy()
     ctx.set_rules(w.tri_rule, w.rect_gl_n)
 
@@ -229,8 +244,8 @@ def main():
     mixed_ach = alg_flops / (1e-3 * float(np.mean(farmx))) / 1e12
     counted32 = counted_flops_from_profile("counted_fp32_flops_per_launch_mixed")
     c32 = None if counted32 is None else counted32 / (1e-3 * float(np.mean(farmx))) / 1e12
-    out["mixed"] = {"value": pairs * args.steps / dtmx, "unit": "pairs/s", "ms_per_step": 1e3 * dtmx / args.steps,
-                    "speedup_vs_fp64": dt64 / dtmx, "far_kernel_ms": float(np.mean(farmx)),
+    out["mixed"] = {"value": pairs * side / dtmx, "unit": "pairs/s", "ms_per_step": 1e3 * dtmx / side,
+                    "speedup_vs_fp64": (dt64 / args.steps) / (dtmx / side), "far_kernel_ms": float(np.mean(farmx)),
                     "roofline": {"bound": "alu", "achieved": mixed_ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                  "frac": mixed_ach / PEAK_FP32_TFLOPS,
                                  "counted_fp32_tflops": c32,
@@ -243,17 +258,23 @@ def main():
     out["gradient"] = {k: {kk: vv for kk, vv in v.items() if kk != "G"} for k, v in grad.items()}
     out["gradient"]["flops_per_node_interaction"] = GRAD_FLOP_PER_NODE_INT
 
-    out["dr_rules"] = {"value": pairs * args.steps / dtdr, "unit": "pairs/s", "precision": "fp64",
-                       "ms_per_step": 1e3 * dtdr / args.steps, "far_kernel_ms": float(np.mean(fardr)),
+    dr_flops = FLOP_PER_NODE_INT * stdr["node_interactions"] + FLOP_PER_PAIR * pairs
+    dr_ach = dr_flops / (1e-3 * float(np.mean(fardr))) / 1e12
+    out["dr_rules"] = {"value": pairs * side / dtdr, "unit": "pairs/s", "precision": "fp64",
+                       "ms_per_step": 1e3 * dtdr / side, "far_kernel_ms": float(np.mean(fardr)),
                        "node_interactions": stdr["node_interactions"],
+                       "node_interactions_per_pair_choice": stdr["node_interactions_pair_rule"],
                        "node_interactions_fixed_rules": node_int,
-                       "mixed_value": pairs * args.steps / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
+                       "roofline": {"bound": "alu", "achieved": dr_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": dr_ach / PEAK_FP64_TFLOPS,
+                                    "note": "20 flops per executed node interaction + 16 per pair"},
+                       "mixed_value": pairs * side / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
                        "rules": "triangles 7/12/19/33 points for DR >= 100/25/10/3, rectangles Tables B2/B3/B4 "
                                 "and 7x7 Gauss for DR >= 150/40/15/3"}
-    out["rect_table_b5"] = {"value": pairs * args.steps / dtb5, "unit": "pairs/s", "precision": "fp64",
-                            "ms_per_step": 1e3 * dtb5 / args.steps, "far_kernel_ms": float(np.mean(farb5)),
+    out["rect_table_b5"] = {"value": pairs * side / dtb5, "unit": "pairs/s", "precision": "fp64",
+                            "ms_per_step": 1e3 * dtb5 / side, "far_kernel_ms": float(np.mean(farb5)),
                             "node_interactions": stb5["node_interactions"],
-                            "mixed_value": pairs * args.steps / dtb5m, "mixed_far_kernel_ms": float(np.mean(farb5m)),
+                            "mixed_value": pairs * side / dtb5m, "mixed_far_kernel_ms": float(np.mean(farb5m)),
                             "rules": "33-point triangles, Table B5 (33 points) rectangles"}
 
     if not args.quick:
@@ -335,8 +356,16 @@ def main():
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             st = cctx.stats()
+            rhs = wc.sigma.shape[0]
+            cflops = COLLOC_FLOP_PER_NODE_INT * st["node_interactions"] + 2 * rhs * st["pairs"]
+            peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+            ach = cflops / (1e-3 * st["far_ms"]) / 1e12
             colloc[prec] = {"ms": 1e3 * dt, "pairs_per_s": st["pairs"] / dt, "near_pairs": st["near_pairs"],
-                            "far_kernel_ms": st["far_ms"], "near_kernel_ms": st["near_ms"]}
+                            "far_kernel_ms": st["far_ms"], "near_kernel_ms": st["near_ms"],
+                            "node_interactions": st["node_interactions"],
+                            "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                                         "frac": ach / peak,
+                                         "note": "11 flops per node interaction + 2 per pair and density"}}
         rows = np.random.default_rng(3).choice(wc.n_elements, 64, replace=False)
         cref = oracle.collocation(wc.tri, wc.rect, wc.sigma, rows=rows)
         got64 = res  # last result is mixed; recompute fp64 for the check
@@ -351,16 +380,50 @@ def main():
         cctx.close()
 
         out["solver"] = solver_bench(torch, bemc, W)
+        out["icosphere"] = icosphere_bench(torch, bemc, W, reps=1000)
 
-        if args.serving_queries > 0:
+        if args.serving_queries > 0 or args.serving_queries_dr > 0:
             # one stream for long batches, one for queries of <= 4096 points; fixed rules,
-            # then the rule choice by distance ratio on the same stream of queries
+            # then the rule choice by distance ratio on a longer prefix of the same stream;
+            # served results of sampled queries checked against the oracle
             g = W.serving_geometry()
             policy = dict(max_batch_points=1 << 16, small_query_points=4096, n_streams=2)
-            out["serving"] = serving(args.serving_queries, torch, bemc, W, g=g, **policy)
-            out["serving_dr"] = serving(args.serving_queries, torch, bemc, W, g=g, dr=True, **policy)
+            if args.serving_queries > 0:
+                out["serving"] = serving(args.serving_queries, torch, bemc, W, g=g, check=4, **policy)
+            if args.serving_queries_dr > 0:
+                out["serving_dr"] = serving(args.serving_queries_dr, torch, bemc, W, g=g, dr=True, check=8, **policy)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def icosphere_bench(torch, bemc, W, reps):
+    """The 1,280-triangle icosphere with 4,096 points and the 7-point rule (every pair far):
+    a launch-bound evaluation, timed over `reps` evaluations enqueued back to back."""
+    log(f"icosphere: {reps} evaluations")
+    w = W.icosphere_workload()
+    ctx = bemc.Context(0)
+    ctx.set_rules(7, 7)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    ctx.set_near_capacity(1 << 16)  # fixed (no near pairs on this workload)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    n = pts.shape[1]
+    phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    E = torch.empty((3, n), dtype=torch.float64, device="cuda:0")
+    for _ in range(20):
+        ctx.eval(pts, "fp64", phi=phi, E=E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval(pts, "fp64", phi=phi, E=E)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    return {"workload": "icosphere R=1, 1,280 triangles (7-point rule), 4,096 points in 2 <= r <= 10",
+            "reps": reps, "us_per_eval": 1e6 * dt / reps, "pairs_per_s": st["pairs"] * reps / dt,
+            "far_kernel_us": 1e3 * st["far_ms"], "near_pairs": st["near_pairs"],
+            "note": "each evaluation: Morton ordering, near-pair list, far field, near stage, unordering"}
 
 
 def solver_bench(torch, bemc, W):
@@ -397,9 +460,11 @@ def solver_bench(torch, bemc, W):
 
 
 def serving(n_queries, torch, bemc, W, g=None, dr=False, small_query_points=4096, max_batch_points=1 << 16,
-            n_streams=2):
+            n_streams=2, check=0):
     """Open-loop Poisson arrivals on the 1,000,000-element cylinder: saturation rate from a
-    burst, then arrivals at 0.7 x that rate; latency = arrival -> results in host memory."""
+    burst of (at most) the first 500 queries, then arrivals at 0.7 x that rate; latency =
+    arrival -> results in host memory.  check > 0: that many served queries (32 points of
+    each) are compared with the oracle."""
     log(f"serving: 1,000,000-element cylinder, {n_queries} queries, rule choice by DR {dr}, "
         f"short-query class {small_query_points}, batch {max_batch_points}, {n_streams} streams")
     g = g or W.serving_geometry()
@@ -413,13 +478,14 @@ def serving(n_queries, torch, bemc, W, g=None, dr=False, small_query_points=4096
     Es = [np.empty((s, 3)) for s in sizes]
     ctx.server_start(mem_budget_bytes=16 << 30, max_batch_points=max_batch_points, n_streams=n_streams,
                      precision="mixed", small_query_points=small_query_points)
-    # warm-up and saturation rate (all queries at once)
+    # warm-up and saturation rate (a burst of the first queries at once)
+    n_burst = min(n_queries, 500)
     t0 = time.perf_counter()
-    tickets = [ctx.server_submit(qpts[i], phis[i], Es[i]) for i in range(n_queries)]
+    tickets = [ctx.server_submit(qpts[i], phis[i], Es[i]) for i in range(n_burst)]
     for t in tickets:
         ctx.server_wait(t)
     burst = time.perf_counter() - t0
-    sat_rate = n_queries / burst
+    sat_rate = n_burst / burst
     log(f"serving burst: {burst:.2f} s ({sat_rate:.1f} queries/s)")
     rate = 0.7 * sat_rate
     arrivals = W.poisson_arrivals(n_queries, rate)
@@ -439,7 +505,24 @@ def serving(n_queries, torch, bemc, W, g=None, dr=False, small_query_points=4096
     lat = np.array(lat)
     log(f"serving open loop: p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
     lat_small = lat[np.array(sizes) <= max(small_query_points, 4096)]
+    accuracy = None
+    if check > 0:
+        import oracle
+
+        rng = np.random.default_rng(11)
+        qs = rng.choice(n_queries, check, replace=False)
+        sel = [(q, rng.choice(sizes[q], min(32, sizes[q]), replace=False)) for q in qs]
+        P = np.concatenate([qpts[q][i] for q, i in sel])
+        log(f"serving: oracle on {P.shape[0]} served points of {check} queries")
+        ref = oracle.evaluate(g.tri, g.rect, g.sigma[0], P, oracle.params(33, 7, dr_rules=dr), with_abs=True)
+        ph = np.concatenate([phis[q][i] for q, i in sel])
+        Ev = np.concatenate([Es[q][i] for q, i in sel])
+        ep = np.abs(ph - ref["phi"]) / ref["abs_phi"]
+        ee = np.sum(np.abs(Ev - ref["E"]), axis=1) / ref["abs_E"]
+        accuracy = {"points": int(P.shape[0]), "queries": int(check), "max_norm_err_phi": float(ep.max()),
+                    "max_norm_err_E": float(ee.max()), "within_1e-6": bool(ep.max() <= 1e-6 and ee.max() <= 1e-6)}
     return {"workload": g.name, "queries": int(n_queries), "points": int(np.sum(sizes)),
+            "accuracy_vs_oracle": accuracy, "burst_queries": n_burst,
             "precision": "mixed far field, FP64 near field",
             "rules": "by distance ratio" if dr else "33-point triangles, 7x7 rectangles",
             "policy": {"max_batch_points": max_batch_points, "streams": n_streams,

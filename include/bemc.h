@@ -20,9 +20,15 @@
  * coordinates about the point (principal value for the in-plane field, zero normal part).
  *
  * Conventions.
- *   * All entry points return BEMC_OK (0), a negative BEMC_E_* error, or (bemc_eval and
- *     bemc_eval_gradient only) the positive warning BEMC_W_ON_SURFACE.  On error, bemc_last_error() gives a
+ *   * All entry points return BEMC_OK (0), a negative BEMC_E_* error, or (bemc_query_stats
+ *     only) the positive warning BEMC_W_ON_SURFACE.  On error, bemc_last_error() gives a
  *     message for the calling thread.  No entry point aborts the process.
+ *   * Evaluations (bemc_eval, bemc_eval_gradient, bemc_collocation_matvec) are enqueued on
+ *     the caller's stream and return before they have run; the caller synchronizes the
+ *     stream (or calls bemc_query_stats) before it reads the results.  Problems that show
+ *     only on the device (an overflowing fixed near-pair list, the subdivision visit limit,
+ *     points on elements) are reported by bemc_query_stats, and errors also by the next
+ *     evaluation call that finds the earlier call finished.
  *   * "device" pointers are GPU memory of the context's device (e.g. torch tensors on
  *     cuda:N); "host" pointers are ordinary CPU memory.  The caller owns every buffer it
  *     passes; the library copies host inputs before returning.
@@ -87,8 +93,13 @@ typedef struct {
     int64_t on_surface;     /* pairs whose field point lies on the element */
     int64_t max_depth;      /* deepest subdivision level reached */
     int64_t near_capacity;  /* current size of the near-pair list */
-    double far_ms;          /* far-field kernel time (HIP events) */
-    double near_ms;         /* near-field kernel time (HIP events) */
+    double far_ms;          /* far-field kernel time (HIP events around its launch) */
+    double near_ms;         /* what follows it: chunk reduction, near-list regrouping, near
+                               field and ordered sums (HIP events) */
+    int64_t node_interactions_pair_rule; /* rule choice by distance ratio: the terms if every
+                                            far pair summed its own level (a wavefront sums
+                                            the finest level any of its pairs needs); else
+                                            node_interactions */
 } bemc_stats;
 
 /* Message for the last non-OK status returned to this host thread ("" if none). */
@@ -105,8 +116,10 @@ int bemc_destroy(bemc_handle h);
 /* Cubature rules and near-field parameters (Sec. 3, Tables A1-A5, B1-B5; Sec. 4
  * distance-ratio switch).  tri_rule in {4, 7, 12, 19, 33}; rect_rule in 1..16 for the
  * tensor Gauss-Legendre rule with rect_rule^2 points, or -4, -7, -12, -17, -33 for Table
- * B1..B5 (App. B); near_dr > 0 (pairs with D < near_dr * L are subdivided); max_depth in
- * 0..30.  Takes effect for subsequent evaluations; node tables are rebuilt.
+ * B1..B5 (App. B); near_dr >= 2 (pairs with D < near_dr * L are subdivided; the far-field
+ * sums expand r^2 about the centroid, whose rounding stays bounded at these distance
+ * ratios, also in FP32); max_depth in 0..30.  Takes effect for subsequent evaluations;
+ * node tables are rebuilt.
  * Errors: INVALID_ARG. */
 int bemc_set_rules(bemc_handle h, int tri_rule, int rect_rule, double near_dr, int max_depth);
 
@@ -153,15 +166,21 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
  * The points are processed in Morton (Z-curve) order, which keeps the points of a
  * wavefront close together; results are returned in the caller's order and do not depend
  * on that order.  The ordering workspace (about 110 bytes per point) is kept by the context.
- * The call enqueues the far-field kernel (classification, near-pair compaction and the
- * point-charge sums) and the FP64 near-field kernel on `stream` and returns after both
- * have finished (it waits on the host for the near-pair count: when the near-pair list
- * overflowed, the list is grown and the evaluation repeated).  Results are reproducible
- * bit for bit: far-field chunks are added in fixed order, and each point's near pairs
- * are summed in element order.  Returns BEMC_W_ON_SURFACE
- * when a field point lies on an element (its field there is the principal value).
- * Errors: NO_GEOMETRY, INVALID_ARG, LIMIT (n >= 2^31, or a near pair needed more than
- * 2^22 subdivision steps), OUT_OF_MEMORY, DEVICE. */
+ * The call enqueues on `stream` the near-pair list (every pair with D < near_dr L, by a
+ * classification pass), the far-field kernel (point-charge sums of the other pairs) and the
+ * FP64 near field, and returns without waiting for them.  With a growing near-pair list
+ * (the default, see bemc_set_near_capacity) the host reads the list pass's pair count --
+ * a wait of about a millisecond, while the far field is already queued behind it -- and,
+ * if the list was too short, grows it and repeats the list pass (never the far field)
+ * before it enqueues the near field.  With a fixed list there is no host wait at all.
+ * Results are reproducible bit for bit: far-field chunks are added in fixed order, and
+ * each point's near pairs are summed in element order.  A field point lying on an
+ * element gets the principal-value field there; bemc_query_stats then returns
+ * BEMC_W_ON_SURFACE.  Consecutive calls on one context may use different streams (each
+ * call waits on the device for the previous one).
+ * Errors: NO_GEOMETRY, INVALID_ARG, LIMIT (n >= 2^31; or reported from an earlier call:
+ * a fixed near-pair list overflowed, or a near pair needed more than 2^22 subdivision
+ * steps), OUT_OF_MEMORY, DEVICE. */
 int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
               double* phi, double* E, void* stream);
 
@@ -174,8 +193,8 @@ int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rh
  * subdivision, rule choice (including bemc_set_dr_rules) and precision handling are those
  * of bemc_eval; BEMC_MIXED forms the FP32 node sums from unit vectors d/r (no power of 1/r
  * above the third in FP32).  A field point lying on an element gets NaN in all six rows
- * (the normal field jumps there) and the call returns BEMC_W_ON_SURFACE.  Synchronous
- * like bemc_eval.  Errors: as bemc_eval. */
+ * (the normal field jumps there) and bemc_query_stats returns BEMC_W_ON_SURFACE.
+ * Asynchronous like bemc_eval.  Errors: as bemc_eval. */
 int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
                        double* G, void* stream);
 
@@ -184,8 +203,8 @@ int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precisio
  * densities sigma[r][:], r < n_rhs (1..8), for every element i.  sigma and out are device
  * arrays [n_rhs][n_E].  The element's own contribution is its exact on-element integral;
  * neighbours below near_dr are subdivided in FP64.  precision as in bemc_eval (far pairs
- * only).  Independent of the densities of bemc_upload_densities.  Returns after the work
- * has finished, like bemc_eval.  Errors: NO_GEOMETRY, INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+ * only).  Independent of the densities of bemc_upload_densities.  Asynchronous like
+ * bemc_eval.  Errors: NO_GEOMETRY, INVALID_ARG, LIMIT, OUT_OF_MEMORY, DEVICE. */
 int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision,
                             double* out, void* stream);
 
@@ -212,14 +231,22 @@ typedef struct {
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
                          int restart, int precision, bemc_solve_info* info, void* stream);
 
-/* Pre-size the near-pair list (8 bytes per pair, plus 24 for its regrouping and 8 per
+/* Size of the near-pair list (8 bytes per pair, plus 24 for its regrouping and 8 per
  * result row -- 4 for the field, 6 for the gradient -- allocated at the next evaluation;
- * at most 2^32 - 1 pairs).  The list also grows by itself when an evaluation finds more
- * near pairs than it holds (the evaluation is then repeated), so this only avoids that
- * repetition.  Errors: INVALID_ARG, LIMIT, OUT_OF_MEMORY. */
-int bemc_set_near_capacity(bemc_handle h, int64_t pairs);
+ * 1 <= pairs <= 2^32 - 1).  grow != 0: the list starts at this size and grows to what an
+ * evaluation needs (the default policy, starting at max(2^20, 8 n) pairs; the host reads
+ * each evaluation's pair count before it enqueues the near field).  grow = 0: the size is
+ * fixed and evaluations never wait on the host; an evaluation that finds more near pairs
+ * evaluates the near field of those that fit only, and bemc_query_stats (and the next
+ * evaluation call) reports BEMC_E_LIMIT.  Waits for the evaluations in flight.
+ * Errors: INVALID_ARG, LIMIT, OUT_OF_MEMORY. */
+int bemc_set_near_capacity(bemc_handle h, int64_t pairs, int grow);
 
-/* Counters of the last evaluation.  Errors: INVALID_ARG. */
+/* Waits for the last evaluation on the context and returns its counters.  Returns
+ * BEMC_W_ON_SURFACE when some of its field points lie on an element, BEMC_E_LIMIT (once)
+ * when an evaluation since the last report overflowed a fixed near-pair list or hit the
+ * subdivision visit limit, BEMC_E_DEVICE when one failed on the device.
+ * Errors: INVALID_ARG. */
 int bemc_query_stats(bemc_handle h, bemc_stats* out);
 
 /* ---------------------------------------------------------------------------------

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("node_interactions", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("leaves", ctypes.c_int64), ("cap_hits", ctypes.c_int64),
                 ("on_surface", ctypes.c_int64), ("max_depth", ctypes.c_int64),
-                ("near_capacity", ctypes.c_int64), ("far_ms", ctypes.c_double), ("near_ms", ctypes.c_double)]
+                ("near_capacity", ctypes.c_int64), ("far_ms", ctypes.c_double), ("near_ms", ctypes.c_double),
+                ("node_interactions_pair_rule", ctypes.c_int64)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -98,7 +99,7 @@ def load_library():
     lib.bemc_eval_gradient.argtypes = [vp, vp, i64, ci, ci, vp, vp]
     lib.bemc_collocation_matvec.argtypes = [vp, vp, ci, ci, vp, vp]
     lib.bemc_query_stats.argtypes = [vp, ctypes.POINTER(Stats)]
-    lib.bemc_set_near_capacity.argtypes = [vp, i64]
+    lib.bemc_set_near_capacity.argtypes = [vp, i64, ci]
     lib.bemc_set_dr_rules.argtypes = [vp, ci, vp, vp]
     lib.bemc_solve_densities.argtypes = [vp, vp, vp, ctypes.c_double, ci, ci, ci, ctypes.POINTER(SolveInfo), vp]
     lib.bemc_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig)]
@@ -209,7 +210,9 @@ class Context:
 
     # -- evaluation
     def eval(self, pts, precision="fp64", rhs=0, with_E=True, phi=None, E=None):
-        """pts: float64 CUDA tensor [3, n] (SoA).  Returns (phi [n], E [3, n] or None, status)."""
+        """pts: float64 CUDA tensor [3, n] (SoA).  Returns (phi [n], E [3, n] or None, status of
+        the call).  The evaluation is enqueued on the current stream; stats() waits for it and
+        reports points on elements (status W_ON_SURFACE)."""
         torch = _torch()
         n = pts.shape[1]
         _dev_f64(pts, (3, n))
@@ -223,7 +226,8 @@ class Context:
         return phi, (E if with_E else None), rc
 
     def eval_gradient(self, pts, precision="fp64", rhs=0, G=None):
-        """pts: float64 CUDA tensor [3, n].  Returns (G [6, n] rows xx yy zz xy xz yz, status)."""
+        """pts: float64 CUDA tensor [3, n].  Returns (G [6, n] rows xx yy zz xy xz yz, status of
+        the call); enqueued like eval()."""
         torch = _torch()
         n = pts.shape[1]
         _dev_f64(pts, (3, n))
@@ -244,8 +248,10 @@ class Context:
                                                 _dev_f64(out, tuple(s.shape)), _stream_ptr()))
         return out
 
-    def set_near_capacity(self, pairs):
-        _check(self.lib.bemc_set_near_capacity(self.h, int(pairs)))
+    def set_near_capacity(self, pairs, grow=False):
+        """Near-pair list of `pairs` entries; grow=False: fixed (evaluations never wait on the
+        host, an overflow is reported by stats()), grow=True: grows to what evaluations need."""
+        _check(self.lib.bemc_set_near_capacity(self.h, int(pairs), int(bool(grow))))
 
     def solve(self, potential, tol=1e-10, max_iter=500, restart=50, precision="fp64", sigma=None):
         """Densities sigma [n_E] (CUDA float64) whose collocation potentials equal `potential` [n_E]."""
@@ -260,9 +266,14 @@ class Context:
         return sigma, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
     def stats(self):
+        """Waits for the last evaluation; its counters and "status" (OK or W_ON_SURFACE).
+        Raises for an error of an evaluation since the last report (e.g. an overflowing fixed
+        near-pair list)."""
         st = Stats()
-        _check(self.lib.bemc_query_stats(self.h, ctypes.byref(st)))
-        return {f: getattr(st, f) for f, _ in Stats._fields_}
+        rc = _check(self.lib.bemc_query_stats(self.h, ctypes.byref(st)), allow_warning=True)
+        out = {f: getattr(st, f) for f, _ in Stats._fields_}
+        out["status"] = rc
+        return out
 
     # -- serving
     def server_start(self, mem_budget_bytes=8 << 30, max_batch_points=1 << 17, n_streams=4, precision="mixed",

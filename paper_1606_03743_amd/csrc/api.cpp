@@ -60,6 +60,36 @@ void dev_free(T*& p)
 
 }  // namespace
 
+
+// Device buffers of one evaluation: point ordering, near-pair list and its regrouping,
+// element-chunk partial sums, counters.  The context owns one set that grows on demand;
+// the allocation-free entry point uses a fixed set carved from a static device array.
+struct EvalWork {
+    OrderWork ow{};
+    int64_t ow_cap = 0;              // points
+    NearPair* near = nullptr;
+    unsigned long long near_cap = 0;  // pairs
+    NearWork nw{};
+    int64_t nw_pts = 0;
+    unsigned long long nw_pairs = 0;
+    int nw_rows = 0;
+    double* partial = nullptr;
+    size_t partial_cap = 0;  // doubles
+    DevCounters* ctr = nullptr;
+};
+
+// Record of one enqueued evaluation: pinned copies of its counters and its events.  A
+// small ring of them lets evaluations be in flight while the host goes on.
+struct CallRec {
+    DevCounters* h_ctr = nullptr;   // counters at the end of the call (pinned)
+    DevCounters* h_list = nullptr;  // counters after the near-pair list pass (pinned)
+    hipEvent_t ev_list = nullptr, ev_far0 = nullptr, ev_far1 = nullptr, ev_near1 = nullptr, ev_done = nullptr;
+    bool pending = false;
+    int mode = 0;
+    int64_t pairs = 0, node_ints = 0;  // node_ints < 0: counted on the device
+    unsigned long long cap = 0;
+};
+
 struct bemc_context {
     int device = 0;
     int tri_rule = 33, rect_gl_n = 7, max_depth = 24;  // rect_gl_n < 0: Table B with -rect_gl_n points
@@ -73,11 +103,6 @@ struct bemc_context {
     double tri_dr[3] = { 100.0, 25.0, 10.0 }, rect_dr[3] = { 150.0, 40.0, 15.0 };
     double *d_lv_tri = nullptr, *d_lv_rect = nullptr;
     int lv_tri_off[5] = { 0, 0, 0, 0, 0 }, lv_rect_off[5] = { 0, 0, 0, 0, 0 };
-    // Morton ordering workspace
-    OrderWork ow{};
-    int64_t ow_cap = 0;
-    int ensure_order(int64_t n);
-    void free_order();
     LevelRules levels() const;
 
     // elements (device)
@@ -88,33 +113,37 @@ struct bemc_context {
     int n_rhs = 0;
     bool have_geometry = false;
 
-    // near-pair list and counters
-    NearPair* d_near = nullptr;
-    unsigned long long near_cap = 0;
-    // deterministic near-field accumulation: per-point segments and per-pair results
-    NearWork nw{};
-    int64_t nw_pts = 0;
-    unsigned long long nw_pairs = 0;
-    int nw_rows = 0;
+    // evaluation buffers and the near-pair list policy
+    EvalWork w{};
+    bool near_grow = true;  // the list grows to each evaluation's near-pair count
+    int ensure_order(int64_t n);
+    int ensure_near_capacity(unsigned long long need);
     int ensure_near_work(int64_t n, int rows);
-    void free_near_work();
-    double* d_partial = nullptr;  // element-chunk partial sums
-    size_t partial_cap = 0;       // doubles
-    DevCounters* d_ctr = nullptr;
-    DevCounters* h_ctr = nullptr;  // pinned
-    hipEvent_t ev[4] = { nullptr, nullptr, nullptr, nullptr };
+    int ensure_partial(size_t need);
+    void free_work();
+
+    // evaluations in flight
+    static constexpr int kCallRing = 4;
+    CallRec rec[kCallRing];
+    int rec_next = 0, rec_last = -1;
+    hipStream_t last_stream = nullptr;
+    int sticky = BEMC_OK;  // an error found in an earlier call, reported once
+    std::string sticky_msg;
+    int last_status = BEMC_OK;  // of the last finished call (OK or BEMC_W_ON_SURFACE)
     bemc_stats last{};
+    int finish(int i);          // wait for record i and fold it into last / sticky
+    void poll_finished();       // fold every finished record (no waiting)
+    int drain();                // wait for every pending record
 
     bemc::Server* server = nullptr;
 
     int set_rules_tables();
-    int ensure_near_capacity(unsigned long long need);
     Elements elements() const;
     RuleTables rules() const;
     // mode kNearEval: phi, E at points; kNearColloc: out (= phi) [n_rhs][ne] at centroids;
-    // kNearGrad: G (= phi) [6][n] at points
+    // kNearGrad: G (= phi) [6][n] at points.  noalloc: use the fixed buffers in W.
     int run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
-            double* E, hipStream_t s);
+            double* E, hipStream_t s, EvalWork& W, bool noalloc);
 };
 
 Elements bemc_context::elements() const
@@ -166,6 +195,7 @@ int bemc_context::set_rules_tables()
     if (!triangle_rule(tri_rule, tn)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
     if (!rect_rule_nodes(rect_gl_n, rn)) return fail(BEMC_E_INVALID_ARG, "invalid rectangle rule %d", rect_gl_n);
     HIP_TRY(hipSetDevice(device));
+    if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
     std::vector<double> t64, r64;
     pack_tri(tn, t64);
     pack_rect(rn, r64);
@@ -211,204 +241,312 @@ LevelRules bemc_context::levels() const
     return L;
 }
 
-void bemc_context::free_order()
+// ------------------------------------------------------------ evaluation buffers ---
+namespace {
+void free_order(OrderWork& ow)
 {
     dev_free(ow.keys_in); dev_free(ow.keys_out); dev_free(ow.idx_in); dev_free(ow.perm);
     if (ow.temp) (void)hipFree(ow.temp);
     ow.temp = nullptr;
     dev_free(ow.bbox); dev_free(ow.pts); dev_free(ow.res);
-    ow_cap = 0;
+}
+}  // namespace
+
+void bemc_context::free_work()
+{
+    free_order(w.ow);
+    w.ow_cap = 0;
+    dev_free(w.near);
+    w.near_cap = 0;
+    near_work_free(w.nw);
+    w.nw_pts = 0;
+    w.nw_pairs = 0;
+    w.nw_rows = 0;
+    dev_free(w.partial);
+    w.partial_cap = 0;
 }
 
+// Buffers are only replaced once every evaluation in flight has finished (drain first).
 int bemc_context::ensure_order(int64_t n)
 {
-    if (n <= ow_cap && order_temp_bytes(n) <= ow.temp_bytes) return ok();
-    n = std::max(n, ow_cap);
-    free_order();
+    if (n <= w.ow_cap && order_temp_bytes(n) <= w.ow.temp_bytes) return ok();
+    n = std::max(n, w.ow_cap);
+    if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    free_order(w.ow);
+    w.ow_cap = 0;
     const size_t m = (size_t)n;
-    ow.temp_bytes = order_temp_bytes(n);
-    if (dev_alloc(&ow.keys_in, m) || dev_alloc(&ow.keys_out, m) || dev_alloc(&ow.idx_in, m) || dev_alloc(&ow.perm, m) ||
-        hipMalloc(&ow.temp, std::max<size_t>(ow.temp_bytes, 1)) || dev_alloc(&ow.bbox, 6 * 1024) ||
-        dev_alloc(&ow.pts, 3 * m) || dev_alloc(&ow.res, 6 * m)) {
+    w.ow.temp_bytes = order_temp_bytes(n);
+    if (dev_alloc(&w.ow.keys_in, m) || dev_alloc(&w.ow.keys_out, m) || dev_alloc(&w.ow.idx_in, m) ||
+        dev_alloc(&w.ow.perm, m) || hipMalloc(&w.ow.temp, std::max<size_t>(w.ow.temp_bytes, 1)) ||
+        dev_alloc(&w.ow.bbox, 6 * 1024) || dev_alloc(&w.ow.pts, 3 * m) || dev_alloc(&w.ow.res, 6 * m)) {
         (void)hipGetLastError();
-        free_order();
+        free_order(w.ow);
         return fail(BEMC_E_OUT_OF_MEMORY, "point-ordering workspace for %lld points", (long long)n);
     }
-    ow_cap = n;
+    w.ow_cap = n;
     return ok();
-}
-
-void bemc_context::free_near_work()
-{
-    near_work_free(nw);
-    nw_pts = 0;
-    nw_pairs = 0;
-    nw_rows = 0;
 }
 
 int bemc_context::ensure_near_work(int64_t n, int rows)
 {
-    if (n <= nw_pts && near_cap <= nw_pairs && rows <= nw_rows && near_scan_temp_bytes(n) <= nw.temp_bytes) return ok();
-    const int64_t np = std::max(n, nw_pts);
-    const unsigned long long pairs = std::max(near_cap, nw_pairs);
-    const int nr = std::max(rows, nw_rows);
-    free_near_work();
-    if (near_work_alloc(nw, np, pairs, nr) != hipSuccess)
+    if (n <= w.nw_pts && w.near_cap <= w.nw_pairs && rows <= w.nw_rows && near_scan_temp_bytes(n) <= w.nw.temp_bytes)
+        return ok();
+    const int64_t np = std::max(n, w.nw_pts);
+    const unsigned long long pairs = std::max(w.near_cap, w.nw_pairs);
+    const int nrw = std::max(rows, w.nw_rows);
+    if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    near_work_free(w.nw);
+    w.nw_pts = 0;
+    w.nw_pairs = 0;
+    w.nw_rows = 0;
+    if (near_work_alloc(w.nw, np, pairs, nrw) != hipSuccess)
         return fail(BEMC_E_OUT_OF_MEMORY, "near-field work buffers for %llu pairs", pairs);
-    nw_pts = np;
-    nw_pairs = pairs;
-    nw_rows = nr;
+    w.nw_pts = np;
+    w.nw_pairs = pairs;
+    w.nw_rows = nrw;
     return ok();
 }
 
 int bemc_context::ensure_near_capacity(unsigned long long need)
 {
-    if (need <= near_cap) return ok();
+    if (need <= w.near_cap) return ok();
     if (need > kMaxNearPairs) return fail(BEMC_E_LIMIT, "%llu near pairs exceed the 2^32 - 1 limit", need);
     unsigned long long cap = std::max<unsigned long long>(need, 1ull << 20);
     cap = std::min(cap + cap / 4, kMaxNearPairs);
-    dev_free(d_near);
-    if (dev_alloc(&d_near, (size_t)cap) != hipSuccess) {
-        near_cap = 0;
+    if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    dev_free(w.near);
+    w.near_cap = 0;
+    if (dev_alloc(&w.near, (size_t)cap) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list of %llu entries", cap);
     }
-    near_cap = cap;
+    w.near_cap = cap;
     return ok();
 }
 
-int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc,
-                      double* phi, double* E, hipStream_t s)
+int bemc_context::ensure_partial(size_t need)
+{
+    if (need <= w.partial_cap) return ok();
+    if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    dev_free(w.partial);
+    w.partial_cap = 0;
+    if (dev_alloc(&w.partial, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return BEMC_E_OUT_OF_MEMORY;  // the caller falls back to one chunk
+    }
+    w.partial_cap = need;
+    return ok();
+}
+
+// -------------------------------------------------------- evaluations in flight ---
+int bemc_context::finish(int i)
+{
+    CallRec& r = rec[i];
+    if (!r.pending) return BEMC_OK;
+    r.pending = false;
+    const hipError_t e = hipEventSynchronize(r.ev_done);
+    if (e != hipSuccess) {
+        sticky = BEMC_E_DEVICE;
+        sticky_msg = std::string("an evaluation failed on the device: ") + hipGetErrorString(e);
+        return BEMC_E_DEVICE;
+    }
+    const DevCounters& c = *r.h_ctr;
+    float far_ms = 0.f, near_ms = 0.f;
+    (void)hipEventElapsedTime(&far_ms, r.ev_far0, r.ev_far1);
+    (void)hipEventElapsedTime(&near_ms, r.ev_far1, r.ev_near1);
+    last = bemc_stats{};
+    last.pairs = r.pairs;
+    last.node_interactions = r.node_ints >= 0 ? r.node_ints : (int64_t)c.node_ints;
+    last.near_pairs = (int64_t)c.near_count;
+    last.leaves = (int64_t)c.leaves;
+    last.cap_hits = (int64_t)c.cap_hits;
+    last.on_surface = (int64_t)c.on_surface;
+    last.max_depth = (int64_t)c.max_depth;
+    last.near_capacity = (int64_t)r.cap;
+    last.far_ms = far_ms;
+    last.near_ms = near_ms;
+    last.node_interactions_pair_rule = r.node_ints >= 0 ? r.node_ints : (int64_t)c.node_ints_pair;
+    last_status = (r.mode != kNearColloc && c.on_surface) ? BEMC_W_ON_SURFACE : BEMC_OK;
+    char buf[256];
+    if (c.near_count > r.cap) {
+        snprintf(buf, sizeof buf,
+                 "an evaluation found %llu near pairs but the near-pair list holds %llu: its near field is "
+                 "incomplete (raise bemc_set_near_capacity or let the list grow)",
+                 c.near_count, r.cap);
+        sticky = BEMC_E_LIMIT;
+        sticky_msg = buf;
+    } else if (c.visit_limit_hits) {
+        snprintf(buf, sizeof buf, "%llu near pairs hit the subdivision visit limit", c.visit_limit_hits);
+        sticky = BEMC_E_LIMIT;
+        sticky_msg = buf;
+    }
+    return BEMC_OK;
+}
+
+void bemc_context::poll_finished()
+{
+    for (int i = 0; i < kCallRing; ++i)
+        if (rec[i].pending && hipEventQuery(rec[i].ev_done) == hipSuccess) (void)finish(i);
+}
+
+int bemc_context::drain()
+{
+    int rc = BEMC_OK;
+    // oldest first, so that `last` ends with the latest call
+    for (int k = 1; k <= kCallRing; ++k) {
+        const int i = (rec_next + k - 1) % kCallRing;
+        if (rec[i].pending && finish(i)) rc = BEMC_E_DEVICE;
+    }
+    return rc;
+}
+
+// The pipeline of one evaluation, enqueued on `s`:
+//   Morton ordering of the points (field and gradient);
+//   near-pair list (near_list_kernel: classification with box culling, compaction);
+//   far field (near pairs excluded by the same test), element-chunk reduction;
+//   near-list regrouping, FP64 near field, ordered per-point sums, unordering;
+//   counters to pinned host memory.
+// Growing list (default): the host reads the list pass's pair count after the far field is
+// enqueued and, if the list was too short, grows it and repeats the list pass (never the
+// far field), then enqueues the near field and returns.  Fixed list: no host wait at all; an
+// overflow is reported by bemc_query_stats and the next call.  Allocation-free: the list
+// count is read before the far field is enqueued, and an overflow is an error.
+int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
+                      double* E, hipStream_t s, EvalWork& W, bool noalloc)
 {
     HIP_TRY(hipSetDevice(device));
     const bool colloc = mode == kNearColloc;
     const bool grad = mode == kNearGrad;
-    // Evaluate on Morton-ordered points and scatter the results back at the end: the points
-    // of a wavefront then lie close together, so they mostly need the same rule level (rule
-    // choice by distance ratio) and are near the same elements, which turns the near-pair
-    // records of a wavefront into few contiguous runs.  Per-point results do not depend on
-    // the order.  Collocation points (centroids in element order) are already coherent.
-    const bool ordered = !colloc;
+    const int64_t npts = colloc ? ne : n;
+    const int near_rows = colloc ? 1 : (grad ? 6 : 4);
+    // errors found in finished earlier calls are reported first, once
+    poll_finished();
+    if (sticky) {
+        const int rc = sticky;
+        sticky = BEMC_OK;
+        return fail(rc, "%s", sticky_msg.c_str());
+    }
+    // buffers (the growing ones only change once nothing is in flight)
+    if (!noalloc) {
+        if (!colloc) {
+            int rc = ensure_order(n);
+            if (rc) return rc;
+        }
+        if (W.near_cap == 0) {
+            int rc = ensure_near_capacity(std::max<unsigned long long>(1ull << 20, (unsigned long long)npts * 8));
+            if (rc) return rc;
+        }
+        int rc = ensure_near_work(npts, near_rows);
+        if (rc) return rc;
+    }
+    // element split: many more workgroups than resident slots, so that the dispatcher
+    // balances the tail; the chunk partial sums are reduced in fixed order
+    const int64_t blocks = (npts + 511) / 512;  // nominal 512 points per workgroup (256-768 in fact)
+    int n_split = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (kSplitTargetBlocks + blocks - 1) / blocks));
+    n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 64));  // chunks of >= 64 elements
+    const int64_t rows = colloc ? n_rhs_colloc : (grad ? 6 : 4);
+    if (n_split > 1) {
+        const size_t need = (size_t)n_split * (size_t)rows * (size_t)npts;
+        if (noalloc) {
+            while (n_split > 1 && (size_t)n_split * (size_t)rows * (size_t)npts > W.partial_cap) --n_split;
+        } else if (ensure_partial(need)) {
+            n_split = 1;  // not enough memory for the chunks: one chunk
+        }
+    }
+    // the call record (waits only if the ring is full of calls in flight)
+    const int ri = rec_next;
+    if (rec[ri].pending && finish(ri)) return fail(BEMC_E_DEVICE, "%s", sticky_msg.c_str());
+    rec_next = (rec_next + 1) % kCallRing;
+    CallRec& R = rec[ri];
+    if (rec_last >= 0 && last_stream != s) HIP_TRY(hipStreamWaitEvent(s, rec[rec_last].ev_done, 0));
+
     double* user_phi = phi;
     double* user_E = E;
-    if (ordered) {
-        int rc = ensure_order(n);
-        if (rc) return rc;
-        HIP_TRY(order_points(pts, n, ow, s));
-        pts = ow.pts;
-        phi = ow.res;
-        E = E ? ow.res + n : nullptr;
+    if (!colloc) {
+        HIP_TRY(order_points(pts, n, W.ow, s));
+        pts = W.ow.pts;
+        phi = W.ow.res;
+        E = E ? W.ow.res + n : nullptr;
     }
     double* G = grad ? phi : nullptr;
     if (grad) phi = E = nullptr;
-    if (near_cap == 0) {
-        int rc = ensure_near_capacity(std::max<unsigned long long>(1ull << 20, (unsigned long long)(colloc ? ne : n) * 8));
-        if (rc) return rc;
-    }
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        FarArgs fa{};
-        fa.el = elements(); fa.rules = rules();
-        if (colloc) { fa.el.q = d_qc; fa.el.n_rhs = n_rhs_colloc; } fa.pts = pts; fa.n = colloc ? ne : n; fa.rhs = rhs;
-        fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant(); fa.phi = phi; fa.E = E; fa.G = G; fa.partial = nullptr;
-        fa.elem_begin = 0; fa.elem_end = ne; fa.n_split = 1; fa.chunk = ne; fa.near_list = d_near; fa.near_cap = near_cap;
-        fa.ctr = d_ctr;
-        fa.dr_rules = (dr_rules && !colloc) ? 1 : 0;
-        fa.lv = levels();
-        NearArgs na{};
-        na.el = fa.el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = fa.n; na.rhs = rhs;
-        na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_cap = near_cap;
-        na.ctr = d_ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
-        const int near_rows = colloc ? 1 : (grad ? 6 : 4);
-        {
-            const int64_t np = colloc ? ne : n;
-            int rc = ensure_near_work(np, near_rows);
-            if (rc) return rc;
-        }
-        na.near_list = d_near;
-        na.slot = nw.slot;
-        na.res = nw.res;
-        na.res_stride = nw_pairs;
 
-        // Split the element range over blockIdx.y so that the launch has many more
-        // workgroups than resident slots: the dispatcher then balances the tail.  The chunk
-        // partial sums are reduced in fixed order (results do not depend on scheduling).
-        const int64_t npts = colloc ? ne : n;
-        const int64_t blocks = (npts + 511) / 512;  // nominal 512 points per workgroup (256-768 in fact)
-        int n_split = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (kSplitTargetBlocks + blocks - 1) / blocks));
-        n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 64));  // chunks of >= 64 elements
-        const int64_t rows = colloc ? n_rhs_colloc : (grad ? 6 : 4);
-        if (n_split > 1) {
-            const size_t need = (size_t)n_split * (size_t)rows * (size_t)npts;
-            if (need > partial_cap) {
-                dev_free(d_partial);
-                partial_cap = 0;
-                if (dev_alloc(&d_partial, need) != hipSuccess) {
-                    (void)hipGetLastError();
-                    n_split = 1;  // fall back to one chunk
-                } else {
-                    partial_cap = need;
-                }
-            }
-        }
-        fa.n_split = n_split;
-        fa.chunk = (ne + n_split - 1) / n_split;
-        fa.partial = n_split > 1 ? d_partial : nullptr;
-        HIP_TRY(launch_zero_counters(d_ctr, s));
-        HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(colloc ? launch_far_colloc(fa, precision, s)
-                       : (grad ? launch_far_grad(fa, precision, s) : launch_far_eval(fa, precision, s)));
-        if (n_split > 1) {
-            if (colloc) HIP_TRY(launch_reduce_chunks(d_partial, n_split, rows, npts, fa.K, phi, s));
-            else if (grad) HIP_TRY(launch_reduce_chunks(d_partial, n_split, rows, npts, fa.K, G, s));
-            else HIP_TRY(launch_reduce_split(d_partial, n_split, npts, fa.K, phi, E, s));
-        }
-        HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(near_order(d_near, d_ctr, near_cap, npts, nw, s));
-        HIP_TRY(launch_near(na, mode, s));
-        HIP_TRY(near_reduce(nw, npts, nw_pairs, mode, phi, E, G, fa.el.q, ne, n_rhs_colloc, fa.K, s));
-        HIP_TRY(hipEventRecord(ev[2], s));
-        if (ordered) {
-            if (grad) {
-                HIP_TRY(unorder_rows(ow, n, ow.res, 6, user_phi, s));
-            } else {
-                HIP_TRY(unorder_rows(ow, n, ow.res, 1, user_phi, s));
-                if (user_E) HIP_TRY(unorder_rows(ow, n, ow.res + n, 3, user_E, s));
-            }
-        }
-        HIP_TRY(hipMemcpyAsync(h_ctr, d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(ev[3], s));
-        HIP_TRY(hipEventSynchronize(ev[3]));
-        const unsigned long long found = h_ctr->near_count;
-        if (found > near_cap) {  // list overflowed: grow it and evaluate again
+    Elements el = elements();
+    if (colloc) { el.q = d_qc; el.n_rhs = n_rhs_colloc; }
+    const double* lpts = colloc ? d_cen : pts;
+    HIP_TRY(launch_zero_counters(W.ctr, s));
+    HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
+    const bool read_count = near_grow || noalloc;
+    if (read_count) {
+        HIP_TRY(hipMemcpyAsync(R.h_list, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(R.ev_list, s));
+    }
+    if (noalloc) {
+        HIP_TRY(hipEventSynchronize(R.ev_list));
+        if (R.h_list->near_count > W.near_cap)
+            return fail(BEMC_E_LIMIT, "%llu near pairs exceed the %llu of the fixed scratch buffer",
+                        R.h_list->near_count, W.near_cap);
+    }
+
+    FarArgs fa{};
+    fa.el = el; fa.rules = rules();
+    fa.pts = pts; fa.n = npts; fa.rhs = rhs; fa.n_rhs = n_rhs_colloc; fa.K = coulomb_constant();
+    fa.phi = phi; fa.E = E; fa.G = G;
+    fa.elem_begin = 0; fa.elem_end = ne; fa.n_split = n_split; fa.chunk = (ne + n_split - 1) / n_split;
+    fa.partial = n_split > 1 ? W.partial : nullptr;
+    fa.near_list = W.near; fa.near_cap = W.near_cap; fa.ctr = W.ctr;
+    fa.dr_rules = (dr_rules && !colloc) ? 1 : 0;
+    fa.lv = levels();
+    HIP_TRY(hipEventRecord(R.ev_far0, s));
+    HIP_TRY(colloc ? launch_far_colloc(fa, precision, s)
+                   : (grad ? launch_far_grad(fa, precision, s) : launch_far_eval(fa, precision, s)));
+    HIP_TRY(hipEventRecord(R.ev_far1, s));  // far_ms: the far-field kernel alone
+    if (n_split > 1) {
+        if (colloc) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, phi, s));
+        else if (grad) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, G, s));
+        else HIP_TRY(launch_reduce_split(W.partial, n_split, npts, fa.K, phi, E, s));
+    }
+
+    if (near_grow && !noalloc) {
+        // the far field runs meanwhile; the list pass finished long before it
+        HIP_TRY(hipEventSynchronize(R.ev_list));
+        const unsigned long long found = R.h_list->near_count;
+        if (found > W.near_cap) {  // grow the list and list again
             int rc = ensure_near_capacity(found);
             if (rc) return rc;
-            continue;
+            if ((rc = ensure_near_work(npts, near_rows))) return rc;
+            HIP_TRY(launch_reset_near_count(W.ctr, s));
+            HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
         }
-        float far_ms = 0.f, near_ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&far_ms, ev[0], ev[1]));
-        HIP_TRY(hipEventElapsedTime(&near_ms, ev[1], ev[2]));
-        last = bemc_stats{};
-        last.pairs = npts * ne;
-        last.node_interactions = fa.dr_rules ? (int64_t)h_ctr->node_ints
-                                             : npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
-        last.near_pairs = (int64_t)found;
-        last.leaves = (int64_t)h_ctr->leaves;
-        last.cap_hits = (int64_t)h_ctr->cap_hits;
-        last.on_surface = (int64_t)h_ctr->on_surface;
-        last.max_depth = (int64_t)h_ctr->max_depth;
-        last.near_capacity = (int64_t)near_cap;
-        last.far_ms = far_ms;
-        last.near_ms = near_ms;
-        if (h_ctr->visit_limit_hits)
-            return fail(BEMC_E_LIMIT, "%llu near pairs hit the subdivision visit limit", h_ctr->visit_limit_hits);
-        if (!colloc && h_ctr->on_surface) {
-            g_last_error = grad ? "some field points lie on an element (their gradient is NaN)"
-                                : "some field points lie on an element (principal-value field)";
-            return BEMC_W_ON_SURFACE;
-        }
-        return ok();
     }
-    return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list kept overflowing");
+
+    NearArgs na{};
+    na.el = el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = npts; na.rhs = rhs;
+    na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_cap = W.near_cap;
+    na.ctr = W.ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
+    na.near_list = W.near; na.slot = W.nw.slot; na.res = W.nw.res;
+    HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, W.nw, s));
+    HIP_TRY(launch_near(na, mode, s));
+    HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, s));
+    HIP_TRY(hipEventRecord(R.ev_near1, s));
+    if (!colloc) {
+        if (grad) {
+            HIP_TRY(unorder_rows(W.ow, n, W.ow.res, 6, user_phi, s));
+        } else {
+            HIP_TRY(unorder_rows(W.ow, n, W.ow.res, 1, user_phi, s));
+            if (user_E) HIP_TRY(unorder_rows(W.ow, n, W.ow.res + n, 3, user_E, s));
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(R.h_ctr, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(R.ev_done, s));
+    R.pending = true;
+    R.mode = mode;
+    R.pairs = npts * ne;
+    R.node_ints = fa.dr_rules ? -1 : npts * (n_tri * (int64_t)nt + n_rect * (int64_t)nr);
+    R.cap = W.near_cap;
+    rec_last = ri;
+    last_stream = s;
+    return ok();
 }
 
 // ======================================================================= C ABI ====
@@ -433,15 +571,22 @@ int bemc_create(int device, bemc_handle* out)
     if (device < 0 || device >= ndev) return fail(BEMC_E_INVALID_ARG, "device %d of %d", device, ndev);
     bemc_context* h = new bemc_context();
     h->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete h; return fail(BEMC_E_DEVICE, "hipSetDevice(%d)", device); }
     int rc = h->set_rules_tables();
     if (rc) { bemc_destroy(h); return rc; }
-    if (dev_alloc(&h->d_ctr, 1) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->h_ctr), sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+    if (dev_alloc(&h->w.ctr, 1) != hipSuccess) {
         bemc_destroy(h);
         return fail(BEMC_E_OUT_OF_MEMORY, "counter buffers");
     }
-    for (auto& e : h->ev)
-        if (hipEventCreate(&e) != hipSuccess) { bemc_destroy(h); return fail(BEMC_E_DEVICE, "hipEventCreate"); }
+    for (auto& r : h->rec) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&r.h_ctr), sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&r.h_list), sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+            bemc_destroy(h);
+            return fail(BEMC_E_OUT_OF_MEMORY, "pinned counter buffers");
+        }
+        for (hipEvent_t* e : { &r.ev_list, &r.ev_far0, &r.ev_far1, &r.ev_near1, &r.ev_done })
+            if (hipEventCreate(e) != hipSuccess) { bemc_destroy(h); return fail(BEMC_E_DEVICE, "hipEventCreate"); }
+    }
     *out = h;
     return ok();
 }
@@ -459,16 +604,19 @@ int bemc_destroy(bemc_handle h)
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
     if (h->server) bemc_server_stop(h);
     (void)hipSetDevice(h->device);
+    (void)h->drain();
     (void)hipDeviceSynchronize();
     free_elements(h);
     dev_free(h->d_tri); dev_free(h->d_rect);
     dev_free(h->d_lv_tri); dev_free(h->d_lv_rect);
-    h->free_order();
-    dev_free(h->d_near); dev_free(h->d_ctr); dev_free(h->d_partial);
-    h->free_near_work();
-    if (h->h_ctr) (void)hipHostFree(h->h_ctr);
-    for (auto& e : h->ev)
-        if (e) (void)hipEventDestroy(e);
+    h->free_work();
+    dev_free(h->w.ctr);
+    for (auto& r : h->rec) {
+        if (r.h_ctr) (void)hipHostFree(r.h_ctr);
+        if (r.h_list) (void)hipHostFree(r.h_list);
+        for (hipEvent_t e : { r.ev_list, r.ev_far0, r.ev_far1, r.ev_near1, r.ev_done })
+            if (e) (void)hipEventDestroy(e);
+    }
     delete h;
     return ok();
 }
@@ -477,7 +625,9 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
 {
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
     if (h->server) return fail(BEMC_E_INVALID_ARG, "rules cannot change while serving");
-    if (!(near_dr > 0.0) || !std::isfinite(near_dr)) return fail(BEMC_E_INVALID_ARG, "near_dr must be > 0");
+    // the far-field sums expand r^2 about the element's centroid, whose rounding is bounded
+    // for DR >= 2 (in FP32 by about 9 ulp of r^2)
+    if (!(near_dr >= 2.0) || !std::isfinite(near_dr)) return fail(BEMC_E_INVALID_ARG, "near_dr must be >= 2");
     if (max_depth < 0 || max_depth > 30) return fail(BEMC_E_INVALID_ARG, "max_depth must be in 0..30");
     std::vector<TriNode> t;
     if (!triangle_rule(tri_rule, t)) return fail(BEMC_E_INVALID_ARG, "unknown triangle rule %d", tri_rule);
@@ -502,6 +652,7 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
         std::vector<double> thr(h->h_L.size());
         for (size_t i = 0; i < thr.size(); ++i) thr[i] = (near_dr * h->h_L[i]) * (near_dr * h->h_L[i]);
         HIP_TRY(hipSetDevice(h->device));
+        if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
         HIP_TRY(hipMemcpy(h->d_thr2, thr.data(), thr.size() * 8, hipMemcpyHostToDevice));
     }
     return ok();
@@ -600,6 +751,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     }
 
     HIP_TRY(hipSetDevice(h->device));
+    if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
     HIP_TRY(hipStreamSynchronize(s));
     free_elements(h);
     h->n_tri = n_tri;
@@ -640,6 +792,7 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
         for (size_t i = 0; i < cnt; ++i)
             if (!std::isfinite(sigma[i])) return fail(BEMC_E_NONFINITE, "sigma[%zu] is not finite", i);
     HIP_TRY(hipSetDevice(h->device));
+    if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
     HIP_TRY(hipStreamSynchronize(s));
     dev_free(h->d_q);
     h->n_rhs = 0;
@@ -669,7 +822,7 @@ int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rh
     if (!pts || !phi) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
     if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
     if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
-    return h->run(kNearEval, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream));
+    return h->run(kNearEval, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream), h->w, false);
 }
 
 int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precision, int rhs, double* G, void* stream)
@@ -682,7 +835,8 @@ int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precisio
     if (!pts || !G) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
     if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
     if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
-    return h->run(kNearGrad, pts, n, precision, rhs, 1, G, nullptr, reinterpret_cast<hipStream_t>(stream));
+    return h->run(kNearGrad, pts, n, precision, rhs, 1, G, nullptr, reinterpret_cast<hipStream_t>(stream), h->w,
+                  false);
 }
 
 int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision, double* out, void* stream)
@@ -696,13 +850,15 @@ int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int p
     if (h->ne == 0) return ok();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(h->device));
-    // charges q = sigma * area of these densities, kept apart from the evaluation densities
+    // charges q = sigma * area of these densities, kept apart from the evaluation densities;
+    // the buffer is shared by the calls on the context, so this one waits for the last
     if (!h->d_qc && dev_alloc(&h->d_qc, (size_t)kMaxRhs * (size_t)h->ne) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BEMC_E_OUT_OF_MEMORY, "collocation charges");
     }
+    if (h->rec_last >= 0 && h->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, h->rec[h->rec_last].ev_done, 0));
     HIP_TRY(launch_charges(sigma, h->d_area, h->d_qc, h->ne, n_rhs, s));
-    return h->run(kNearColloc, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s);
+    return h->run(kNearColloc, nullptr, h->ne, precision, 0, n_rhs, out, nullptr, s, h->w, false);
 }
 
 int bemc_solve_densities(bemc_handle h, const double* potential, double* sigma, double tol, int max_iter,
@@ -751,26 +907,38 @@ int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const dou
     return ok();
 }
 
-int bemc_set_near_capacity(bemc_handle h, int64_t pairs)
+int bemc_set_near_capacity(bemc_handle h, int64_t pairs, int grow)
 {
     if (!h || pairs < 1) return fail(BEMC_E_INVALID_ARG, "invalid capacity");
     if ((unsigned long long)pairs > kMaxNearPairs) return fail(BEMC_E_LIMIT, "capacity above 2^32 - 1 pairs");
     HIP_TRY(hipSetDevice(h->device));
-    HIP_TRY(hipDeviceSynchronize());
-    dev_free(h->d_near);
-    h->near_cap = 0;
-    if (dev_alloc(&h->d_near, (size_t)pairs) != hipSuccess) {
+    if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    dev_free(h->w.near);
+    h->w.near_cap = 0;
+    if (dev_alloc(&h->w.near, (size_t)pairs) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BEMC_E_OUT_OF_MEMORY, "near-pair list of %lld entries", (long long)pairs);
     }
-    h->near_cap = (unsigned long long)pairs;
+    h->w.near_cap = (unsigned long long)pairs;
+    h->near_grow = grow != 0;
     return ok();
 }
 
 int bemc_query_stats(bemc_handle h, bemc_stats* out)
 {
     if (!h || !out) return fail(BEMC_E_INVALID_ARG, "null argument");
+    (void)hipSetDevice(h->device);
+    (void)h->drain();
     *out = h->last;
+    if (h->sticky) {
+        const int rc = h->sticky;
+        h->sticky = BEMC_OK;
+        return fail(rc, "%s", h->sticky_msg.c_str());
+    }
+    if (h->last_status == BEMC_W_ON_SURFACE) {
+        g_last_error = "some field points of the last evaluation lie on an element";
+        return BEMC_W_ON_SURFACE;
+    }
     return ok();
 }
 
@@ -780,6 +948,8 @@ int bemc_server_start(bemc_handle h, const bemc_server_config* cfg)
     if (!h || !cfg) return fail(BEMC_E_INVALID_ARG, "null argument");
     if (!h->have_geometry || h->n_rhs == 0) return fail(BEMC_E_NO_GEOMETRY, "geometry and densities must be uploaded");
     if (h->server) return fail(BEMC_E_INVALID_ARG, "server already running");
+    HIP_TRY(hipSetDevice(h->device));
+    if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
     ServerEnv env{};
     env.device = h->device;
     env.el = h->elements();

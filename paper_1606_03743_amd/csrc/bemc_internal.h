@@ -84,6 +84,7 @@ struct DevCounters {
     unsigned long long max_depth;
     unsigned long long visit_limit_hits;
     unsigned long long node_ints;  // point-charge terms summed (rule choice by distance ratio)
+    unsigned long long node_ints_pair;  // the terms each far pair's own level would sum
 };
 
 // Arguments of the far-field kernels.
@@ -123,8 +124,8 @@ struct NearArgs {
     const NearPair* near_list;   // as the far kernel appended it
     unsigned long long near_cap;
     const uint32_t* slot;        // result slot of each list entry
-    double* res;                 // per-pair results [rows][res_stride] (rows 4, 6 or 1)
-    unsigned long long res_stride;
+    double* res;                 // per-pair result records at the pairs' slots: [slot][4] field,
+                                 // [slot][6] gradient, [slot] collocation
     DevCounters* ctr;
     double near_dr2;    // near_dr^2
     int max_depth;
@@ -143,6 +144,10 @@ hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, do
 hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows, int64_t n, double K, double* out,
                                 hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
+hipError_t launch_reset_near_count(DevCounters* c, hipStream_t s);  // near_count = 0 only
+// near-pair list: every pair with D^2 < (near_dr L)^2 of the n points pts[3][n]
+hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, NearPair* list, unsigned long long cap,
+                            DevCounters* ctr, hipStream_t s);
 
 hipError_t launch_self_diag(const Elements& el, double K, double* diag, hipStream_t s);
 hipError_t launch_multi_dot(const double* V, int k, int64_t n, const double* w, double* partial, int blocks, hipStream_t s);
@@ -168,7 +173,7 @@ struct NearWork {
     uint32_t* origin;                  // [capacity] list index of each grouped pair
     NearPair* sorted;                  // [capacity] pairs in (point, element) order
     uint32_t* slot;                    // [capacity] result slot (sorted position) of each list index
-    double* res;                       // [rows][capacity] per-pair results of the near kernel
+    double* res;                       // [capacity][rows] per-pair result records of the near kernel
     void* temp;                        // scan workspace
     size_t temp_bytes;
 };
@@ -178,8 +183,8 @@ void near_work_free(NearWork& w);
 // regroup the list (length read from ctr) into per-point segments sorted by element
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
                       const NearWork& w, hipStream_t s);
-// add each point's segment of per-pair results (row stride `stride`) to its outputs
-hipError_t near_reduce(const NearWork& w, int64_t n, unsigned long long stride, int mode, double* phi, double* E,
+// add each point's segment of per-pair result records to its outputs
+hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
                        double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
 constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 

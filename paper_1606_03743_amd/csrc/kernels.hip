@@ -76,36 +76,197 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
     }
 }
 
+// ------------------------------------------------------------- near-pair list -----
+// Every (point, element) pair with D^2 < (near_dr L)^2 (the distance-ratio switch, Sec. 2)
+// goes into the near-pair list, compacted per wavefront; pairs past the capacity are
+// counted, not stored.  A workgroup takes kListPoints consecutive points (Morton order:
+// neighbours in space) and bounds them by a box; an element takes the per-point test only
+// when its centroid lies within near_dr L of that box.  Collocation: the points are the
+// centroids themselves (the same [3][n] layout).
+constexpr int kListPPT = 2;
+constexpr int kListPoints = kBlock * kListPPT;
+
+__global__ __launch_bounds__(kBlock) void near_list_kernel(const double* __restrict__ pts, int64_t n, Elements el,
+                                                           NearPair* __restrict__ list, unsigned long long cap,
+                                                           DevCounters* __restrict__ ctr)
+{
+    __shared__ double wbox[kBlock / 64][6];
+    __shared__ double box[6];
+    __shared__ uint32_t cand[kBlock];
+    __shared__ int ncand;
+    const int64_t ne = el.ne;
+    double x[kListPPT], y[kListPPT], z[kListPPT];
+    bool valid[kListPPT];
+    uint32_t idx[kListPPT];
+    double lo[3] = { INFINITY, INFINITY, INFINITY }, hi[3] = { -INFINITY, -INFINITY, -INFINITY };
+#pragma unroll
+    for (int k = 0; k < kListPPT; ++k) {
+        const int64_t p = (int64_t)blockIdx.x * kListPoints + (int64_t)k * kBlock + threadIdx.x;
+        valid[k] = p < n;
+        idx[k] = (uint32_t)p;
+        x[k] = valid[k] ? pts[p] : 0.0;
+        y[k] = valid[k] ? pts[n + p] : 0.0;
+        z[k] = valid[k] ? pts[2 * n + p] : 0.0;
+        if (valid[k]) {
+            lo[0] = fmin(lo[0], x[k]); lo[1] = fmin(lo[1], y[k]); lo[2] = fmin(lo[2], z[k]);
+            hi[0] = fmax(hi[0], x[k]); hi[1] = fmax(hi[1], y[k]); hi[2] = fmax(hi[2], z[k]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[c] = fmin(lo[c], __shfl_xor(lo[c], o));
+            hi[c] = fmax(hi[c], __shfl_xor(hi[c], o));
+        }
+    const int wave = threadIdx.x / 64;
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { wbox[wave][c] = lo[c]; wbox[wave][3 + c] = hi[c]; }
+    }
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = wbox[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) v = threadIdx.x < 3 ? fmin(v, wbox[w][threadIdx.x]) : fmax(v, wbox[w][threadIdx.x]);
+        box[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const double b0 = box[0], b1 = box[1], b2 = box[2], b3 = box[3], b4 = box[4], b5 = box[5];
+    for (int64_t c0 = 0; c0 < ne; c0 += kBlock) {
+        const int64_t e = c0 + threadIdx.x;
+        bool hit = false;
+        if (e < ne) {
+            const double cx = el.cen[e], cy = el.cen[ne + e], cz = el.cen[2 * ne + e];
+            const double dx = fmax(fmax(b0 - cx, cx - b3), 0.0);
+            const double dy = fmax(fmax(b1 - cy, cy - b4), 0.0);
+            const double dz = fmax(fmax(b2 - cz, cz - b5), 0.0);
+            hit = fma(dx, dx, fma(dy, dy, dz * dz)) < el.thr2[e];
+        }
+        const unsigned long long m = __ballot(hit);
+        if (m) {
+            int base = 0;
+            if (lane_id() == 0) base = atomicAdd(&ncand, __popcll(m));
+            base = __shfl(base, 0);
+            if (hit) cand[base + (int)lanes_below(m)] = (uint32_t)e;
+        }
+        __syncthreads();
+        const int nc = ncand;
+        for (int i = 0; i < nc; ++i) {
+            const uint32_t ce = cand[i];
+            const double cx = el.cen[ce], cy = el.cen[ne + ce], cz = el.cen[2 * ne + ce], t2 = el.thr2[ce];
+#pragma unroll
+            for (int k = 0; k < kListPPT; ++k) {
+                const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
+                const bool nr = valid[k] && fma(dx, dx, fma(dy, dy, dz * dz)) < t2;
+                record_near(nr, idx[k], ce, list, cap, ctr);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) ncand = 0;
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- LDS staging ------
 // Each element is summed in its own orthonormal frame: origin at the centroid, f1 and f2
-// in its plane, f3 its unit normal.  A Gaussian point has in-plane coordinates (a, b) and
-// a field point the coordinates (p1, p2, p3), so
-//   r^2 = (p1 - a)^2 + (p2 - b)^2 + p3^2 = |p|^2 + (a^2 + b^2) - 2 (p1 a + p2 b):
-// with a^2 + b^2 staged per node and |p|^2 = D^2 from the distance test, r^2 takes one addition and
-// two FMAs per node (for DR >= 3 the expansion adds about a tenth of an ulp to the rounding
-// of 1/r; the gradient keeps the two differences).  The sums are rotated back to the global axes once per pair.  For rectangles f1
-// runs along the second side, so the nodes of a tensor Gauss-Legendre rule that share their
-// first coordinate share b; for the 7 x 7 rule (p2 - b)^2 + p3^2 is formed once per group of
-// seven and r^2 takes one difference and one FMA per node.
+// in its plane, f3 its unit normal.  A Gaussian point has in-plane coordinates (a, b).
+//
+// Expanded form (triangles, Table B rectangles, the short distance-ratio levels): with
+// d = P - centroid, |p|^2 = D^2 from the distance test and q1 = -2 f1.d, q2 = -2 f2.d,
+//   r^2 = D^2 + (a^2 + b^2) + q1 a + q2 b,
+// and the field follows from the node sums S3 = sum w/r^3, S1 = sum w a/r^3, S2 = sum w b/r^3
+// as E = q (S3 d - f1 S1 - f2 S2), rotated once per pair.  When every weight is positive,
+// the nodes are staged divided by w^2, (a, b, a^2 + b^2, 1) / w^2: the reciprocal square
+// root of r^2 / w^2 is w/r itself, and (w/r)^3 times the staged values gives the three
+// field sums, which saves the multiplication by the weight per node.
+//
+// Rows form (the 7 x 7 Gauss-Legendre rectangle rule, and the gradient): the point is
+// rotated into the frame, p = (f1.d, f2.d, f3.d).  For rectangles f1 runs along the second
+// side, so the nodes of a tensor Gauss-Legendre rule that share their first coordinate share
+// b: (p2 - b)^2 + p3^2 is formed once per group of seven and r^2 takes one difference and
+// one FMA per node.  The local field (sum w (p1 - a)/r^3, sum w (p2 - b)/r^3, p3 sum w/r^3)
+// is rotated back with the frame.
+enum FrameForm { kFrExp = 0, kFrRows = 1 };
+
 template <bool MIXED, int NRHS>
 struct TileLds {
     using T = typename std::conditional<MIXED, float, double>::type;
     using T4 = typename std::conditional<MIXED, float4, double4>::type;
-    T4 nd[kTileNodes];  // a, b, a^2 + b^2, weight (unit element charge)
+    T4 nd[kTileNodes];  // (a, b, a^2 + b^2, w), or divided by w^2 as (a, b, a^2 + b^2, 1) / w^2
     double cx[kMaxTileElems], cy[kMaxTileElems], cz[kMaxTileElems], thr2[kMaxTileElems];
-    T f[9][kMaxTileElems];  // f1, f2, f3 (x, y, z each), in the precision of the node sums
+    T fr[9][kMaxTileElems];      // point rotation: expanded -2 f1, -2 f2; rows f1, f2, f3
+    double qr[9][kMaxTileElems]; // rotation back scaled by the charge: expanded -q f1, -q f2;
+                                 // rows q f1, q f2, q f3
     double q[NRHS][kMaxTileElems];
+    T lc[6][kMaxTileElems];      // triangles: in-plane coordinates of A, B, C relative to the centroid
 };
+
+// Orbit structure of the compiled triangle rules (Tables A2-A5 as expanded on the host:
+// the centroid first, then the S21 orbits with the distinct coordinate at A, B, C in turn,
+// then the other orbits in groups of gs nodes).  A node of an S21 orbit lies on the line
+// from the centroid to its vertex, at n = (l_k - l_other) u_k with u_k the vertex relative
+// to the centroid, so d.n = s d.u_k needs one product per node once d.u_k is known per pair.
+template <int NN> struct TriOrbits { static constexpr int nc = 0, n21 = 0, gs = 4; };
+template <> struct TriOrbits<7> { static constexpr int nc = 1, n21 = 2, gs = 1; };    // Table A2
+template <> struct TriOrbits<12> { static constexpr int nc = 0, n21 = 0, gs = 3; };   // Table A3 (cyclic)
+template <> struct TriOrbits<19> { static constexpr int nc = 1, n21 = 4, gs = 6; };   // Table A4
+template <> struct TriOrbits<33> { static constexpr int nc = 0, n21 = 5, gs = 6; };   // Table A5
+
+// Staging form of the triangle nodes: levels back to back (one for a fixed rule), each with
+// nc centroid nodes and n21 S21 nodes (three per orbit) in front.
+struct TriForms {
+    int nlev;
+    int off[5];
+    int nc[4], n21[4];
+};
+
+template <int NN, bool ORBITS>
+__device__ __forceinline__ TriForms fixed_forms(int nn)
+{
+    TriForms t{ 1, { 0, nn, nn, nn, nn }, { 0, 0, 0, 0 }, { 0, 0, 0, 0 } };
+    if (ORBITS) {
+        t.nc[0] = TriOrbits<NN>::nc;
+        t.n21[0] = 3 * TriOrbits<NN>::n21;
+    }
+    return t;
+}
+
+// Pair rows of the 7 x 7 Gauss-Legendre rectangle rule (node i*7 + j at natural coordinates
+// (x_i, x_j)): the row of x_i has b = x_i beta and the nodes a = a0 + x_j alpha, a0 = x_i gamma,
+// with x_{6-j} = -x_j, the same weight for j and 6 - j and x_3 = 0.  Four slots per row:
+//   header (b, a0, w of the middle node, a0^2 + b^2), then per pair j = 0, 1, 2 with
+//   s = x_{6-j} alpha: (s, s^2, w, w s).
+constexpr int kPairRowSlots = 28;
+__device__ __forceinline__ double4 pair_row_slot(const RuleTables& R, int prow, int m, double gamma, double beta,
+                                                 double alpha)
+{
+    const int r = m >> 2, c = m & 3;
+    if (c == 0) {
+        const int i = prow + r * 7 + 3;
+        const double x = R.rect[4 * i];
+        const double b = x * beta, a0 = x * gamma;
+        return make_double4(b, a0, R.rect[4 * i + 2], fma(a0, a0, b * b));
+    }
+    const int i = prow + r * 7 + 7 - c;  // j = 6 - (c - 1)
+    const double sv = R.rect[4 * i + 1] * alpha, w = R.rect[4 * i + 2];
+    return make_double4(sv, sv * sv, w, w * sv);
+}
 
 // Gaussian points of elements [t0, t0 + te) in their frames (Eq. 3.2 / 3.3): triangle
 // (a, b) = la A' + lb B' + lc C' from the in-plane coordinates of the vertices relative to
 // the centroid; rectangle a = x gamma + y alpha, b = x beta for the rule point (x, y) in
 // [-1, 1]^2 (alpha = |e2| / 2; beta, gamma the components of e1 / 2 across and along e2).
-// FP32 tiles hold the FP64 values rounded once; the mixed path also rotates in FP32.
-template <bool TRI, bool MIXED, int NRHS>
+// FP32 tiles hold the FP64 values rounded once.  QR: stage the rotation back (field only).
+// The first nfold nodes of each element are staged divided by w^2 (positive weights only).
+// Nodes from prow on are a 7 x 7 Gauss-Legendre rule staged as pair rows (pair_row_slot).
+// Triangles: centroid and S21 nodes (TriForms, folded nodes only) are staged as
+// (0, 0, 1/w^2, 0) and (s, |n|^2, 1, 0) / w^2 with n = s u_k.
+template <bool TRI, bool MIXED, int NRHS, int FR, bool QR>
 __device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elements& el, const RuleTables& R, int nn,
-                                           int64_t t0, int te, int rhs0, int nrhs)
+                                           int64_t t0, int te, int rhs0, int nrhs, int nfold, int prow,
+                                           const TriForms& tf)
 {
+    using T = typename TileLds<MIXED, NRHS>::T;
     const int64_t ne = el.ne;
     for (int k = threadIdx.x; k < te; k += kBlock) {
         const int64_t e = t0 + k;
@@ -113,18 +274,61 @@ __device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elemen
         s.cy[k] = el.cen[ne + e];
         s.cz[k] = el.cen[2 * ne + e];
         s.thr2[k] = el.thr2[e];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) s.f[c][k] = (typename TileLds<MIXED, NRHS>::T)el.frame[(int64_t)c * ne + e];
         for (int r = 0; r < nrhs; ++r) s.q[r][k] = el.q[(int64_t)(rhs0 + r) * ne + e];
+        const double q = QR ? el.q[(int64_t)rhs0 * ne + e] : 0.0;
+        if constexpr (FR == kFrExp) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double f = el.frame[(int64_t)c * ne + e];
+                s.fr[c][k] = (T)(-2.0 * f);
+                if (QR) s.qr[c][k] = -q * f;
+                if (TRI) s.lc[c][k] = (T)el.loc[(int64_t)c * ne + e];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const double f = el.frame[(int64_t)c * ne + e];
+                s.fr[c][k] = (T)f;
+                if (QR) s.qr[c][k] = q * f;
+            }
+        }
     }
     for (int k = threadIdx.x; k < te * nn; k += kBlock) {
         const int j = k / nn;
         const int i = k - j * nn;
         const int64_t e = t0 + j;
+        if (!TRI && i >= prow) {
+            if (i - prow < kPairRowSlots) {
+                const double4 v = pair_row_slot(R, prow, i - prow, el.loc[e], el.loc[ne + e], el.loc[2 * ne + e]);
+                if constexpr (MIXED) s.nd[k] = make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+                else s.nd[k] = v;
+            }
+            continue;
+        }
         double a, b, w;
         if (TRI) {
             const double la = R.tri[4 * i], lb = R.tri[4 * i + 1], lc = R.tri[4 * i + 2];
             w = R.tri[4 * i + 3];
+            if (i < nfold) {
+                int l = 0;
+                while (l + 1 < tf.nlev && i >= tf.off[l + 1]) ++l;
+                const int il = i - tf.off[l];
+                if (il < tf.nc[l] + tf.n21[l]) {
+                    const double iw2 = 1.0 / (w * w);
+                    double v0 = 0.0, v1 = 0.0;
+                    if (il >= tf.nc[l]) {  // S21: the distinct coordinate at vertex kk
+                        const int kk = (il - tf.nc[l]) % 3;
+                        const double lam[3] = { la, lb, lc };
+                        const double sv = lam[kk] - lam[(kk + 1) % 3];
+                        const double na = sv * el.loc[(int64_t)(2 * kk) * ne + e], nb = sv * el.loc[(int64_t)(2 * kk + 1) * ne + e];
+                        v0 = sv * iw2;
+                        v1 = fma(na, na, nb * nb) * iw2;
+                    }
+                    if constexpr (MIXED) s.nd[k] = make_float4((float)v0, (float)v1, (float)iw2, 0.0f);
+                    else s.nd[k] = make_double4(v0, v1, iw2, 0.0);
+                    continue;
+                }
+            }
             a = la * el.loc[e] + lb * el.loc[2 * ne + e] + lc * el.loc[4 * ne + e];
             b = la * el.loc[ne + e] + lb * el.loc[3 * ne + e] + lc * el.loc[5 * ne + e];
         } else {
@@ -133,7 +337,14 @@ __device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elemen
             a = x * el.loc[e] + y * el.loc[2 * ne + e];
             b = x * el.loc[ne + e];
         }
-        const double g = fma(a, a, b * b);
+        double g = fma(a, a, b * b);
+        if (i < nfold) {
+            const double iw2 = 1.0 / (w * w);
+            a *= iw2;
+            b *= iw2;
+            g *= iw2;
+            w = iw2;
+        }
         if constexpr (MIXED) s.nd[k] = make_float4((float)a, (float)b, (float)g, (float)w);
         else s.nd[k] = make_double4(a, b, g, w);
     }
@@ -160,26 +371,29 @@ struct PointSet {
     double acc[Sums<MODE>::kOut][PPT];
 };
 
-// Offsets of the lane's points from the element in hand, in its frame.
+// The lane's points relative to the element in hand.
 template <int PPT, typename T>
 struct Local {
-    T p1[PPT], p2[PPT], p3[PPT], h[PPT];  // h = p3^2
-    T q1[PPT], q2[PPT], H[PPT];           // -2 p1, -2 p2, |p|^2 (expanded r^2 only)
+    T q1[PPT], q2[PPT], H[PPT];           // expanded: -2 f1.d, -2 f2.d, D^2
+    T p1[PPT], p2[PPT], p3[PPT], h[PPT];  // rows: f1.d, f2.d, f3.d, p3^2
+    double dx[PPT], dy[PPT], dz[PPT];     // d = P - centroid (FP64)
 };
 
-// Runs term(i) for the nodes i = 0 .. n-1 of one element.  Long rules (and run-time
-// counts) go in groups of four with a separate remainder: this keeps the accumulators in
-// place, where an unrolled loop with a remainder makes the compiler copy them every
-// iteration.  The short rules of the distance-ratio levels use a plain unrolled loop.
+// Runs term(i) for the nodes i = 1 .. n-1 of one element (node 0 is peeled off by the
+// caller, so that the sums start from its terms instead of from zero).  Long rules (and
+// run-time counts) go in groups of four with a separate remainder: this keeps the
+// accumulators in place, where an unrolled loop with a remainder makes the compiler copy
+// them every iteration.  The short rules of the distance-ratio levels use a plain
+// unrolled loop.
 template <int NN, typename Term>
 __device__ __forceinline__ void for_nodes(int n, Term term)
 {
     if (NN > 0 && NN < 32) {
 #pragma unroll 4
-        for (int i = 0; i < n; ++i) term(i);
+        for (int i = 1; i < n; ++i) term(i);
         return;
     }
-    int i = 0;
+    int i = 1;
 #pragma unroll 1
     for (; i + 4 <= n; i += 4) {
 #pragma unroll
@@ -188,251 +402,380 @@ __device__ __forceinline__ void for_nodes(int n, Term term)
     for (; i < n; ++i) term(i);
 }
 
-// Element sums in the frame, per field point (unit element charge).  EXP: r^2 expanded;
-// otherwise from the differences da = p1 - a, db = p2 - b (the gradient).
-//   kFarField  (sum w/r, sum w a/r^3, sum w b/r^3, sum w/r^3) expanded, the field's in-plane
-//              parts following as p1 sum w/r^3 - sum w a/r^3 and likewise for b;
-//              (sum w/r, sum w da/r^3, sum w db/r^3, sum w/r^3) from differences;
-//   kFarGrad   FP64: (sum w/r^3, sum w/r^5, sum w da/r^5, sum w db/r^5, sum w da^2/r^5,
-//              sum w db^2/r^5, sum w da db/r^5), turned into the local tensor after the loop;
-//              FP32: the local tensor itself, sum w/r^3 and sum w u_i u_j / r^3 over the unit
-//              offset u = (da, db, p3)/r (xx, yy, zz, xy, xz, yz), so that no power of 1/r
-//              above the third is formed in single precision;
-//   kFarPhi    sum w/r.
-template <int PPT, int MODE, bool EXP>
-__device__ __forceinline__ void node_term64(const double4 Q, const Local<PPT, double>& L,
-                                            double (&o)[Sums<MODE>::kNode][PPT])
+// 1/sqrt(x) in the precision of T (FP64 refined, see rsqrt64)
+__device__ __forceinline__ double rsqrtT(double x) { return rsqrt64(x); }
+__device__ __forceinline__ float rsqrtT(float x) { return rsqrt32(x); }
+
+// Node sums of one element per field point (unit element charge, Eq. 4.1), accumulated into
+// o, whose sums start at -0.0 (so that adding the first node folds into an assignment).
+//   kFarField, expanded: (sum w/r, sum w a/r^3, sum w b/r^3, sum w/r^3);
+//              FOLD: the staged node is (a, b, g, 1) / w^2 and rsqrt(r^2 / w^2) = w/r;
+//   kFarPhi,   expanded: sum w/r; FOLD in FP64: the potential of the node is y (1 + e/2 +
+//              3 e^2 / 8) with y the hardware estimate of w/r and e = 1 - (r^2/w^2) y^2,
+//              formed as one FMA of y with the factor (the same third-order step as rsqrt64);
+//   kFarGrad   (differences da = p1 - a, db = p2 - b): FP64 (sum w/r^3, sum w/r^5,
+//              sum w da/r^5, sum w db/r^5, sum w da^2/r^5, sum w db^2/r^5, sum w da db/r^5),
+//              turned into the local tensor after the loop; FP32: the local tensor itself,
+//              sum w/r^3 and sum w u_i u_j / r^3 over the unit offset u = (da, db, p3)/r (xx,
+//              yy, zz, xy, xz, yz), so that no power of 1/r above the third is formed in
+//              single precision.
+template <int PPT, int MODE, bool FOLD, typename T, typename T4>
+__device__ __forceinline__ void node_term(const T4 Q, const Local<PPT, T>& L, T (&o)[Sums<MODE>::kNode][PPT])
 {
-    const double a = Q.x, b = Q.y, g = Q.z, w = Q.w;
+    constexpr bool F64 = std::is_same<T, double>::value;
+    const T a = Q.x, b = Q.y, g = Q.z, w = Q.w;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if constexpr (MODE != kFarGrad) {
-            double ri, ca, cb;  // ca, cb: a, b (expanded) or da, db
-            if constexpr (EXP) {
-                ri = rsqrt64(fma(L.q1[k], a, fma(L.q2[k], b, L.H[k] + g)));
-                ca = a;
-                cb = b;
+        if constexpr (MODE == kFarGrad) {
+            const T da = L.p1[k] - a, db = L.p2[k] - b;
+            const T ri = rsqrtT(fma(da, da, fma(db, db, L.h[k])));
+            if constexpr (F64) {
+                const T ri2 = ri * ri;
+                const T w3 = (w * ri) * ri2;
+                const T w5 = w3 * ri2;
+                const T ua = w5 * da, ub = w5 * db;
+                o[0][k] += w3;
+                o[1][k] += w5;
+                o[2][k] += ua;
+                o[3][k] += ub;
+                o[4][k] = fma(ua, da, o[4][k]);
+                o[5][k] = fma(ub, db, o[5][k]);
+                o[6][k] = fma(ua, db, o[6][k]);
             } else {
-                ca = L.p1[k] - a;
-                cb = L.p2[k] - b;
-                ri = rsqrt64(fma(ca, ca, fma(cb, cb, L.h[k])));
+                const T w3 = (w * ri) * (ri * ri);
+                const T va = da * ri, vb = db * ri, vc = L.p3[k] * ri;
+                const T ua = w3 * va, ub = w3 * vb, uc = w3 * vc;
+                o[0][k] += w3;
+                o[1][k] = fma(ua, va, o[1][k]);
+                o[2][k] = fma(ub, vb, o[2][k]);
+                o[3][k] = fma(uc, vc, o[3][k]);
+                o[4][k] = fma(ua, vb, o[4][k]);
+                o[5][k] = fma(ua, vc, o[5][k]);
+                o[6][k] = fma(ub, vc, o[6][k]);
             }
+        } else if constexpr (FOLD) {
+            const T x = fma(L.q1[k], a, fma(L.q2[k], b, fma(L.H[k], w, g)));  // r^2 / w^2
+            if constexpr (MODE == kFarPhi) {
+                if constexpr (F64) {
+                    const double y = __builtin_amdgcn_rsq(x);
+                    const double e = fma(-(x * y), y, 1.0);
+                    o[0][k] = fma(y, fma(e, fma(e, 0.375, 0.5), 1.0), o[0][k]);
+                } else {
+                    o[0][k] += rsqrtT(x);
+                }
+            } else {
+                const T wr = rsqrtT(x);  // w / r
+                const T wr3 = (wr * wr) * wr;
+                o[0][k] += wr;
+                o[1][k] = fma(wr3, a, o[1][k]);
+                o[2][k] = fma(wr3, b, o[2][k]);
+                o[3][k] = fma(wr3, w, o[3][k]);
+            }
+        } else {
+            const T ri = rsqrtT(fma(L.q1[k], a, fma(L.q2[k], b, L.H[k] + g)));
             if constexpr (MODE == kFarPhi) {
                 o[0][k] = fma(w, ri, o[0][k]);
             } else {
-                const double wr = w * ri;
-                const double w3 = wr * (ri * ri);
+                const T wr = w * ri;
+                const T w3 = wr * (ri * ri);
                 o[0][k] += wr;
-                o[1][k] = fma(w3, ca, o[1][k]);
-                o[2][k] = fma(w3, cb, o[2][k]);
+                o[1][k] = fma(w3, a, o[1][k]);
+                o[2][k] = fma(w3, b, o[2][k]);
                 o[3][k] += w3;
             }
-        } else {
-            const double da = L.p1[k] - a, db = L.p2[k] - b;
-            const double ri = rsqrt64(fma(da, da, fma(db, db, L.h[k])));
-            const double ri2 = ri * ri;
-            const double w3 = (w * ri) * ri2;
-            const double w5 = w3 * ri2;
-            const double ua = w5 * da, ub = w5 * db;
-            o[0][k] += w3;
-            o[1][k] += w5;
-            o[2][k] += ua;
-            o[3][k] += ub;
-            o[4][k] = fma(ua, da, o[4][k]);
-            o[5][k] = fma(ub, db, o[5][k]);
-            o[6][k] = fma(ua, db, o[6][k]);
         }
     }
 }
 
-template <int PPT, int MODE, bool EXP>
-__device__ __forceinline__ void node_term32(const float4 Q, const Local<PPT, float>& L,
-                                            float (&o)[Sums<MODE>::kNode][PPT])
+// Tensor rule in G groups of G nodes with the same b: per group the lane forms db and
+// (p2 - b)^2 + p3^2 once; per node one difference remains.  Field: the b-component and
+// sum w/r^3 are gathered per group.  Gradient (the FP64 sums of node_term): sum w/r^5 and
+// sum w da/r^5 are gathered per group, and the sums with db follow from them.  The sums
+// in o start at -0.0.
+template <int G, int PPT, int MODE, typename T, typename T4>
+__device__ __forceinline__ void group_body(const T4* t, int n0, const Local<PPT, T>& L, T (&o)[Sums<MODE>::kNode][PPT])
 {
-    const float a = Q.x, b = Q.y, g = Q.z, w = Q.w;
+    const T b = t[n0].y;
+    T db[PPT], B[PPT], sg[PPT], xg[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if constexpr (MODE != kFarGrad) {
-            float ri, ca, cb;
-            if constexpr (EXP) {
-                ri = rsqrt32(fmaf(L.q1[k], a, fmaf(L.q2[k], b, L.H[k] + g)));
-                ca = a;
-                cb = b;
-            } else {
-                ca = L.p1[k] - a;
-                cb = L.p2[k] - b;
-                ri = rsqrt32(fmaf(ca, ca, fmaf(cb, cb, L.h[k])));
-            }
+        db[k] = L.p2[k] - b;
+        B[k] = fma(db[k], db[k], L.h[k]);
+        sg[k] = T(-0.0);
+        xg[k] = T(-0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const T a = t[n0 + i].x, w = t[n0 + i].w;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const T da = L.p1[k] - a;
+            const T ri = rsqrtT(fma(da, da, B[k]));
             if constexpr (MODE == kFarPhi) {
-                o[0][k] = fmaf(w, ri, o[0][k]);
-            } else {
-                const float wr = w * ri;
-                const float w3 = wr * (ri * ri);
+                o[0][k] = fma(w, ri, o[0][k]);
+            } else if constexpr (MODE == kFarField) {
+                const T wr = w * ri;
+                const T w3 = wr * (ri * ri);
                 o[0][k] += wr;
-                o[1][k] = fmaf(w3, ca, o[1][k]);
-                o[2][k] = fmaf(w3, cb, o[2][k]);
-                o[3][k] += w3;
+                o[1][k] = fma(w3, da, o[1][k]);
+                sg[k] += w3;
+            } else {
+                const T ri2 = ri * ri;
+                const T w3 = (w * ri) * ri2;
+                const T w5 = w3 * ri2;
+                const T ua = w5 * da;
+                o[0][k] += w3;
+                sg[k] += w5;
+                xg[k] += ua;
+                o[4][k] = fma(ua, da, o[4][k]);
+            }
+        }
+    }
+    if constexpr (MODE == kFarField) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            o[2][k] = fma(sg[k], db[k], o[2][k]);
+            o[3][k] += sg[k];
+        }
+    } else if constexpr (MODE == kFarGrad) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const T u = sg[k] * db[k];  // sum w db / r^5 of the group
+            o[1][k] += sg[k];
+            o[2][k] += xg[k];
+            o[3][k] += u;
+            o[5][k] = fma(u, db[k], o[5][k]);
+            o[6][k] = fma(xg[k], db[k], o[6][k]);
+        }
+    }
+}
+
+template <int G, int PPT, int MODE, typename T, typename T4>
+__device__ __forceinline__ void group_sum(const T4* t, int base, const Local<PPT, T>& L, T (&o)[Sums<MODE>::kNode][PPT])
+{
+    static_assert(!(MODE == kFarGrad && std::is_same<T, float>::value), "the FP32 gradient takes the node form");
+    group_body<G, PPT, MODE>(t, base, L, o);  // the first group starts the sums
+#pragma unroll 1
+    for (int g = 1; g < G; ++g) group_body<G, PPT, MODE>(t, base + g * G, L, o);
+}
+
+// One pair row of the 7 x 7 rule (slots n0 .. n0 + 3, see pair_row_slot) for potential and
+// field, or the potential alone.  With da0 = p1 - a0 and C = |d - (a0 f1 + b f2)|^2, formed
+// like the expanded form from D^2 (C = D^2 + a0^2 + b^2 - 2 (p1 a0 + p2 b): the rotation's
+// rounding then enters only through the small products), the pair at a0 -+ s has
+// r^2 = C + s^2 -+ 2 da0 s; its sums go in as w (1/r+ + 1/r-), w (1/r+^3 +
+// 1/r-^3) and w s (1/r+^3 - 1/r-^3), the last one into SA.  Per row the field's local parts
+// follow as E1 += da0 sg, E2 += (p2 - b) sg, S3 += sg with sg = sum over the row of w/r^3;
+// E1 -= SA once per element.  FP64 potential only: each pair's 1/r as y (1 + e (1/2 + 3e/8))
+// from the hardware estimate y (the third-order step of rsqrt64), the weight applied once.
+template <int PPT, int MODE, typename T, typename T4>
+__device__ __forceinline__ void pair_row(const T4* t, int n0, const Local<PPT, T>& L, T (&o)[Sums<MODE>::kNode][PPT],
+                                         T (&SA)[PPT])
+{
+    constexpr bool F64 = std::is_same<T, double>::value;
+    const T4 hd = t[n0];
+    const T b = hd.x, a0 = hd.y, wc = hd.z, g0 = hd.w;
+    T db[PPT], da0[PPT], C[PPT], mq[PPT], pq[PPT], sg[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        db[k] = L.p2[k] - b;
+        da0[k] = L.p1[k] - a0;
+        C[k] = fma(L.q1[k], a0, fma(L.q2[k], b, L.H[k] + g0));
+        mq[k] = T(-2) * da0[k];
+        pq[k] = T(2) * da0[k];
+    }
+    // the middle node (a = a0)
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if constexpr (MODE == kFarPhi) {
+            if constexpr (F64) {
+                const double y = __builtin_amdgcn_rsq(C[k]);
+                const double e = fma(-(C[k] * y), y, 1.0);
+                o[0][k] = fma(wc * y, fma(e, fma(e, 0.375, 0.5), 1.0), o[0][k]);
+            } else {
+                o[0][k] = fma(wc, rsqrtT(C[k]), o[0][k]);
             }
         } else {
-            const float da = L.p1[k] - a, db = L.p2[k] - b;
-            const float ri = rsqrt32(fmaf(da, da, fmaf(db, db, L.h[k])));
-            const float w3 = (w * ri) * (ri * ri);
-            const float va = da * ri, vb = db * ri, vc = L.p3[k] * ri;
-            const float ua = w3 * va, ub = w3 * vb, uc = w3 * vc;
-            o[0][k] += w3;
-            o[1][k] = fmaf(ua, va, o[1][k]);
-            o[2][k] = fmaf(ub, vb, o[2][k]);
-            o[3][k] = fmaf(uc, vc, o[3][k]);
-            o[4][k] = fmaf(ua, vb, o[4][k]);
-            o[5][k] = fmaf(ua, vc, o[5][k]);
-            o[6][k] = fmaf(ub, vc, o[6][k]);
+            const T ri = rsqrtT(C[k]);
+            o[0][k] = fma(wc, ri, o[0][k]);
+            sg[k] = wc * ((ri * ri) * ri);
+        }
+    }
+#pragma unroll
+    for (int pi = 1; pi <= 3; ++pi) {
+        const T4 Q = t[n0 + pi];
+        const T sv = Q.x, s2 = Q.y, w = Q.z, ws = Q.w;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const T u = C[k] + s2;
+            const T xp = fma(mq[k], sv, u), xm = fma(pq[k], sv, u);
+            if constexpr (MODE == kFarPhi) {
+                if constexpr (F64) {
+                    const double yp = __builtin_amdgcn_rsq(xp), ym = __builtin_amdgcn_rsq(xm);
+                    const double ep = fma(-(xp * yp), yp, 1.0), em = fma(-(xm * ym), ym, 1.0);
+                    const double vp = fma(ep, fma(ep, 0.375, 0.5), 1.0), vm = fma(em, fma(em, 0.375, 0.5), 1.0);
+                    o[0][k] = fma(w, fma(ym, vm, yp * vp), o[0][k]);
+                } else {
+                    o[0][k] = fma(w, rsqrtT(xp) + rsqrtT(xm), o[0][k]);
+                }
+            } else {
+                const T rp = rsqrtT(xp), rm = rsqrtT(xm);
+                const T r3p = (rp * rp) * rp, r3m = (rm * rm) * rm;
+                o[0][k] = fma(w, rp + rm, o[0][k]);
+                sg[k] = fma(w, r3p + r3m, sg[k]);
+                SA[k] = fma(ws, r3p - r3m, SA[k]);
+            }
+        }
+    }
+    if constexpr (MODE == kFarField) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            o[1][k] = fma(da0[k], sg[k], o[1][k]);
+            o[2][k] = fma(db[k], sg[k], o[2][k]);
+            o[3][k] += sg[k];
         }
     }
 }
 
-// Tensor rule in groups of G nodes with the same b: per group the lane forms db and
-// (p2 - b)^2 + p3^2 once; per node one difference remains.  Field: the b-component and
-// sum w/r^3 are gathered per group.  Gradient (the FP64 sums of node_term64): sum w/r^5
-// and sum w da/r^5 are gathered per group, and the sums with db follow from them.
-template <int G, int PPT, int MODE>
-__device__ __forceinline__ void group_sum64(const double4* t, int base, const Local<PPT, double>& L,
-                                            double (&o)[Sums<MODE>::kNode][PPT])
+// The 7 x 7 rule as seven pair rows; o (and SA) start at -0.0, the first row is peeled off.
+template <int PPT, int MODE, typename T, typename T4>
+__device__ __forceinline__ void pair_rows_sum(const T4* t, int base, const Local<PPT, T>& L,
+                                              T (&o)[Sums<MODE>::kNode][PPT])
 {
+    T SA[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) SA[k] = T(-0.0);
+    pair_row<PPT, MODE>(t, base, L, o, SA);
 #pragma unroll 1
-    for (int g = 0; g < G; ++g) {
-        const int n0 = base + g * G;
-        const double b = t[n0].y;
-        double db[PPT], B[PPT], sg[PPT], xg[PPT];
+    for (int r = 1; r < 7; ++r) pair_row<PPT, MODE>(t, base + 4 * r, L, o, SA);
+    if constexpr (MODE == kFarField) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            db[k] = L.p2[k] - b;
-            B[k] = fma(db[k], db[k], L.h[k]);
-            sg[k] = 0.0;
-            xg[k] = 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const double a = t[n0 + i].x, w = t[n0 + i].w;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const double da = L.p1[k] - a;
-                const double ri = rsqrt64(fma(da, da, B[k]));
-                if constexpr (MODE == kFarPhi) {
-                    o[0][k] = fma(w, ri, o[0][k]);
-                } else if constexpr (MODE == kFarField) {
-                    const double wr = w * ri;
-                    const double w3 = wr * (ri * ri);
-                    o[0][k] += wr;
-                    o[1][k] = fma(w3, da, o[1][k]);
-                    sg[k] += w3;
-                } else {
-                    const double ri2 = ri * ri;
-                    const double w3 = (w * ri) * ri2;
-                    const double w5 = w3 * ri2;
-                    const double ua = w5 * da;
-                    o[0][k] += w3;
-                    sg[k] += w5;
-                    xg[k] += ua;
-                    o[4][k] = fma(ua, da, o[4][k]);
-                }
-            }
-        }
-        if constexpr (MODE == kFarField) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                o[2][k] = fma(sg[k], db[k], o[2][k]);
-                o[3][k] += sg[k];
-            }
-        } else if constexpr (MODE == kFarGrad) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const double u = sg[k] * db[k];  // sum w db / r^5 of the group
-                o[1][k] += sg[k];
-                o[2][k] += xg[k];
-                o[3][k] += u;
-                o[5][k] = fma(u, db[k], o[5][k]);
-                o[6][k] = fma(xg[k], db[k], o[6][k]);
-            }
-        }
+        for (int k = 0; k < PPT; ++k) o[1][k] -= SA[k];
     }
 }
 
-template <int G, int PPT, int MODE>
-__device__ __forceinline__ void group_sum32(const float4* t, int base, const Local<PPT, float>& L,
-                                            float (&o)[Sums<MODE>::kNode][PPT])
+// One folded node whose r^2 / w^2 is x: potential (and field sums S3 and, for S21 nodes, the
+// vertex sum tv = sum (w/r)^3 s / w^2, from which S1 and S2 follow per pair).
+template <int MODE, typename T>
+__device__ __forceinline__ void folded_point(T x, T iw2, T sv, T& o0, T& o3, T& tv)
 {
-    static_assert(MODE != kFarGrad, "the gradient takes the node-by-node form");
-#pragma unroll 1
-    for (int g = 0; g < G; ++g) {
-        const int n0 = base + g * G;
-        const float b = t[n0].y;
-        float db[PPT], B[PPT], sg[PPT];
+    if constexpr (MODE == kFarPhi) {
+        if constexpr (std::is_same<T, double>::value) {
+            const double y = __builtin_amdgcn_rsq(x);
+            const double e = fma(-(x * y), y, 1.0);
+            o0 = fma(y, fma(e, fma(e, 0.375, 0.5), 1.0), o0);
+        } else {
+            o0 += rsqrtT(x);
+        }
+    } else {
+        const T wr = rsqrtT(x);  // w / r
+        const T wr3 = (wr * wr) * wr;
+        o0 += wr;
+        tv = fma(wr3, sv, tv);
+        o3 = fma(wr3, iw2, o3);
+    }
+}
+
+// A compiled triangle rule with its orbit structure (TriOrbits), folded nodes: the centroid
+// (r^2 = D^2), the S21 orbits (r^2 = D^2 + |n|^2 + s P_k with P_k = -2 d.u_k per pair; the
+// field's in-plane sums per vertex), then the other orbits with the expanded form of
+// node_term.  The sums in o start at -0.0; the first orbit of each kind is peeled off.
+template <int NN, int PPT, int MODE, typename Lds, typename T>
+__device__ __forceinline__ void tri_sum(const Lds& s, int j, int base, const Local<PPT, T>& L,
+                                        T (&o)[Sums<MODE>::kNode][PPT])
+{
+    using O = TriOrbits<NN>;
+    constexpr int NC = O::nc, N21 = O::n21, GS = O::gs, NG = NN - NC - 3 * N21;
+    static_assert(NG % GS == 0, "orbit groups");
+    constexpr int I3 = MODE == kFarPhi ? 0 : 3;  // index of S3 (unused for the potential alone)
+    T Pk[3][PPT], Tk[3][PPT], dummy[PPT];
+    if constexpr (N21 > 0) {
+        const T ax = s.lc[0][j], ay = s.lc[1][j], bx = s.lc[2][j], by = s.lc[3][j];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            db[k] = L.p2[k] - b;
-            B[k] = fmaf(db[k], db[k], L.h[k]);
-            sg[k] = 0.0f;
+            Pk[0][k] = fma(ax, L.q1[k], ay * L.q2[k]);
+            Pk[1][k] = fma(bx, L.q1[k], by * L.q2[k]);
+            Pk[2][k] = -(Pk[0][k] + Pk[1][k]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Tk[c][k] = T(-0.0);
         }
+    }
+    if constexpr (NC > 0) {
+        const T iw2 = s.nd[base].z;
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const float4 Q = t[n0 + i];
+        for (int k = 0; k < PPT; ++k)
+            folded_point<MODE, T>(L.H[k] * iw2, iw2, T(0), o[0][k], o[I3][k], dummy[k]);
+    }
+    if constexpr (N21 > 0) {
+        auto orbit = [&](int ob) {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const float da = L.p1[k] - Q.x;
-                const float ri = rsqrt32(fmaf(da, da, B[k]));
-                if constexpr (MODE == kFarPhi) {
-                    o[0][k] = fmaf(Q.w, ri, o[0][k]);
-                } else {
-                    const float wr = Q.w * ri;
-                    const float w3 = wr * (ri * ri);
-                    o[0][k] += wr;
-                    o[1][k] = fmaf(w3, da, o[1][k]);
-                    sg[k] += w3;
-                }
+            for (int kk = 0; kk < 3; ++kk) {
+                const auto Q = s.nd[base + NC + 3 * ob + kk];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    folded_point<MODE, T>(fma(Q.x, Pk[kk][k], fma(L.H[k], Q.z, Q.y)), Q.z, Q.x, o[0][k], o[I3][k],
+                                       Tk[kk][k]);
             }
-        }
-        if constexpr (MODE == kFarField) {
+        };
+        orbit(0);
+#pragma unroll 1
+        for (int ob = 1; ob < N21; ++ob) orbit(ob);
+    }
+    if constexpr (NG > 0) {
+        const int g0 = base + NC + 3 * N21;
+        auto group = [&](int g) {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                o[2][k] = fmaf(sg[k], db[k], o[2][k]);
-                o[3][k] += sg[k];
-            }
+            for (int u = 0; u < GS; ++u) node_term<PPT, MODE, true>(s.nd[g0 + g * GS + u], L, o);
+        };
+        group(0);
+#pragma unroll 1
+        for (int g = 1; g < NG / GS; ++g) group(g);
+    }
+    if constexpr (N21 > 0 && MODE == kFarField) {
+        const T l0 = s.lc[0][j], l1 = s.lc[1][j], l2 = s.lc[2][j], l3 = s.lc[3][j], l4 = s.lc[4][j], l5 = s.lc[5][j];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            o[1][k] = fma(l0, Tk[0][k], fma(l2, Tk[1][k], fma(l4, Tk[2][k], o[1][k])));
+            o[2][k] = fma(l1, Tk[0][k], fma(l3, Tk[1][k], fma(l5, Tk[2][k], o[2][k])));
         }
     }
 }
 
 // Sums of one element over its nodes [base, base + n) of the tile (Eq. 4.1, unit element
 // charge) in the precision T of the tile (FP64, or FP32 for the mixed path).  NN > 0:
-// compile-time node count; G > 0: tensor rule in groups of G.  Gradient: the result is the
-// local tensor (sum w/r^3; sum w d_i d_j / r^5 for xx, yy, zz, xy, xz, yz, d = (da, db, p3)).
-template <int NN, int G, bool MIXED, int PPT, int MODE, bool EXP, typename Lds, typename T>
-__device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const Local<PPT, T>& L,
+// compile-time node count; G > 0: tensor rule in groups of G (rows form).  Field, expanded:
+// (sum w/r, S1, S2, S3) in node coordinates; rows: (sum w/r, local E1, local E2 without p3,
+// sum w/r^3).  Gradient: the local tensor (sum w/r^3; sum w d_i d_j / r^5 for xx, yy, zz,
+// xy, xz, yz, d = (da, db, p3)).
+template <int NN, int G, bool FOLD, bool TRI, int PPT, int MODE, typename Lds, typename T>
+__device__ __forceinline__ void element_sum(const Lds& s, int j, int base, int n, const Local<PPT, T>& L,
                                             T (&o)[Sums<MODE>::kNode][PPT])
 {
     constexpr int S = Sums<MODE>::kNode;
-    T r[S][PPT];
+    constexpr bool MIXED = std::is_same<T, float>::value;
 #pragma unroll
     for (int c = 0; c < S; ++c)
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) r[c][k] = T(0);
+        for (int k = 0; k < PPT; ++k) o[c][k] = T(-0.0);
     const int nn = NN > 0 ? NN : n;
     constexpr bool GROUPS = G > 0 && (MODE != kFarGrad || !MIXED);
-    if constexpr (!MIXED) {
-        if constexpr (GROUPS) group_sum64<G, PPT, MODE>(s.nd, base, L, r);
-        else for_nodes<NN>(nn, [&](int i) { node_term64<PPT, MODE, EXP>(s.nd[base + i], L, r); });
+    if constexpr (GROUPS && MODE == kFarGrad) {
+        group_sum<G, PPT, MODE>(s.nd, base, L, o);
+    } else if constexpr (GROUPS) {
+        static_assert(G == 7, "pair rows are built for the 7 x 7 rule");
+        pair_rows_sum<PPT, MODE>(s.nd, base, L, o);
+    } else if constexpr (TRI && FOLD && NN > 0 && MODE != kFarGrad) {
+        tri_sum<NN, PPT, MODE>(s, j, base, L, o);
     } else {
-        if constexpr (GROUPS) group_sum32<G, PPT, MODE>(s.nd, base, L, r);
-        else for_nodes<NN>(nn, [&](int i) { node_term32<PPT, MODE, EXP>(s.nd[base + i], L, r); });
+        node_term<PPT, MODE, FOLD>(s.nd[base], L, o);
+        for_nodes<NN>(nn, [&](int i) { node_term<PPT, MODE, FOLD>(s.nd[base + i], L, o); });
     }
-    if constexpr (MODE == kFarField && EXP && !GROUPS) {
+    if constexpr (MODE == kFarGrad && !MIXED) {
+        T r[S][PPT];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            o[0][k] = r[0][k];
-            o[1][k] = fma(L.p1[k], r[3][k], -r[1][k]);
-            o[2][k] = fma(L.p2[k], r[3][k], -r[2][k]);
-            o[3][k] = r[3][k];
-        }
-    } else if constexpr (MODE == kFarGrad && !MIXED) {
+        for (int c = 0; c < S; ++c)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) r[c][k] = o[c][k];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             o[0][k] = r[0][k];
@@ -443,18 +786,15 @@ __device__ __forceinline__ void element_sum(const Lds& s, int base, int n, const
             o[5][k] = L.p3[k] * r[2][k];
             o[6][k] = L.p3[k] * r[3][k];
         }
-    } else {
-#pragma unroll
-        for (int c = 0; c < S; ++c)
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) o[c][k] = r[c][k];
     }
 }
 
 // Offsets of the lane's points from element j of the tile: D^2 in FP64 (the distance test,
-// Sec. 2) and the coordinates in the element's frame, in the precision of the node sums;
-// EXP: with -2 p and |p|^2 for the expanded r^2; H2: with p3^2 (differences, rows).
-template <bool EXP, bool H2 = !EXP, int PPT, typename Lds, typename T>
+// Sec. 2) and the coordinates the node sums need, in their precision.  Expanded: -2 f1.d,
+// -2 f2.d and |p|^2 = D^2 (the rotation keeps the length, to rounding); rows: p = F d and
+// p3^2; BOTH (rectangles with the rule chosen by distance ratio): rows, and the expanded
+// coordinates from them.
+template <int FR, bool BOTH, int PPT, typename Lds, typename T>
 __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[PPT], const double (&y)[PPT],
                                          const double (&z)[PPT], double (&D2)[PPT], Local<PPT, T>& L)
 {
@@ -462,37 +802,52 @@ __device__ __forceinline__ void to_frame(const Lds& s, int j, const double (&x)[
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
+        L.dx[k] = dx;
+        L.dy[k] = dy;
+        L.dz[k] = dz;
         D2[k] = fma(dx, dx, fma(dy, dy, dz * dz));
         const T u = (T)dx, v = (T)dy, w = (T)dz;
-        L.p1[k] = fma(u, s.f[0][j], fma(v, s.f[1][j], w * s.f[2][j]));
-        L.p2[k] = fma(u, s.f[3][j], fma(v, s.f[4][j], w * s.f[5][j]));
-        L.p3[k] = fma(u, s.f[6][j], fma(v, s.f[7][j], w * s.f[8][j]));
-        if constexpr (EXP) {  // |p|^2 = D^2: the rotation keeps the length (to rounding)
-            L.q1[k] = T(-2) * L.p1[k];
-            L.q2[k] = T(-2) * L.p2[k];
+        if constexpr (FR == kFrExp) {
+            L.q1[k] = fma(u, s.fr[0][j], fma(v, s.fr[1][j], w * s.fr[2][j]));
+            L.q2[k] = fma(u, s.fr[3][j], fma(v, s.fr[4][j], w * s.fr[5][j]));
             L.H[k] = (T)D2[k];
+        } else {
+            L.p1[k] = fma(u, s.fr[0][j], fma(v, s.fr[1][j], w * s.fr[2][j]));
+            L.p2[k] = fma(u, s.fr[3][j], fma(v, s.fr[4][j], w * s.fr[5][j]));
+            L.p3[k] = fma(u, s.fr[6][j], fma(v, s.fr[7][j], w * s.fr[8][j]));
+            L.h[k] = L.p3[k] * L.p3[k];
+            if constexpr (BOTH) {
+                L.q1[k] = T(-2) * L.p1[k];
+                L.q2[k] = T(-2) * L.p2[k];
+                L.H[k] = (T)D2[k];
+            }
         }
-        if constexpr (H2) L.h[k] = L.p3[k] * L.p3[k];
     }
 }
 
-// acc += q * (element sums of point k), rotated to the global axes in the precision of the
-// sums and accumulated in FP64
-template <int PPT, int MODE, typename Lds, typename T>
+// acc += the element's contribution to point k (charge q, sums o), in FP64.
+//   expanded sums:  phi += q sum w/r;  E += (q S3) d - (q f1) S1 - (q f2) S2;
+//   rows:           phi += q sum w/r;  E += (q f1) E1 + (q f2) E2 + (q f3) p3 S3;
+//   gradient:       the global tensor M = F m F^T of the local one m (F: the frame vectors
+//                   as columns), dE_i/dx_j += q (delta_ij sum w/r^3 - 3 M_ij).
+template <int FR, int PPT, int MODE, typename Lds, typename T>
 __device__ __forceinline__ void add_element(PointSet<PPT, MODE>& P, int k, double q, const Lds& s, int j,
                                             const Local<PPT, T>& L, const T (&o)[Sums<MODE>::kNode][PPT])
 {
     if constexpr (MODE == kFarField) {
         P.acc[0][k] = fma(q, (double)o[0][k], P.acc[0][k]);
-        const T t3 = L.p3[k] * o[3][k];
+        if constexpr (FR == kFrExp) {
+            const double s1 = (double)o[1][k], s2 = (double)o[2][k], qs3 = q * (double)o[3][k];
+            P.acc[1][k] = fma(qs3, L.dx[k], fma(s.qr[0][j], s1, fma(s.qr[3][j], s2, P.acc[1][k])));
+            P.acc[2][k] = fma(qs3, L.dy[k], fma(s.qr[1][j], s1, fma(s.qr[4][j], s2, P.acc[2][k])));
+            P.acc[3][k] = fma(qs3, L.dz[k], fma(s.qr[2][j], s1, fma(s.qr[5][j], s2, P.acc[3][k])));
+        } else {
+            const double e1 = (double)o[1][k], e2 = (double)o[2][k], e3 = (double)(L.p3[k] * o[3][k]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T e = fma(s.f[c][j], o[1][k], fma(s.f[3 + c][j], o[2][k], s.f[6 + c][j] * t3));
-            P.acc[1 + c][k] = fma(q, (double)e, P.acc[1 + c][k]);
+            for (int c = 0; c < 3; ++c)
+                P.acc[1 + c][k] = fma(s.qr[c][j], e1, fma(s.qr[3 + c][j], e2, fma(s.qr[6 + c][j], e3, P.acc[1 + c][k])));
         }
     } else {
-        // global tensor M = F m F^T of the local one m (F: the frame vectors as columns);
-        // dE_i/dx_j = q (delta_ij sum w/r^3 - 3 M_ij)
         const T m[3][3] = { { o[1][k], o[4][k], o[5][k] },
                             { o[4][k], o[2][k], o[6][k] },
                             { o[5][k], o[6][k], o[3][k] } };
@@ -501,9 +856,9 @@ __device__ __forceinline__ void add_element(PointSet<PPT, MODE>& P, int k, doubl
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                U[a][c] = fma(m[a][0], s.f[c][j], fma(m[a][1], s.f[3 + c][j], m[a][2] * s.f[6 + c][j]));
+                U[a][c] = fma(m[a][0], s.fr[c][j], fma(m[a][1], s.fr[3 + c][j], m[a][2] * s.fr[6 + c][j]));
         auto M = [&](int u, int v) -> double {
-            return (double)fma(s.f[u][j], U[0][v], fma(s.f[3 + u][j], U[1][v], s.f[6 + u][j] * U[2][v]));
+            return (double)fma(s.fr[u][j], U[0][v], fma(s.fr[3 + u][j], U[1][v], s.fr[6 + u][j] * U[2][v]));
         };
         const double s3 = (double)o[0][k];
 #pragma unroll
@@ -514,43 +869,62 @@ __device__ __forceinline__ void add_element(PointSet<PPT, MODE>& P, int k, doubl
     }
 }
 
-// group size of the tensor path for a rectangle rule of NN nodes (7 x 7 only)
+// group size of the rows form for a rectangle rule of NN nodes (7 x 7 only)
 template <bool TRI, int NN>
 constexpr int tensor_group() { return (!TRI && NN == 49) ? 7 : 0; }
 
+// frame form of an element kind with a compiled rule of NN nodes
+template <bool TRI, int NN, int MODE>
+constexpr int frame_form() { return (MODE == kFarGrad || tensor_group<TRI, NN>() > 0) ? kFrRows : kFrExp; }
+
 // One element kind over [e_begin, e_end) with one rule; NN > 0 is the compile-time node
-// count, NN == 0 reads it at run time.
-template <int NN, bool TRI, bool MIXED, int PPT, int MODE, typename Lds>
+// count, NN == 0 reads it at run time.  FOLD: the rule's weights are all positive (the
+// nodes are staged divided by w^2).
+template <int NN, bool TRI, bool MIXED, int PPT, int MODE, bool FOLD, typename Lds>
 __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSet<PPT, MODE>& P, int64_t e_begin,
                                                int64_t e_end)
 {
     using T = typename Lds::T;
-    // the expanded r^2 (node loop without rows; the gradient keeps the differences)
-    constexpr bool EXPAND = MODE != kFarGrad && tensor_group<TRI, NN>() == 0;
+    constexpr int FR = frame_form<TRI, NN, MODE>();
+    constexpr bool FOLD_ = FOLD && FR == kFrExp;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
+    const TriForms tf = fixed_forms<NN, TRI && FOLD_>(nn);
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
         const int te = (int)min((int64_t)TE, e_end - t0);
         __syncthreads();
-        stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, a.rhs, 1);
+        constexpr bool PROWS = tensor_group<TRI, NN>() > 0 && MODE != kFarGrad;
+        stage_tile<TRI, MIXED, 1, FR, MODE == kFarField>(s, a.el, a.rules, nn, t0, te, a.rhs, 1, FOLD_ ? nn : 0,
+                                                         PROWS ? 0 : nn, tf);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<EXPAND>(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<FR, FR == kFrRows && MODE != kFarGrad>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                nr[k] = P.valid[k] && (D2[k] < thr2);
-                record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+                nr[k] = P.valid[k] && (D2[k] < thr2);  // listed by near_list_kernel
             }
             T o[Sums<MODE>::kNode][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, MODE, EXPAND>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), FOLD_, TRI, PPT, MODE>(s, j, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (!nr[k]) add_element<PPT, MODE>(P, k, q, s, j, L, o);
+                if (!nr[k]) add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
         }
+    }
+}
+
+// Expanded sums (node coordinates) of a rectangle level turned into the local field of the
+// rows form: E1 = p1 S3 - S1, E2 = p2 S3 - S2.
+template <int PPT, typename T>
+__device__ __forceinline__ void exp_to_rows(const Local<PPT, T>& L, T (&o)[4][PPT])
+{
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        o[1][k] = fma(L.p1[k], o[3][k], -o[1][k]);
+        o[2][k] = fma(L.p2[k], o[3][k], -o[2][k]);
     }
 }
 
@@ -559,33 +933,48 @@ __device__ __forceinline__ void far_eval_range(const FarArgs& a, Lds& s, PointSe
 // L)^2 (the last level otherwise).  The wavefront runs the finest level that any of its
 // pairs needs, once, for all its lanes: a finer rule is at least as accurate at a larger
 // distance ratio, and one level per wavefront costs less than each level a lane needs.
-// N0..N3 > 0: compile-time counts.
+// N0..N3 > 0: compile-time counts (the levels' weights are then all positive).
+// Triangles take the expanded form throughout; rectangles the rows form for a 7 x 7 last
+// level, the expanded form (turned into the rows form's local field) for the others.
 template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, int MODE, typename Lds>
 __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, MODE>& P, int64_t e_begin,
-                                                  int64_t e_end, unsigned long long& terms)
+                                                  int64_t e_end, unsigned long long& terms,
+                                                  unsigned long long& terms_pair)
 {
     using T = typename Lds::T;
+    constexpr bool GRAD = MODE == kFarGrad;
+    constexpr int FR = (TRI && !GRAD) ? kFrExp : kFrRows;
+    constexpr bool FOLD = N0 > 0 && !GRAD;
     const int* off = TRI ? a.lv.tri_off : a.lv.rect_off;
     const double* c = TRI ? a.lv.tri_c : a.lv.rect_c;
     const int o1 = off[1], o2 = off[2], o3 = off[3], nn = off[4];
     const double c0 = c[0], c1 = c[1], c2 = c[2];
     const int TE = tile_elems(nn);
+    TriForms tf{ 4, { off[0], o1, o2, o3, nn }, { 0, 0, 0, 0 }, { 0, 0, 0, 0 } };
+    if (TRI && FOLD) {
+        tf.nc[0] = TriOrbits<N0>::nc; tf.n21[0] = 3 * TriOrbits<N0>::n21;
+        tf.nc[1] = TriOrbits<N1>::nc; tf.n21[1] = 3 * TriOrbits<N1>::n21;
+        tf.nc[2] = TriOrbits<N2>::nc; tf.n21[2] = 3 * TriOrbits<N2>::n21;
+        tf.nc[3] = TriOrbits<N3>::nc; tf.n21[3] = 3 * TriOrbits<N3>::n21;
+    }
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
         const int te = (int)min((int64_t)TE, e_end - t0);
         __syncthreads();
-        stage_tile<TRI, MIXED>(s, a.el, a.lv.tab, nn, t0, te, a.rhs, 1);
+        // the 7 x 7 last level of the rectangles keeps its weights (rows form)
+        const int nfold = !FOLD ? 0 : (tensor_group<TRI, N3>() > 0 ? o3 : nn);
+        const int prow = (tensor_group<TRI, N3>() > 0 && !GRAD) ? o3 : nn;
+        stage_tile<TRI, MIXED, 1, FR, !GRAD>(s, a.el, a.lv.tab, nn, t0, te, a.rhs, 1, nfold, prow, tf);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
             const double thr2 = s.thr2[j], q = s.q[0][j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<MODE != kFarGrad, true>(s, j, P.x, P.y, P.z, D2, L);
+            to_frame<FR, !TRI && !GRAD>(s, j, P.x, P.y, P.z, D2, L);
             bool nr[PPT];
             int lvl[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                nr[k] = P.valid[k] && (D2[k] < thr2);
-                record_near(nr[k], P.idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+                nr[k] = P.valid[k] && (D2[k] < thr2);  // listed by near_list_kernel
                 lvl[k] = D2[k] >= c0 * thr2 ? 0 : (D2[k] >= c1 * thr2 ? 1 : (D2[k] >= c2 * thr2 ? 2 : 3));
                 if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
             }
@@ -598,37 +987,44 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             T o[Sums<MODE>::kNode][PPT];
             const int b = j * nn;
             int nw;
-            constexpr bool X = MODE != kFarGrad;
-            if (wl == 0) { element_sum<N0, 0, MIXED, PPT, MODE, X>(s, b, o1, L, o); nw = o1; }
-            else if (wl == 1) { element_sum<N1, 0, MIXED, PPT, MODE, X>(s, b + o1, o2 - o1, L, o); nw = o2 - o1; }
-            else if (wl == 2) { element_sum<N2, 0, MIXED, PPT, MODE, X>(s, b + o2, o3 - o2, L, o); nw = o3 - o2; }
+            if (wl == 0) { element_sum<N0, 0, FOLD, TRI, PPT, MODE>(s, j, b, o1, L, o); nw = o1; }
+            else if (wl == 1) { element_sum<N1, 0, FOLD, TRI, PPT, MODE>(s, j, b + o1, o2 - o1, L, o); nw = o2 - o1; }
+            else if (wl == 2) { element_sum<N2, 0, FOLD, TRI, PPT, MODE>(s, j, b + o2, o3 - o2, L, o); nw = o3 - o2; }
             else {
-                element_sum<N3, tensor_group<TRI, N3>(), MIXED, PPT, MODE, X>(s, b + o3, nn - o3, L, o);
+                constexpr int G3 = tensor_group<TRI, N3>();
+                element_sum<N3, G3, FOLD && (TRI || G3 == 0), TRI, PPT, MODE>(s, j, b + o3, nn - o3, L, o);
                 nw = nn - o3;
+            }
+            if constexpr (!TRI && !GRAD) {
+                // rows form for the rotation back; the 7 x 7 last level is in it already
+                if (!(wl == 3 && tensor_group<TRI, N3>() > 0)) exp_to_rows<PPT>(L, o);
             }
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (lvl[k] >= 0) {
-                    add_element<PPT, MODE>(P, k, q, s, j, L, o);
+                    add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
                     terms += (unsigned)nw;
+                    // the terms of the pair's own level (the per-pair choice)
+                    terms_pair += (unsigned)(lvl[k] == 0 ? o1 : (lvl[k] == 1 ? o2 - o1 : (lvl[k] == 2 ? o3 - o2 : nn - o3)));
                 }
         }
     }
 }
 
-__device__ __forceinline__ void add_terms(unsigned long long terms, DevCounters* ctr)
+// wavefront sum of a counter, added with one atomic per wavefront
+__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* dst)
 {
-    // wavefront sum, one atomic per wavefront
     for (int o = 32; o > 0; o >>= 1) {
-        const unsigned lo = __shfl_xor((unsigned)terms, o);
-        const unsigned hi = __shfl_xor((unsigned)(terms >> 32), o);
-        terms += ((unsigned long long)hi << 32) | lo;
+        const unsigned lo = __shfl_xor((unsigned)v, o);
+        const unsigned hi = __shfl_xor((unsigned)(v >> 32), o);
+        v += ((unsigned long long)hi << 32) | lo;
     }
-    if (lane_id() == 0 && terms) atomicAdd(&ctr->node_ints, terms);
+    if (lane_id() == 0 && v) atomicAdd(dst, v);
 }
 
 // DR == false: one rule per kind, NT / NR nodes.  DR == true: levels (T0..T3 / R0..R3).
-// GRAD: field gradient instead of potential and field.
+// GRAD: field gradient instead of potential and field.  Compiled node counts (NT, NR > 0)
+// are used only for rules whose weights are all positive (their nodes are folded).
 template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT, bool GRAD>
 __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
 {
@@ -656,13 +1052,16 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
     const int64_t nt_end = min((int64_t)a.el.n_tri, e_hi);
     const int64_t nr_begin = max((int64_t)a.el.n_tri, e_lo);
     if (DR) {
-        unsigned long long terms = 0;
-        if (e_lo < nt_end) far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end, terms);
-        if (nr_begin < e_hi) far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi, terms);
-        add_terms(terms, a.ctr);
+        unsigned long long terms = 0, terms_pair = 0;
+        if (e_lo < nt_end)
+            far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end, terms, terms_pair);
+        if (nr_begin < e_hi)
+            far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi, terms, terms_pair);
+        add_count(terms, &a.ctr->node_ints);
+        add_count(terms_pair, &a.ctr->node_ints_pair);
     } else {
-        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end);
-        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi);
+        if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, MODE, (NT > 0)>(a, s, P, e_lo, nt_end);
+        if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, MODE, (NR > 0)>(a, s, P, nr_begin, e_hi);
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -694,28 +1093,30 @@ __device__ __forceinline__ void far_colloc_range(const FarArgs& a, Lds& s, const
                                                  double (&acc)[PPT][kMaxRhs], int64_t e_begin, int64_t e_end)
 {
     using T = typename Lds::T;
-    constexpr bool EXPAND = tensor_group<TRI, NN>() == 0;
+    constexpr int FR = frame_form<TRI, NN, kFarPhi>();
+    constexpr bool FOLD = NN > 0 && FR == kFrExp;
     const int nn = NN > 0 ? NN : (TRI ? a.rules.nt : a.rules.nr);
     const int TE = tile_elems(nn);
     const int nrhs = a.n_rhs;
+    const TriForms tf = fixed_forms<NN, TRI && FOLD>(nn);
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
         const int te = (int)min((int64_t)TE, e_end - t0);
         __syncthreads();
-        stage_tile<TRI, MIXED>(s, a.el, a.rules, nn, t0, te, 0, nrhs);
+        stage_tile<TRI, MIXED, kMaxRhs, FR, false>(s, a.el, a.rules, nn, t0, te, 0, nrhs, FOLD ? nn : 0,
+                                                   tensor_group<TRI, NN>() > 0 ? 0 : nn, tf);
         __syncthreads();
         for (int j = 0; j < te; ++j) {
             const double thr2 = s.thr2[j];
             double D2[PPT];
             Local<PPT, T> L;
-            to_frame<EXPAND>(s, j, px, py, pz, D2, L);
+            to_frame<FR, FR == kFrRows>(s, j, px, py, pz, D2, L);
             bool nr[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                nr[k] = valid[k] && (D2[k] < thr2);
-                record_near(nr[k], idx[k], (uint32_t)(t0 + j), a.near_list, a.near_cap, a.ctr);
+                nr[k] = valid[k] && (D2[k] < thr2);  // listed by near_list_kernel
             }
             T o[1][PPT];
-            element_sum<NN, tensor_group<TRI, NN>(), MIXED, PPT, kFarPhi, EXPAND>(s, j * nn, nn, L, o);
+            element_sum<NN, tensor_group<TRI, NN>(), FOLD, TRI, PPT, kFarPhi>(s, j, j * nn, nn, L, o);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!nr[k]) {
@@ -1057,6 +1458,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 // leaf: the element's rule on this node, weights scaled by the area ratio h^2
                 double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
                 if (st.kind == 0) {
+#pragma unroll 4
                     for (int i = 0; i < a.rules.nt; ++i) {
                         const double la = a.rules.tri[4 * i], lb = a.rules.tri[4 * i + 1], lc = a.rules.tri[4 * i + 2];
                         const double w = a.rules.tri[4 * i + 3];
@@ -1067,6 +1469,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     }
                 } else {
                     const double hh = 0.5 * h;
+#pragma unroll 4
                     for (int i = 0; i < a.rules.nr; ++i) {
                         const double x = a.rules.rect[4 * i] * hh, y = a.rules.rect[4 * i + 1] * hh;
                         const double w = a.rules.rect[4 * i + 2];
@@ -1102,15 +1505,22 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         }
 
         if (finished) {
-            // the pair's own result slot(s); collocation keeps the unit-density potential
-            // (the densities are applied per right-hand side when the sums are formed)
-            const unsigned long long S = a.res_stride;
+            // the pair's own result record at its slot, written at once (32 bytes for the
+            // field, 48 for the gradient); collocation keeps the unit-density potential (the
+            // densities are applied per right-hand side when the sums are formed)
             if (COLLOC) {
                 a.res[cur] = acc[0];
             } else {
                 const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
-#pragma unroll
-                for (int c = 0; c < (GRAD ? 6 : 4); ++c) a.res[c * S + cur] = Kq * acc[c];
+                if (GRAD) {
+                    double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
+                    r[0] = make_double2(Kq * acc[0], Kq * acc[1]);
+                    r[1] = make_double2(Kq * acc[2], Kq * acc[3]);
+                    r[2] = make_double2(Kq * acc[4], Kq * acc[5]);
+                } else {
+                    reinterpret_cast<double4*>(a.res)[cur] =
+                        make_double4(Kq * acc[0], Kq * acc[1], Kq * acc[2], Kq * acc[3]);
+                }
             }
             active = false;
             st.level = 0;
@@ -1275,6 +1685,16 @@ hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, NearPair* list, unsigned long long cap,
+                            DevCounters* ctr, hipStream_t s)
+{
+    if (n <= 0 || el.ne <= 0) return hipSuccess;
+    const int64_t blocks = (n + kListPoints - 1) / kListPoints;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    near_list_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(pts, n, el, list, cap, ctr);
+    return hipGetLastError();
+}
+
 hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s)
 {
     const int64_t tot = ne * n_rhs;
@@ -1379,6 +1799,14 @@ __global__ void divide_kernel(double* __restrict__ y, const double* __restrict__
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) y[i] = x[i] / d[i];
+}
+
+__global__ void reset_near_count_kernel(DevCounters* c) { c->near_count = 0ull; }
+
+hipError_t launch_reset_near_count(DevCounters* c, hipStream_t s)
+{
+    reset_near_count_kernel<<<1, 1, 0, s>>>(c);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s)

@@ -1,14 +1,14 @@
 // Deterministic near-field accumulation.
 //
-// The far kernel appends near pairs to a list in an order that depends on scheduling.
+// The list pass appends near pairs to a list in an order that depends on scheduling.
 // Before the near kernel runs, each pair gets a result slot in (point, element) order:
 // pairs are regrouped by field point (counts per point, an exclusive scan, a scatter) and
 // each point's segment is ordered by element index.  The near kernel walks the pairs in
-// the far kernel's list order (neighbouring points and the same element: similar
-// subdivision trees side by side) and writes each result to the pair's slot; one thread
-// per point then adds its segment in element order to the point's far-field result.  The
-// outcome does not depend on how the GPU scheduled the work.  No step needs the pair count
-// on the host: the kernels read it from the device counters.
+// the list's order (neighbouring points and the same element: similar subdivision trees
+// side by side) and writes each pair's result record to its slot; one thread per point
+// then adds its segment in element order to the point's far-field result.  The outcome
+// does not depend on how the GPU scheduled the work.  No step needs the pair count on the
+// host: the kernels read it from the device counters.
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"
@@ -77,11 +77,12 @@ __global__ void rank_sort_kernel(const uint32_t* __restrict__ start, const uint3
 }
 
 // Adds each point's near-pair results, in element order, to its far-field result.
-// mode kNearEval: rows phi, Ex, Ey, Ez (already scaled); kNearGrad: six gradient rows
-// (scaled); kNearColloc: one unscaled row, multiplied here by K q_r(element) per density r.
+// mode kNearEval: records (phi, Ex, Ey, Ez) (already scaled); kNearGrad: records of the six
+// gradient rows (scaled); kNearColloc: one unscaled value per pair, multiplied here by
+// K q_r(element) per density r.
 __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
                                     int64_t n, const NearPair* __restrict__ sorted, const double* __restrict__ res,
-                                    unsigned long long stride, int mode, double* __restrict__ phi,
+                                    int mode, double* __restrict__ phi,
                                     double* __restrict__ E, double* __restrict__ G, const double* __restrict__ q,
                                     int64_t ne, int n_rhs, double K)
 {
@@ -97,10 +98,11 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
         }
         return;
     }
+    const int rec = mode == kNearGrad ? 6 : 4;  // result record of a pair (see near_kernel)
     const int rows = mode == kNearGrad ? 6 : (E ? 4 : 1);
     for (int c = 0; c < rows; ++c) {
         double acc = 0.0;
-        for (uint32_t m = 0; m < k; ++m) acc += res[(unsigned long long)c * stride + s + m];
+        for (uint32_t m = 0; m < k; ++m) acc += res[(unsigned long long)(s + m) * rec + c];
         if (mode == kNearGrad) G[(int64_t)c * n + p] += acc;
         else if (c == 0) phi[p] += acc;
         else E[(int64_t)(c - 1) * n + p] += acc;
@@ -174,12 +176,12 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
     return hipGetLastError();
 }
 
-hipError_t near_reduce(const NearWork& w, int64_t n, unsigned long long stride, int mode, double* phi, double* E,
+hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
                        double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     reduce_pairs_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        w.start, w.count, n, w.sorted, w.res, stride, mode, phi, E, G, q, ne, n_rhs, K);
+        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K);
     return hipGetLastError();
 }
 

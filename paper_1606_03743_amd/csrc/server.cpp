@@ -234,6 +234,7 @@ bool Server::launch(Slot& s, std::string& err)
     fa.ctr = s.d_ctr;
     fa.dr_rules = env_.dr_rules;
     fa.lv = env_.lv;
+    if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
     if (e == hipSuccess) e = launch_far_eval(fa, cfg_.precision, s.stream);
     if (e == hipSuccess && n_split > 1) e = launch_reduce_split(s.d_partial, n_split, n, K, s.d_phi, s.d_E, s.stream);
     NearArgs na{};
@@ -250,7 +251,6 @@ bool Server::launch(Slot& s, std::string& err)
     na.near_cap = s.near_cap;
     na.slot = s.nw.slot;
     na.res = s.nw.res;
-    na.res_stride = s.near_cap;
     na.ctr = s.d_ctr;
     na.near_dr2 = env_.near_dr * env_.near_dr;
     na.max_depth = env_.max_depth;
@@ -258,7 +258,7 @@ bool Server::launch(Slot& s, std::string& err)
     if (e == hipSuccess) e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.nw, s.stream);
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess)
-        e = near_reduce(s.nw, n, s.near_cap, kNearEval, s.d_phi, s.d_E, nullptr, env_.el.q, ne, 1, K, s.stream);
+        e = near_reduce(s.nw, n, kNearEval, s.d_phi, s.d_E, nullptr, env_.el.q, ne, 1, K, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_phi, (size_t)n * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out + n, s.d_E, (size_t)n * 3 * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);

@@ -133,13 +133,63 @@ def test_ragged_point_counts(cyl, n):
 def test_near_list_overflow_regrows(cyl):
     w, ref = cyl
     ctx = make_ctx(w)
-    ctx.set_near_capacity(8)
+    ctx.set_near_capacity(8, grow=True)
     phi, E, _ = run_gpu(ctx, w.points, "fp64")
     st = ctx.stats()
     ctx.close()
     assert st["near_capacity"] >= st["near_pairs"] > 8
     ep, ee = nerr(phi, E, ref)
     assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+def test_fixed_near_list_overflow_is_reported(cyl):
+    """A fixed near-pair list never makes the host wait; an evaluation that overflows it is
+    reported by stats() and, once it has finished, by the next call; a growing list then
+    gives the oracle's result."""
+    torch = torch_mod()
+    w, ref = cyl
+    ctx = make_ctx(w)
+    ctx.set_near_capacity(8)
+    pts = torch.tensor(np.ascontiguousarray(w.points.T), dtype=torch.float64, device="cuda:0")
+    _, _, rc = ctx.eval(pts)
+    assert rc == 0
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.stats()
+    assert ei.value.code == bemc.E_LIMIT and "near pairs" in str(ei.value)
+    ctx.eval(pts)
+    torch.cuda.synchronize()
+    with pytest.raises(bemc.BemcError) as ei:
+        ctx.eval(pts)
+    assert ei.value.code == bemc.E_LIMIT
+    ctx.set_near_capacity(8, grow=True)
+    phi, E, rc = run_gpu(ctx, w.points, "fp64")
+    st = ctx.stats()
+    ctx.close()
+    assert rc == 0 and st["near_capacity"] >= st["near_pairs"] == ref["stats"]["near_pairs"]
+    ep, ee = nerr(phi, E, ref)
+    assert ep.max() <= 1e-12 and ee.max() <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("near_dr", [2.0, 10.0])
+def test_other_near_thresholds(precision, near_dr):
+    """The distance-ratio switch at 2 (the smallest accepted: far sums expanded about the
+    centroid down to DR 2) and at 10, against the oracle with the same threshold."""
+    w = W.cylinder_workload(40, 30, 1200, n_points=1500, near_frac=0.3, seed=23)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7, near_dr=near_dr), with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.set_rules(33, 7, near_dr)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    phi, E, rc = run_gpu(ctx, w.points, precision)
+    st = ctx.stats()
+    with pytest.raises(bemc.BemcError):
+        ctx.set_rules(33, 7, 1.9)
+    ctx.close()
+    assert rc == 0 and st["near_pairs"] == ref["stats"]["near_pairs"] > 0
+    ep, ee = nerr(phi, E, ref)
+    print(f"near_dr {near_dr} {precision}: phi {ep.max():.2e} E {ee.max():.2e}, near pairs {st['near_pairs']}")
+    assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
 
 
 @pytest.mark.parametrize("tri_rule,gl", [(4, 2), (7, 3), (12, 5), (19, 7), (33, 8)])
@@ -167,7 +217,7 @@ def test_points_on_elements():
     phi, E, rc = run_gpu(ctx, pts, "fp64")
     st = ctx.stats()
     ctx.close()
-    assert rc == bemc.W_ON_SURFACE
+    assert rc == 0 and st["status"] == bemc.W_ON_SURFACE
     assert st["on_surface"] == ref["stats"]["on_surface"] >= 40
     ep, ee = nerr(phi, E, ref)
     assert ep.max() <= 1e-12 and ee.max() <= 1e-12
@@ -256,7 +306,7 @@ def test_results_are_reproducible_bit_for_bit(cyl, precision):
     ctx = make_ctx(w)
     a = run_gpu(ctx, w.points, precision)
     b = run_gpu(ctx, w.points, precision)
-    ctx.set_near_capacity(8)  # forces an overflow, a larger list and a repeated evaluation
+    ctx.set_near_capacity(8, grow=True)  # forces a larger list and a repeated list pass
     c = run_gpu(ctx, w.points, precision)
     assert ctx.stats()["near_pairs"] > 8
     for x, y in ((a, b), (a, c)):
