@@ -38,8 +38,10 @@ def serve(g, queries, precision, dr, alone, **cfg):
     if alone:
         infos = [ctx.server_wait(ctx.server_submit(q, p, e), 100.0) for q, p, e in zip(queries, phis, Es)]
     else:
-        ts = [ctx.server_submit(q, p, e) for q, p, e in zip(queries, phis, Es)]
-        infos = [ctx.server_wait(t, 100.0) for t in ts]
+        # the longest query first: while its batch runs, the others wait and are packed together
+        order = sorted(range(len(queries)), key=lambda i: -len(queries[i]))
+        ts = {i: ctx.server_submit(queries[i], phis[i], Es[i]) for i in order}
+        infos = [ctx.server_wait(ts[i], 100.0) for i in range(len(queries))]
     ctx.server_stop()
     ctx.close()
     assert all(i["done"] == 1 and i["status"] == 0 for i in infos)
@@ -50,12 +52,15 @@ def serve(g, queries, precision, dr, alone, **cfg):
                                               ("fp64", 1e-12, True), ("mixed", 1e-6, True)])
 def test_serving_full_geometry(big, precision, tol, dr):
     g, queries = big
-    cfg = dict(mem_budget_bytes=16 << 30, max_batch_points=1 << 16, n_streams=2, small_query_points=4096)
+    cfg = dict(mem_budget_bytes=16 << 30, max_batch_points=1 << 16)
     print(f"serving 1M elements: {precision} dr={dr} alone", flush=True)
-    pa, Ea, _ = serve(g, queries, precision, dr, alone=True, **cfg)
+    pa, Ea, _ = serve(g, queries, precision, dr, alone=True, n_streams=2, small_query_points=4096, **cfg)
     print(f"serving 1M elements: {precision} dr={dr} mix", flush=True)
-    pm, Em, im = serve(g, queries, precision, dr, alone=False, **cfg)
-    assert len({i["batch_id"] for i in im}) < len(queries)  # some queries shared a batch
+    # one stream: the queries after the 65,536-point one queue behind it and share a batch
+    pm, Em, im = serve(g, queries, precision, dr, alone=False, n_streams=1, small_query_points=0, **cfg)
+    longest = int(np.argmax([len(q) for q in queries]))
+    assert len({i["batch_id"] for k, i in enumerate(im) if k != longest}) == 1
+    assert im[longest]["batch_id"] not in {i["batch_id"] for k, i in enumerate(im) if k != longest}
     rng = np.random.default_rng(31)
     sel = [rng.choice(len(q), min(32, len(q)), replace=False) for q in queries]
     P = np.concatenate([q[s] for q, s in zip(queries, sel)])
