@@ -184,6 +184,25 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
 int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
               double* phi, double* E, void* stream);
 
+/* Allocation-free variant of bemc_eval, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and asynchronous behaviour as bemc_eval, but the call
+ * allocates nothing: its work buffers (point ordering, near-pair list and its regrouping,
+ * element-chunk partial sums, counters) are carved from a static device array of 64 MiB
+ * that each GPU the library runs on holds from the first context created on it until the
+ * process ends.  Limits: n <= 65536 field points per call (larger n returns BEMC_E_LIMIT
+ * at once) and 524288 near pairs (D < near_dr L) per call; more near pairs leave the near
+ * field incomplete and are reported, as for a fixed list of bemc_set_near_capacity, by
+ * bemc_query_stats and the next evaluation call (BEMC_E_LIMIT).  The element-chunk split
+ * of the far field is capped by the array (results then differ from bemc_eval's in
+ * summation grouping only, at rounding level).  All contexts on one GPU share that GPU's
+ * array, which keeps the last call's contents: calls on one context are ordered (each
+ * waits on the device for the previous one), but calls from different contexts on one
+ * GPU that overlap on the device race -- the caller serialises them (one stream, or
+ * events).  Errors: as bemc_eval; DEVICE when the array's address could not be taken. */
+int bemc_eval_noalloc(bemc_handle h, const double* pts, int64_t n, int precision, int rhs,
+                      double* phi, double* E, void* stream);
+
 /* Field gradient dE_i/dx_j (V/m^2, symmetric and trace-free off the electrodes) at the n
  * field points pts[3][n] (device): G[6][n] (device, overwritten) holds the rows xx, yy, zz,
  * xy, xz, yz.  The derivative of the point-charge sums of Eq. (4.1): each Gaussian point

@@ -37,7 +37,7 @@ EXPORTED = ["bemc_last_error", "bemc_create", "bemc_destroy", "bemc_set_rules", 
             "bemc_upload_densities", "bemc_eval", "bemc_eval_gradient", "bemc_collocation_matvec", "bemc_query_stats",
             "bemc_server_start", "bemc_server_submit", "bemc_server_poll", "bemc_server_wait",
             "bemc_server_stop", "bemc_coulomb_constant", "bemc_rule_size", "bemc_set_near_capacity",
-            "bemc_set_dr_rules", "bemc_solve_densities"]
+            "bemc_set_dr_rules", "bemc_solve_densities", "bemc_eval_noalloc"]
 
 
 class BemcError(RuntimeError):
@@ -96,6 +96,7 @@ def load_library():
     lib.bemc_upload_geometry.argtypes = [vp, vp, i64, vp, i64, vp]
     lib.bemc_upload_densities.argtypes = [vp, vp, ci, ci, vp]
     lib.bemc_eval.argtypes = [vp, vp, i64, ci, ci, vp, vp, vp]
+    lib.bemc_eval_noalloc.argtypes = [vp, vp, i64, ci, ci, vp, vp, vp]
     lib.bemc_eval_gradient.argtypes = [vp, vp, i64, ci, ci, vp, vp]
     lib.bemc_collocation_matvec.argtypes = [vp, vp, ci, ci, vp, vp]
     lib.bemc_query_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -224,6 +225,15 @@ class Context:
                                 _dev_f64(E, (3, n)) if with_E else None, _stream_ptr())
         _check(rc, allow_warning=True)
         return phi, (E if with_E else None), rc
+
+    def eval_noalloc(self, pts, phi, E=None, precision="fp64", rhs=0):
+        """bemc_eval_noalloc: as eval() into caller-provided phi [n] (and E [3, n]); the library
+        allocates nothing (n <= 65536).  Returns the status of the call."""
+        n = pts.shape[1]
+        rc = self.lib.bemc_eval_noalloc(self.h, _dev_f64(pts, (3, n)), n, _PREC[precision], rhs, _dev_f64(phi, (n,)),
+                                        None if E is None else _dev_f64(E, (3, n)), _stream_ptr())
+        _check(rc, allow_warning=True)
+        return rc
 
     def eval_gradient(self, pts, precision="fp64", rhs=0, G=None):
         """pts: float64 CUDA tensor [3, n].  Returns (G [6, n] rows xx yy zz xy xz yz, status of

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbemc.so")
-SOURCES = ["kernels.hip", "order.hip", "near_order.hip", "api.cpp", "server.cpp", "solver.cpp", "rules.cpp"]
+SOURCES = ["kernels.hip", "order.hip", "near_order.hip", "noalloc.hip", "api.cpp", "server.cpp", "solver.cpp", "rules.cpp"]
 ARCH = os.environ.get("BEMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -77,6 +78,85 @@ struct EvalWork {
     size_t partial_cap = 0;  // doubles
     DevCounters* ctr = nullptr;
 };
+
+namespace {
+// Buffers of the allocation-free entry point, one set per device, carved from that device's
+// static scratch array (noalloc.hip) when the first context on the device is created.
+// Nothing is allocated: the set only holds addresses inside the array.
+struct NoAllocSet {
+    bool tried = false;
+    int status = BEMC_OK;
+    std::string msg;
+    EvalWork w{};
+};
+std::mutex g_noalloc_mu;
+NoAllocSet g_noalloc[kNoAllocMaxDevices];
+
+// `device` must be current.  Returns BEMC_OK and the device's set, or the set-up error.
+int noalloc_set(int device, NoAllocSet** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kNoAllocMaxDevices) return BEMC_E_LIMIT;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocSet& S = g_noalloc[device];
+    *out = &S;
+    if (S.tried) return S.status;
+    S.tried = true;
+    void* base = nullptr;
+    const hipError_t e = noalloc_scratch(device, &base);
+    if (e != hipSuccess) {
+        S.status = BEMC_E_DEVICE;
+        S.msg = std::string("address of the allocation-free workspace: ") + hipGetErrorString(e);
+        return S.status;
+    }
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + 255) & ~size_t(255);
+        void* q = p + off;
+        off += bytes;
+        return q;
+    };
+    const size_t P = (size_t)kNoAllocMaxPoints, C = (size_t)kNoAllocMaxNearPairs;
+    EvalWork& W = S.w;
+    W.ctr = static_cast<DevCounters*>(take(sizeof(DevCounters)));
+    W.ow.keys_in = static_cast<uint32_t*>(take(P * 4));
+    W.ow.keys_out = static_cast<uint32_t*>(take(P * 4));
+    W.ow.idx_in = static_cast<uint32_t*>(take(P * 4));
+    W.ow.perm = static_cast<uint32_t*>(take(P * 4));
+    W.ow.temp = take(kNoAllocTempBytes);
+    W.ow.temp_bytes = kNoAllocTempBytes;
+    W.ow.bbox = static_cast<double*>(take(6 * 1024 * 8));
+    W.ow.pts = static_cast<double*>(take(3 * P * 8));
+    W.ow.res = static_cast<double*>(take(4 * P * 8));  // phi and the three field rows
+    W.ow_cap = (int64_t)P;
+    W.near = static_cast<NearPair*>(take(C * sizeof(NearPair)));
+    W.near_cap = C;
+    W.nw.count = static_cast<uint32_t*>(take(P * 4));
+    W.nw.start = static_cast<uint32_t*>(take(P * 4));
+    W.nw.cursor = static_cast<uint32_t*>(take(P * 4));
+    W.nw.grouped = static_cast<NearPair*>(take(C * sizeof(NearPair)));
+    W.nw.origin = static_cast<uint32_t*>(take(C * 4));
+    W.nw.sorted = static_cast<NearPair*>(take(C * sizeof(NearPair)));
+    W.nw.slot = static_cast<uint32_t*>(take(C * 4));
+    W.nw.res = static_cast<double*>(take(C * 4 * 8));
+    W.nw.temp = take(kNoAllocTempBytes);
+    W.nw.temp_bytes = kNoAllocTempBytes;
+    W.nw_pts = (int64_t)P;
+    W.nw_pairs = C;
+    W.nw_rows = 4;
+    W.partial = static_cast<double*>(take(kNoAllocPartialDoubles * 8));
+    W.partial_cap = kNoAllocPartialDoubles;
+    if (off > kNoAllocScratchBytes || order_temp_bytes((int64_t)P) > kNoAllocTempBytes ||
+        near_scan_temp_bytes((int64_t)P) > kNoAllocTempBytes) {
+        S.status = BEMC_E_LIMIT;
+        S.msg = "the allocation-free workspace layout does not fit its array";
+        W = EvalWork{};
+        return S.status;
+    }
+    return BEMC_OK;
+}
+}  // namespace
 
 // Record of one enqueued evaluation: pinned copies of its counters and its events.  A
 // small ring of them lets evaluations be in flight while the host goes on.
@@ -408,9 +488,9 @@ int bemc_context::drain()
 //   counters to pinned host memory.
 // Growing list (default): the host reads the list pass's pair count after the far field is
 // enqueued and, if the list was too short, grows it and repeats the list pass (never the
-// far field), then enqueues the near field and returns.  Fixed list: no host wait at all; an
-// overflow is reported by bemc_query_stats and the next call.  Allocation-free: the list
-// count is read before the far field is enqueued, and an overflow is an error.
+// far field), then enqueues the near field and returns.  Fixed list, and the buffers of the
+// allocation-free entry point: no host wait at all; an overflow is reported by
+// bemc_query_stats and the next call.
 int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int rhs, int n_rhs_colloc, double* phi,
                       double* E, hipStream_t s, EvalWork& W, bool noalloc)
 {
@@ -476,16 +556,10 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     const double* lpts = colloc ? d_cen : pts;
     HIP_TRY(launch_zero_counters(W.ctr, s));
     HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
-    const bool read_count = near_grow || noalloc;
+    const bool read_count = near_grow && !noalloc;
     if (read_count) {
         HIP_TRY(hipMemcpyAsync(R.h_list, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(R.ev_list, s));
-    }
-    if (noalloc) {
-        HIP_TRY(hipEventSynchronize(R.ev_list));
-        if (R.h_list->near_count > W.near_cap)
-            return fail(BEMC_E_LIMIT, "%llu near pairs exceed the %llu of the fixed scratch buffer",
-                        R.h_list->near_count, W.near_cap);
     }
 
     FarArgs fa{};
@@ -574,6 +648,8 @@ int bemc_create(int device, bemc_handle* out)
     if (hipSetDevice(device) != hipSuccess) { delete h; return fail(BEMC_E_DEVICE, "hipSetDevice(%d)", device); }
     int rc = h->set_rules_tables();
     if (rc) { bemc_destroy(h); return rc; }
+    NoAllocSet* na = nullptr;
+    (void)noalloc_set(device, &na);  // once per device; a failure is reported by bemc_eval_noalloc
     if (dev_alloc(&h->w.ctr, 1) != hipSuccess) {
         bemc_destroy(h);
         return fail(BEMC_E_OUT_OF_MEMORY, "counter buffers");
@@ -823,6 +899,28 @@ int bemc_eval(bemc_handle h, const double* pts, int64_t n, int precision, int rh
     if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
     if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
     return h->run(kNearEval, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream), h->w, false);
+}
+
+int bemc_eval_noalloc(bemc_handle h, const double* pts, int64_t n, int precision, int rhs, double* phi, double* E,
+                      void* stream)
+{
+    if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
+    if (!h->have_geometry || h->n_rhs == 0) return fail(BEMC_E_NO_GEOMETRY, "geometry and densities must be uploaded");
+    if (n < 0) return fail(BEMC_E_INVALID_ARG, "n < 0");
+    if (n == 0) return ok();
+    if (n > kNoAllocMaxPoints)
+        return fail(BEMC_E_LIMIT, "%lld points exceed the %lld of the allocation-free workspace", (long long)n,
+                    (long long)kNoAllocMaxPoints);
+    if (!pts || !phi) return fail(BEMC_E_INVALID_ARG, "null point or output pointer");
+    if (precision != BEMC_FP64 && precision != BEMC_MIXED) return fail(BEMC_E_INVALID_ARG, "precision %d", precision);
+    if (rhs < 0 || rhs >= h->n_rhs) return fail(BEMC_E_INVALID_ARG, "rhs %d of %d", rhs, h->n_rhs);
+    HIP_TRY(hipSetDevice(h->device));
+    NoAllocSet* S = nullptr;
+    const int rc = noalloc_set(h->device, &S);
+    if (rc) return fail(rc, "%s", S ? S->msg.c_str() : "device index out of range");
+    if (order_temp_bytes(n) > S->w.ow.temp_bytes || near_scan_temp_bytes(n) > S->w.nw.temp_bytes)
+        return fail(BEMC_E_LIMIT, "sort workspace for %lld points exceeds the allocation-free workspace", (long long)n);
+    return h->run(kNearEval, pts, n, precision, rhs, 1, phi, E, reinterpret_cast<hipStream_t>(stream), S->w, true);
 }
 
 int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precision, int rhs, double* G, void* stream)

@@ -188,6 +188,18 @@ hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, doub
                        double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
 constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 
+// Allocation-free evaluation (noalloc.hip): a static device array per GPU, carved into the
+// buffers of one field evaluation of at most kNoAllocMaxPoints points and
+// kNoAllocMaxNearPairs near pairs.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int64_t kNoAllocMaxPoints = 1 << 16;
+constexpr unsigned long long kNoAllocMaxNearPairs = 1ull << 19;
+constexpr size_t kNoAllocPartialDoubles = size_t(2) << 20;  // element-chunk partial sums (16 MiB)
+constexpr size_t kNoAllocTempBytes = size_t(2) << 20;       // each of the sort and scan workspaces
+constexpr int kNoAllocMaxDevices = 64;
+// device address of this GPU's array (device current); taken once per device and kept
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // Morton ordering of field points (order.hip).  Buffers sized for n points.
 struct OrderWork {
     uint32_t *keys_in, *keys_out, *idx_in, *perm;
