@@ -436,6 +436,68 @@ def test_dr_rules_custom_limits_and_rules(precision):
     assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
 
 
+def band_points(centre, L, dr, n, rng):
+    """n points at distance dr * L from `centre`, isotropic directions."""
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return centre + dr * L * v
+
+
+@pytest.mark.parametrize("kind", ["tri", "rect"])
+def test_dr_rules_single_level_bands(kind):
+    """One element; each evaluation holds only points just above or just below one of the
+    level limits (distance ratio limit * (1 +- 1e-6)), so every wavefront needs exactly one
+    level: the executed terms are n x that level's node count, the per-pair count equals
+    them, and the result equals the oracle's per-pair choice to 1e-14 (plain relative
+    error: one positive element, no cancellation)."""
+    torch = torch_mod()
+    rng = np.random.default_rng(2024)
+    if kind == "tri":
+        tri = np.array([[0.1, -0.2, 0.05, 1.3, 0.1, -0.1, 0.4, 1.1, 0.3]])
+        rect = np.zeros((0, 9))
+        a, b, c = (np.linalg.norm(tri[0, 3:6] - tri[0, 0:3]), np.linalg.norm(tri[0, 6:9] - tri[0, 3:6]),
+                   np.linalg.norm(tri[0, 0:3] - tri[0, 6:9]))
+        L = (a + b + c) / 3.0
+        centre = (tri[0, 0:3] + tri[0, 3:6] + tri[0, 6:9]) / 3.0
+        limits, nodes = (100.0, 25.0, 10.0, 3.0), (7, 12, 19, 33)
+    else:
+        tri = np.zeros((0, 9))
+        e1, e2 = np.array([0.8, 0.3, 0.0]), np.array([-0.3 * 0.5, 0.8 * 0.5, 0.7])
+        e2 -= e1 * (e1 @ e2) / (e1 @ e1)
+        rect = np.concatenate([[0.2, 0.1, -0.3], e1, e2])[None, :]
+        L = 0.5 * (np.linalg.norm(e1) + np.linalg.norm(e2))
+        centre = rect[0, 0:3] + 0.5 * e1 + 0.5 * e2
+        limits, nodes = (150.0, 40.0, 15.0, 3.0), (7, 12, 17, 49)
+    sigma = np.array([[0.7]])
+    ctx = bemc.Context(0)
+    ctx.set_rules(33, 7)
+    ctx.set_dr_rules(True)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(sigma)
+    n = 320
+    prm = oracle.params(33, 7, dr_rules=True)
+    for lvl, lim in enumerate(limits):
+        # just above the limit: this level; just below: the next finer one (none below DR 3)
+        cases = [(lim * (1 + 1e-6), nodes[lvl])]
+        if lvl < 3:
+            cases.append((lim * (1 - 1e-6), nodes[lvl + 1]))
+        for dr, want in cases:
+            P = band_points(centre, L, dr, n, rng)
+            for precision in ("fp64", "mixed"):
+                phi, E, _ = run_gpu(ctx, P, precision)
+                st = ctx.stats()
+                assert st["near_pairs"] == 0
+                assert st["node_interactions"] == n * want, (kind, dr, st["node_interactions"], n * want)
+                assert st["node_interactions_pair_rule"] == n * want
+                if precision == "fp64":
+                    ref = oracle.evaluate(tri, rect, sigma[0], P, prm, with_abs=True)
+                    rp = np.abs(phi - ref["phi"]) / np.abs(ref["phi"])
+                    re = np.linalg.norm(E - ref["E"], axis=1) / np.linalg.norm(ref["E"], axis=1)
+                    print(f"band {kind} DR {dr:.6g}: {want} nodes, phi {rp.max():.1e} E {re.max():.1e}")
+                    assert rp.max() <= 1e-14 and re.max() <= 1e-14
+    ctx.close()
+
+
 @pytest.mark.parametrize("table", [4, 7, 12, 17, 33])
 def test_rectangle_table_rules(table):
     w = W.cylinder_workload(40, 30, 1200, n_points=600, near_frac=0.3, seed=17)
