@@ -33,8 +33,10 @@ FLOP_PER_NODE_INT = 20    # Phi + E per point-charge term
 FLOP_PER_PAIR = 16        # distance-ratio test + charge scaling per element-point pair
 GRAD_FLOP_PER_NODE_INT = 30  # field gradient (six components) per point-charge term
 COLLOC_FLOP_PER_NODE_INT = 11  # potential only (collocation product) per point-charge term
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_hbm.txt")
-VALU_FILE = os.path.join(ROOT, "profiles", "far_eval_fp64_cylinder150k_valu.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_counters_cylinder150k_nested200k.txt")
+VALU_FILE = os.path.join(PROFILES, "valu_counters_cylinder150k_nested200k.txt")
+TRACE_FILE = os.path.join(PROFILES, "kernel_trace_cylinder150k_nested200k.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
 
 
@@ -46,31 +48,54 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per far-kernel launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def profile_value(path, key):
+    """A figure of a committed rocprofv3 summary, or None when the file is missing or the
+    kernel source changed since the profile was taken."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(r"^" + re.escape(key) + r":\s*([0-9.eE+-]+)", txt, re.M)
     if not m or not b or m.group(1) != kernel_hash():
         return None
     return float(b.group(1))
 
 
-def counted_flops_from_profile(key="counted_fp64_flops_per_launch"):
-    """Hardware flops per far-kernel launch from the committed VALU counter summary
-    (64 x (2 FMA + MUL + ADD + TRANS) of the FP64 kernel's FP64 instructions, or of the
-    mixed kernel's FP32 instructions), or None when the kernel changed since."""
-    if not os.path.exists(VALU_FILE):
+def traffic_from_profile(kernel="far_fp64"):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated by a 1 GiB copy)."""
+    return profile_value(TRAFFIC_FILE, f"{kernel}_hbm_bytes_per_launch")
+
+
+def counted_flops_from_profile(kernel="far_fp64"):
+    """Hardware flops per launch: 64 x (2 FMA + MUL + ADD + TRANS) of the kernel's FP64
+    instructions (FP32 for the mixed kernels)."""
+    sfx = "f32" if kernel.endswith("mixed") else "f64"
+    return profile_value(VALU_FILE, f"{kernel}_counted_{sfx}_flops_per_launch")
+
+
+def trace_avg_ms(prefix):
+    """Average duration of a kernel in the committed kernel trace (None if stale)."""
+    if not os.path.exists(TRACE_FILE):
         return None
-    txt = open(VALU_FILE).read()
+    txt = open(TRACE_FILE).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    b = re.search(key + r":\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_hash():
+    if not m or m.group(1) != kernel_hash():
         return None
-    return float(b.group(1))
+    for line in txt.splitlines():
+        if line.startswith(prefix):
+            return float(line[86:].split()[1])
+    return None
+
+
+def profiled(kernel, flops, far_ms, peak):
+    """Counted flops and HBM traffic of a kernel from the committed profiles, per launch,
+    over this run's launch time."""
+    c = counted_flops_from_profile(kernel)
+    t = traffic_from_profile(kernel)
+    s = 1e-3 * far_ms
+    return {"counted_tflops": None if c is None else c / s / 1e12,
+            "counted_frac": None if c is None else c / s / 1e12 / peak,
+            "traffic": t, "hbm_gbps": None if t is None else t / s / 1e9}
 
 
 def nerr(phi, E, ref):
@@ -210,8 +235,9 @@ def main():
     alg_flops = FLOP_PER_NODE_INT * node_int + FLOP_PER_PAIR * pairs
     far_avg_s = 1e-3 * float(np.mean(far64))
     achieved = alg_flops / far_avg_s / 1e12
-    traffic = traffic_from_profile()
-    counted = counted_flops_from_profile()
+    traffic = traffic_from_profile("far_fp64")
+    counted = counted_flops_from_profile("far_fp64")
+    prof_ms = trace_avg_ms("far_eval_kernel<false, 33, 49, 0, 0, 0, 0, 0, 0, false, 3, false>")
     out = {
         "metric": "element-fieldpoint interactions/s (phi+E) FP64 vs mixed @1e-6; p99 query ms",
         "value": value,
@@ -234,15 +260,27 @@ def main():
                      "counted_fp64_tflops": None if counted is None else counted / far_avg_s / 1e12,
                      "counted_frac": None if counted is None else counted / far_avg_s / 1e12 / PEAK_FP64_TFLOPS,
                      "hbm_gbps": None if traffic is None else traffic / far_avg_s / 1e9,
-                     "hbm_frac": None if traffic is None else traffic / far_avg_s / 1e9 / PEAK_HBM_GBPS},
+                     "hbm_frac": None if traffic is None else traffic / far_avg_s / 1e9 / PEAK_HBM_GBPS,
+                     "rocprof_avg_launch_ms": prof_ms,
+                     "rocprof_frac": None if prof_ms is None else alg_flops / (1e-3 * prof_ms) / 1e12 / PEAK_FP64_TFLOPS,
+                     "note": "achieved: algorithmic flops (20 per node interaction + 16 per pair) over the far "
+                             "kernel's mean HIP-event time in this run; rocprof_frac: the same over the committed "
+                             "kernel trace's average (profiling box)"},
         "node_interactions_per_s": node_int * args.steps / dt64,
         "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
-                 "cap_hits": st64["cap_hits"], "kernel_ms": st64["near_ms"]},
+                 "cap_hits": st64["cap_hits"], "stage_ms": st64["near_ms"],
+                 "near_kernel_rocprof_ms": trace_avg_ms("near_kernel<0>"),
+                 "near_list_kernel_rocprof_ms": trace_avg_ms("near_list_kernel"),
+                 "near_kernel_write_bytes": profile_value(TRAFFIC_FILE, "near_field_write_bytes_per_launch"),
+                 "near_kernel_read_bytes": profile_value(TRAFFIC_FILE, "near_field_read_bytes_per_launch"),
+                 "result_bytes": 32 * st64["near_pairs"],
+                 "note": "stage_ms: chunk reduction, near-list regrouping, near kernel and ordered sums (HIP "
+                         "events); the near-pair list pass runs before the far kernel"},
         "upload": {"elements": w.n_elements, "geometry_s": t_geom, "densities_s": t_dens,
                    "note": "host arrays: validation, centroids, frames, charges, copies to the device"},
     }
     mixed_ach = alg_flops / (1e-3 * float(np.mean(farmx))) / 1e12
-    counted32 = counted_flops_from_profile("counted_fp32_flops_per_launch_mixed")
+    counted32 = counted_flops_from_profile("far_mixed")
     c32 = None if counted32 is None else counted32 / (1e-3 * float(np.mean(farmx))) / 1e12
     out["mixed"] = {"value": pairs * side / dtmx, "unit": "pairs/s", "ms_per_step": 1e3 * dtmx / side,
                     "speedup_vs_fp64": (dt64 / args.steps) / (dtmx / side), "far_kernel_ms": float(np.mean(farmx)),
@@ -267,6 +305,7 @@ def main():
                        "node_interactions_fixed_rules": node_int,
                        "roofline": {"bound": "alu", "achieved": dr_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                     "frac": dr_ach / PEAK_FP64_TFLOPS,
+                                    **profiled("far_dr_fp64", dr_flops, float(np.mean(fardr)), PEAK_FP64_TFLOPS),
                                     "note": "20 flops per executed node interaction + 16 per pair"},
                        "mixed_value": pairs * side / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
                        "rules": "triangles 7/12/19/33 points for DR >= 100/25/10/3, rectangles Tables B2/B3/B4 "
@@ -365,6 +404,7 @@ def main():
                             "node_interactions": st["node_interactions"],
                             "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                                          "frac": ach / peak,
+                                         **profiled("colloc_" + prec, cflops, st["far_ms"], peak),
                                          "note": "11 flops per node interaction + 2 per pair and density"}}
         rows = np.random.default_rng(3).choice(wc.n_elements, 64, replace=False)
         cref = oracle.collocation(wc.tri, wc.rect, wc.sigma, rows=rows)
