@@ -276,11 +276,18 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
  * bemc_server_start launches a host scheduler thread that owns `n_streams` HIP streams
  * (default priority).  Submitted queries wait in arrival order; whenever a stream is
  * free the scheduler admits waiting queries in order while their points fit into
- * max_batch_points and the device memory budget, packs them into one batch (one far-
- * field launch over all their points, element-split when the batch is small so the GPU
- * stays full; fixed-order reduction of the element chunks; then the FP64 near field)
- * and copies each query's results to its host buffers when the batch completes.
- * Batches on different streams overlap on the device.  With small_query_points > 0 and
+ * max_batch_points and their batch's device memory fits what the budget has left, packs
+ * them into one batch (one far-field launch over all their points, element-split when
+ * the batch is small so the GPU stays full; fixed-order reduction of the element chunks;
+ * then the FP64 near field) and copies each query's results to its host buffers when the
+ * batch completes.  Batches on different streams overlap on the device.  Each batch
+ * allocates its device buffers on its own stream when admitted (stream-ordered, from the
+ * device's memory pool) and releases them when it completes; the scheduler accounts
+ * them against mem_budget_bytes.  A batch's near-pair list starts at 16 pairs per point;
+ * when its list pass finds more, the list grows on the batch's stream before the near
+ * field (the far field is not repeated, no other stream waits).  A growth that does not
+ * fit the budget waits while another batch is in its near stage; otherwise it proceeds,
+ * so at most one batch at a time exceeds the budget, by its own growth.  With small_query_points > 0 and
  * at least two streams, queries of at most that many points wait in a queue of their
  * own, and one stream serves only that queue, so that short queries do not wait behind
  * long batches; the other streams take the long queue first and the short one when the
@@ -291,7 +298,8 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
  * --------------------------------------------------------------------------------- */
 
 typedef struct {
-    size_t mem_budget_bytes;   /* device bytes for in-flight batch buffers */
+    size_t mem_budget_bytes;   /* device bytes for in-flight batch buffers (at least one
+                                  batch of max_batch_points: else INVALID_ARG) */
     int64_t max_batch_points;  /* points per batch (>= the largest admissible query) */
     int n_streams;             /* 1..8 concurrent batches */
     int precision;             /* BEMC_FP64 or BEMC_MIXED */

@@ -124,6 +124,7 @@ struct NearArgs {
     const NearPair* near_list;   // as the far kernel appended it
     unsigned long long near_cap;
     const uint32_t* slot;        // result slot of each list entry
+    const uint32_t* order;       // list indices in the order the lanes take them (costly first)
     double* res;                 // per-pair result records at the pairs' slots: [slot][4] field,
                                  // [slot][6] gradient, [slot] collocation
     DevCounters* ctr;
@@ -174,15 +175,27 @@ struct NearWork {
     NearPair* sorted;                  // [capacity] pairs in (point, element) order
     uint32_t* slot;                    // [capacity] result slot (sorted position) of each list index
     double* res;                       // [capacity][rows] per-pair result records of the near kernel
+    uint8_t* cost;                     // [capacity] cost class of each list index (near_cost_order)
+    uint32_t* order;                   // [capacity] list indices, most expensive pairs first
+    uint32_t* buckets;                 // [3][kCostClasses] count, start, cursor of each cost class
     void* temp;                        // scan workspace
     size_t temp_bytes;
 };
+// cost classes of near pairs: 128 classes of the estimated subdivision depth x 2 element kinds
+constexpr int kCostClasses = 256;
+constexpr size_t kNearWorkBytesPerPair = 2 * sizeof(NearPair) + 3 * sizeof(uint32_t) + 1;  // + rows x 8
 size_t near_scan_temp_bytes(int64_t n);
 hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int rows);  // frees w first
 void near_work_free(NearWork& w);
-// regroup the list (length read from ctr) into per-point segments sorted by element
+// stream-ordered allocation and release of one batch's buffers (w empty before the allocation)
+hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipStream_t s);
+void near_work_free_async(NearWork& w, hipStream_t s);
+size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows);  // device bytes of those buffers
+// regroup the list (length read from ctr) into per-point segments sorted by element, and
+// order the list indices by estimated subdivision cost (w.order) for the near kernel;
+// pts [3][n] are the field points of the list (the centroids for collocation)
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
-                      const NearWork& w, hipStream_t s);
+                      const double* pts, const Elements& el, const NearWork& w, hipStream_t s);
 // add each point's segment of per-pair result records to its outputs
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
                        double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);

@@ -9,6 +9,13 @@
 // then adds its segment in element order to the point's far-field result.  The outcome
 // does not depend on how the GPU scheduled the work.  No step needs the pair count on the
 // host: the kernels read it from the device counters.
+//
+// The near kernel's lanes take pairs from a shared cursor, most expensive first: a pair's
+// subdivision has a number of leaves that grows with log2(L / d), d the distance from the
+// point to the element (from a few leaves at distance ratio 3 to thousands a thousandth of
+// L above the element).  The list indices are bucketed by an estimate of that depth
+// (counting sort over cost classes, order within a class arbitrary), so the lanes of a
+// wavefront walk trees of similar size and the long walks start first.
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"
@@ -109,6 +116,114 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
     }
 }
 
+// Cost class of a near pair (higher = more subdivision leaves expected): 4 classes per
+// octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the element's
+// plane, rho the in-plane distance from the centroid, R the distance of the farthest
+// vertex from it), times 2 for the element kind.  A point on the element (d = 0: the polar
+// integral, no subdivision) takes the cheapest class.
+__device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_t n, const Elements& el, NearPair pr)
+{
+    const int64_t ne = el.ne, e = pr.elem, p = pr.point;
+    const double dx = pts[p] - el.cen[e], dy = pts[n + p] - el.cen[ne + e], dz = pts[2 * n + p] - el.cen[2 * ne + e];
+    const double h = fabs(dx * el.nrm[e] + dy * el.nrm[ne + e] + dz * el.nrm[2 * ne + e]);
+    const double rho = sqrt(fmax(fma(dx, dx, fma(dy, dy, dz * dz)) - h * h, 0.0));
+    const bool tri = e < el.n_tri;
+    double R2 = 0.0;
+    if (tri) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double vx = el.geom[(3 * m) * ne + e] - el.cen[e];
+            const double vy = el.geom[(3 * m + 1) * ne + e] - el.cen[ne + e];
+            const double vz = el.geom[(3 * m + 2) * ne + e] - el.cen[2 * ne + e];
+            R2 = fmax(R2, fma(vx, vx, fma(vy, vy, vz * vz)));
+        }
+    } else {  // half diagonal
+        const double vx = el.geom[3 * ne + e] + el.geom[6 * ne + e], vy = el.geom[4 * ne + e] + el.geom[7 * ne + e],
+                     vz = el.geom[5 * ne + e] + el.geom[8 * ne + e];
+        R2 = 0.25 * fma(vx, vx, fma(vy, vy, vz * vz));
+    }
+    const double out = fmax(rho - sqrt(R2), 0.0);
+    const double d2 = fma(out, out, h * h);
+    const double L = el.L[e];
+    int c = 0;
+    if (d2 > 1e-24 * L * L) c = min(127, max(1, (int)floor(4.0 * (log2(L) - 0.5 * log2(d2)) + 16.0)));
+    return 2 * c + (tri ? 0 : 1);
+}
+
+// Per-class counts (per-workgroup histograms in LDS, one global atomic per class and
+// workgroup) and the class of every list index.
+__global__ void cost_count_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
+                                  unsigned long long cap, const double* __restrict__ pts, int64_t n, Elements el,
+                                  uint8_t* __restrict__ cost, uint32_t* __restrict__ count)
+{
+    __shared__ uint32_t hist[kCostClasses];
+    hist[threadIdx.x] = 0u;  // kBlock == kCostClasses
+    __syncthreads();
+    const unsigned long long total = pair_total(ctr, cap);
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (unsigned long long)gridDim.x * kBlock) {
+        const int c = cost_class(pts, n, el, list[i]);
+        cost[i] = (uint8_t)c;
+        atomicAdd(&hist[c], 1u);
+    }
+    __syncthreads();
+    if (hist[threadIdx.x]) atomicAdd(&count[threadIdx.x], hist[threadIdx.x]);
+}
+
+// Start of each class in the order, most expensive class first (one workgroup); cursors
+// cleared.
+__global__ void cost_scan_kernel(uint32_t* __restrict__ buckets)
+{
+    __shared__ uint32_t cnt[kCostClasses];
+    const int c = threadIdx.x;
+    cnt[c] = buckets[c];
+    __syncthreads();
+    uint32_t start = 0;
+    for (int k = kCostClasses - 1; k > c; --k) start += cnt[k];
+    buckets[kCostClasses + c] = start;
+    buckets[2 * kCostClasses + c] = 0u;
+}
+
+// order[start[class] + rank] = list index; ranks within a workgroup's chunk from LDS
+// atomics, one global atomic per class and chunk.
+constexpr int kCostItems = 8;  // list entries per thread and chunk
+__global__ void cost_scatter_kernel(const DevCounters* __restrict__ ctr, unsigned long long cap,
+                                    const uint8_t* __restrict__ cost, uint32_t* __restrict__ buckets,
+                                    uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t hist[kCostClasses], base[kCostClasses];
+    const unsigned long long total = pair_total(ctr, cap);
+    const unsigned long long chunk = (unsigned long long)kBlock * kCostItems;
+    for (unsigned long long c0 = (unsigned long long)blockIdx.x * chunk; c0 < total;
+         c0 += (unsigned long long)gridDim.x * chunk) {
+        hist[threadIdx.x] = 0u;
+        __syncthreads();
+        int cls[kCostItems];
+        uint32_t rank[kCostItems];
+#pragma unroll
+        for (int k = 0; k < kCostItems; ++k) {
+            const unsigned long long i = c0 + (unsigned long long)k * kBlock + threadIdx.x;
+            cls[k] = -1;
+            if (i < total) {
+                cls[k] = cost[i];
+                rank[k] = atomicAdd(&hist[cls[k]], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = hist[threadIdx.x];
+        base[threadIdx.x] = cnt ? buckets[kCostClasses + threadIdx.x] +
+                                      atomicAdd(&buckets[2 * kCostClasses + threadIdx.x], cnt)
+                                : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCostItems; ++k) {
+            const unsigned long long i = c0 + (unsigned long long)k * kBlock + threadIdx.x;
+            if (cls[k] >= 0) order[base[cls[k]] + rank[k]] = (uint32_t)i;
+        }
+        __syncthreads();
+    }
+}
+
 unsigned grid_for(int64_t n)
 {
     const int64_t b = (n + kBlock - 1) / kBlock;
@@ -120,7 +235,8 @@ unsigned grid_for(int64_t n)
 void near_work_free(NearWork& w)
 {
     for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
-                       (void*)w.sorted, (void*)w.slot, (void*)w.res, w.temp })
+                       (void*)w.sorted, (void*)w.slot, (void*)w.res, (void*)w.cost, (void*)w.order,
+                       (void*)w.buckets, w.temp })
         if (ptr) (void)hipFree(ptr);
     w = NearWork{};
 }
@@ -138,11 +254,58 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.cost), npairs);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&w.temp, std::max<size_t>(w.temp_bytes, 1));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         const size_t tb = w.temp_bytes;
         near_work_free(w);
+        w.temp_bytes = tb;
+    }
+    return e;
+}
+
+// Stream-ordered variants (serving: buffers of one batch, allocated and released on the
+// batch's stream without waiting for other streams).
+void near_work_free_async(NearWork& w, hipStream_t s)
+{
+    for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
+                       (void*)w.sorted, (void*)w.slot, (void*)w.res, (void*)w.cost, (void*)w.order,
+                       (void*)w.buckets, w.temp })
+        if (ptr) (void)hipFreeAsync(ptr, s);
+    w = NearWork{};
+}
+
+size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows)
+{
+    const size_t np = (size_t)std::max<int64_t>(n, 1), npairs = (size_t)std::max<unsigned long long>(pairs, 1);
+    return np * 3 * sizeof(uint32_t) + npairs * (kNearWorkBytesPerPair + (size_t)rows * sizeof(double)) +
+           3 * kCostClasses * sizeof(uint32_t) + near_scan_temp_bytes(std::max<int64_t>(n, 1));
+}
+
+hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipStream_t s)
+{
+    w = NearWork{};
+    const size_t np = (size_t)std::max<int64_t>(n, 1), npairs = (size_t)std::max<unsigned long long>(pairs, 1);
+    w.temp_bytes = near_scan_temp_bytes(std::max<int64_t>(n, 1));
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&w.count), np * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.start), np * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.cursor), np * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.grouped), npairs * sizeof(NearPair), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.origin), npairs * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.cost), npairs, s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMallocAsync(&w.temp, std::max<size_t>(w.temp_bytes, 1), s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        const size_t tb = w.temp_bytes;
+        near_work_free_async(w, s);
         w.temp_bytes = tb;
     }
     return e;
@@ -156,9 +319,15 @@ size_t near_scan_temp_bytes(int64_t n)
 }
 
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
-                      const NearWork& w, hipStream_t s)
+                      const double* pts, const Elements& el, const NearWork& w, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    static_assert(kBlock == kCostClasses, "one thread per cost class");
+    const unsigned lgrid = grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40));
+    zero_u32_kernel<<<1, kBlock, 0, s>>>(w.buckets, kCostClasses);
+    cost_count_kernel<<<lgrid, kBlock, 0, s>>>(list, ctr, cap, pts, n, el, w.cost, w.buckets);
+    cost_scan_kernel<<<1, kCostClasses, 0, s>>>(w.buckets);
+    cost_scatter_kernel<<<std::max(1u, lgrid / kCostItems), kBlock, 0, s>>>(ctr, cap, w.cost, w.buckets, w.order);
     zero_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(w.count, n);
     zero_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(w.cursor, n);
     count_kernel<<<grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40)), kBlock, 0, s>>>(list, ctr, cap,

@@ -1,12 +1,22 @@
 // Continuous-batching query server.
 //
 // Geometry and densities stay resident; each free stream slot takes the longest prefix of
-// a waiting queue (arrival order) whose points fit into one batch, runs one far-field
-// launch over all of them (split over element chunks when the batch is small, with a
-// fixed-order reduction of the chunks), the FP64 near field, and copies the results back.
-// Slots on different streams overlap on the device; queries arriving while batches run
-// are admitted as soon as a slot is free.  Optionally short queries have a queue and a
-// slot of their own (the other slots take them only when no long query waits).
+// a waiting queue (arrival order) whose points fit into one batch and whose device memory
+// fits what the budget has left, runs one far-field launch over all of them (split over
+// element chunks when the batch is small, with a fixed-order reduction of the chunks), the
+// FP64 near field, and copies the results back.  Slots on different streams overlap on
+// the device; queries arriving while batches run are admitted as soon as a slot and memory
+// are free.  Optionally short queries have a queue and a slot of their own (the other slots
+// take them only when no long query waits).
+//
+// Memory: each batch allocates its buffers on its own stream (stream-ordered allocation
+// from the device's pool) when it is admitted and releases them when it completes; the
+// scheduler accounts their bytes against the budget.  A batch runs in two phases: the
+// near-pair list pass, the far field and the chunk reduction are enqueued at admission;
+// once the list pass's pair count has reached the host (about a millisecond later, while
+// the far field runs), the near stage is enqueued -- after growing the batch's list on its
+// own stream when it was too short.  No host wait stalls the other slots, and the far
+// field is never repeated.
 #include "server.h"
 
 #include <algorithm>
@@ -23,6 +33,19 @@ constexpr int kMaxServeSplit = 1024;  // element chunks of one serving launch
 constexpr int kSlotSplit = 256;       // partial-sum rows of a slot: kSlotSplit x max_batch_points
 constexpr int kPointsPerBlock = 512;  // nominal points per workgroup for sizing the split (the
                                        // far kernels hold 256-768, by precision and rule)
+constexpr size_t kNearPairBytes = sizeof(NearPair) + kNearWorkBytesPerPair + 4 * sizeof(double);
+
+template <typename T>
+hipError_t alloc_async(T** p, size_t count, hipStream_t s)
+{
+    return hipMallocAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), s);
+}
+template <typename T>
+void free_async(T*& p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+}
 }  // namespace
 
 double Server::now() const
@@ -42,6 +65,32 @@ Server* Server::create(const ServerEnv& env, const bemc_server_config& cfg, std:
     return s;
 }
 
+int Server::split_for(int64_t n) const
+{
+    const int64_t blocks = (n + kPointsPerBlock - 1) / kPointsPerBlock;
+    // Element chunks: enough workgroups to fill the chip, and short ones for a small batch
+    // so that it finishes soon even while long batches hold most of the compute units;
+    // partial sums bounded by max_split_ x max_batch_points rows of 4; chunks of at least 64
+    // elements.
+    const int64_t cap = (int64_t)max_split_ * cfg_.max_batch_points / std::max<int64_t>(1, n);
+    return (int)std::max<int64_t>(
+        1, std::min({ kWavesTarget / std::max<int64_t>(1, blocks), cap, env_.el.ne / 64, (int64_t)kMaxServeSplit }));
+}
+
+unsigned long long Server::initial_near(int64_t n) const
+{
+    return (unsigned long long)std::max<int64_t>(4096, 16 * n);
+}
+
+// points, potential and field, element-chunk partial sums, near-pair list with its
+// regrouping, cost order and result records, per-point segments and scan workspace
+size_t Server::batch_bytes(int64_t n, unsigned long long near_pairs) const
+{
+    const int ns = split_for(n);
+    return (size_t)n * 8 * (3 + 1 + 3) + (ns > 1 ? (size_t)ns * 4 * 8 * (size_t)n : 0) +
+           near_pairs * sizeof(NearPair) + near_work_bytes(n, near_pairs, 4);
+}
+
 bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::string& err)
 {
     env_ = env;
@@ -56,37 +105,34 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
     const int64_t M = cfg.max_batch_points;
     const int64_t blocks = (M + kPointsPerBlock - 1) / kPointsPerBlock;
     max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(kSlotSplit, kWavesTarget / std::max<int64_t>(1, blocks)));
-    const unsigned long long near0 = (unsigned long long)std::max<int64_t>(1 << 16, 16 * M);
-    // points, results, partial sums, near list (+ its regrouping and 4 result rows) and
-    // the per-point near-field segments
-    const size_t slot_bytes = (size_t)M * 8 * (3 + 1 + 3 + 4 * (size_t)max_split_) + (size_t)M * 12 +
-                              near0 * (3 * sizeof(NearPair) + 8 + 4 * sizeof(double)) + 4096;
-    int n_slots = (int)std::min<size_t>((size_t)cfg.n_streams, cfg.mem_budget_bytes / slot_bytes);
-    if (n_slots < 1) {
-        err = "memory budget too small for one batch slot";
+    if (batch_bytes(M, initial_near(M)) > cfg.mem_budget_bytes) {
+        err = "memory budget too small for one batch of max_batch_points";
         return false;
     }
     if (hipSetDevice(env.device) != hipSuccess) { err = "hipSetDevice"; return false; }
-    slots_.resize((size_t)n_slots);
+    // keep released batch memory in the device's pool (up to the budget) instead of
+    // returning it to the driver at every synchronisation
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, env.device) == hipSuccess && pool) {
+        uint64_t thr = cfg.mem_budget_bytes;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    slots_.resize((size_t)cfg.n_streams);
     for (auto& s : slots_) {
         bool okk = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&s.listed, hipEventDisableTiming) == hipSuccess &&
                    hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess &&
-                   hipMalloc(reinterpret_cast<void**>(&s.d_pts), (size_t)M * 3 * 8) == hipSuccess &&
-                   hipMalloc(reinterpret_cast<void**>(&s.d_phi), (size_t)M * 8) == hipSuccess &&
-                   hipMalloc(reinterpret_cast<void**>(&s.d_E), (size_t)M * 3 * 8) == hipSuccess &&
-                   hipMalloc(reinterpret_cast<void**>(&s.d_partial), (size_t)M * 4 * 8 * max_split_) == hipSuccess &&
-                   hipMalloc(reinterpret_cast<void**>(&s.d_near), near0 * sizeof(NearPair)) == hipSuccess &&
                    hipMalloc(reinterpret_cast<void**>(&s.d_ctr), sizeof(DevCounters)) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_pts), (size_t)M * 3 * 8, hipHostMallocDefault) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_out), (size_t)M * 4 * 8, hipHostMallocDefault) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_ctr), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess &&
-                   near_work_alloc(s.nw, M, near0, 4) == hipSuccess;
+                   hipHostMalloc(reinterpret_cast<void**>(&s.h_list), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess;
         if (!okk) {
             (void)hipGetLastError();
             err = "out of device or pinned memory for the batch slots";
             return false;
         }
-        s.near_cap = near0;
     }
     if (cfg.small_query_points > 0 && slots_.size() >= 2) slots_.back().small_only = true;
     thread_ = std::thread([this] { loop(); });
@@ -164,17 +210,16 @@ void Server::stop()
     if (thread_.joinable()) thread_.join();
     (void)hipSetDevice(env_.device);
     for (auto& s : slots_) {
-        if (s.stream) (void)hipStreamSynchronize(s.stream);
-        if (s.d_pts) (void)hipFree(s.d_pts);
-        if (s.d_phi) (void)hipFree(s.d_phi);
-        if (s.d_E) (void)hipFree(s.d_E);
-        if (s.d_partial) (void)hipFree(s.d_partial);
-        if (s.d_near) (void)hipFree(s.d_near);
-        near_work_free(s.nw);
+        if (s.stream) {
+            free_batch(s);
+            (void)hipStreamSynchronize(s.stream);
+        }
         if (s.d_ctr) (void)hipFree(s.d_ctr);
         if (s.h_pts) (void)hipHostFree(s.h_pts);
         if (s.h_out) (void)hipHostFree(s.h_out);
         if (s.h_ctr) (void)hipHostFree(s.h_ctr);
+        if (s.h_list) (void)hipHostFree(s.h_list);
+        if (s.listed) (void)hipEventDestroy(s.listed);
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         s = Slot{};
@@ -182,14 +227,46 @@ void Server::stop()
     slots_.clear();
 }
 
-// Enqueue the batch held by slot s (its queries and point count are set).
-bool Server::launch(Slot& s, std::string& err)
+bool Server::alloc_batch(Slot& s, std::string& err)
 {
     const int64_t n = s.n;
-    if (s.near_cap == 0 || !s.d_near || !s.nw.count) {  // a failed regrowth left no near-field buffers
-        err = "batch slot has no near-pair buffers";
+    s.n_split = split_for(n);
+    s.near_cap = initial_near(n);
+    hipError_t e = alloc_async(&s.d_pts, (size_t)n * 3, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_phi, (size_t)n, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_E, (size_t)n * 3, s.stream);
+    if (e == hipSuccess && s.n_split > 1) e = alloc_async(&s.d_partial, (size_t)s.n_split * 4 * (size_t)n, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_near, (size_t)s.near_cap, s.stream);
+    if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, s.near_cap, 4, s.stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        err = std::string("batch buffers: ") + hipGetErrorString(e);
+        free_batch(s);
         return false;
     }
+    s.bytes = batch_bytes(n, s.near_cap);
+    mem_used_ += s.bytes;
+    return true;
+}
+
+void Server::free_batch(Slot& s)
+{
+    free_async(s.d_pts, s.stream);
+    free_async(s.d_phi, s.stream);
+    free_async(s.d_E, s.stream);
+    free_async(s.d_partial, s.stream);
+    free_async(s.d_near, s.stream);
+    near_work_free_async(s.nw, s.stream);
+    mem_used_ -= std::min(mem_used_, s.bytes);
+    s.bytes = 0;
+    s.near_cap = 0;
+}
+
+// Phase 1, enqueued at admission: copy-in, near-pair list pass (its count copied to the
+// host and marked by s.listed), far field and chunk reduction.
+bool Server::launch_far(Slot& s, std::string& err)
+{
+    const int64_t n = s.n;
     // pack points SoA into pinned staging
     int64_t off = 0;
     for (uint64_t id : s.queries) {
@@ -201,19 +278,13 @@ bool Server::launch(Slot& s, std::string& err)
         }
         off += q.n;
     }
-    const int64_t blocks = (n + kPointsPerBlock - 1) / kPointsPerBlock;
-    // Element chunks: enough workgroups to fill the chip, and short ones for a small batch
-    // so that it finishes soon even while long batches hold most of the compute units;
-    // bounded by the partial-sum buffer (max_split_ x max_batch_points rows of 4) and by
-    // chunks of at least 64 elements.
-    const int64_t cap = (int64_t)max_split_ * cfg_.max_batch_points / std::max<int64_t>(1, n);
-    const int n_split = (int)std::max<int64_t>(
-        1, std::min({ kWavesTarget / blocks, cap, env_.el.ne / 64, (int64_t)kMaxServeSplit }));
     const int64_t ne = env_.el.ne;
-    const int64_t chunk = (ne + n_split - 1) / n_split;
     const double K = coulomb_constant();
     hipError_t e = hipMemcpyAsync(s.d_pts, s.h_pts, (size_t)n * 3 * 8, hipMemcpyHostToDevice, s.stream);
     if (e == hipSuccess) e = launch_zero_counters(s.d_ctr, s.stream);
+    if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_list, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.listed, s.stream);
     FarArgs fa{};
     fa.el = env_.el;
     fa.rules = env_.rules;
@@ -224,19 +295,72 @@ bool Server::launch(Slot& s, std::string& err)
     fa.K = K;
     fa.phi = s.d_phi;
     fa.E = s.d_E;
-    fa.partial = n_split > 1 ? s.d_partial : nullptr;
+    fa.partial = s.n_split > 1 ? s.d_partial : nullptr;
     fa.elem_begin = 0;
     fa.elem_end = ne;
-    fa.n_split = n_split;
-    fa.chunk = chunk;
+    fa.n_split = s.n_split;
+    fa.chunk = (ne + s.n_split - 1) / s.n_split;
     fa.near_list = s.d_near;
     fa.near_cap = s.near_cap;
     fa.ctr = s.d_ctr;
     fa.dr_rules = env_.dr_rules;
     fa.lv = env_.lv;
-    if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
     if (e == hipSuccess) e = launch_far_eval(fa, cfg_.precision, s.stream);
-    if (e == hipSuccess && n_split > 1) e = launch_reduce_split(s.d_partial, n_split, n, K, s.d_phi, s.d_E, s.stream);
+    if (e == hipSuccess && s.n_split > 1)
+        e = launch_reduce_split(s.d_partial, s.n_split, n, K, s.d_phi, s.d_E, s.stream);
+    if (e != hipSuccess) {
+        err = hipGetErrorString(e);
+        return false;
+    }
+    s.state = kFar;
+    return true;
+}
+
+// Phase 2, once the list pass's count is on the host: grow the list on the batch's stream
+// if it was too short (and list again; the far field stays), then regrouping, near field,
+// ordered sums, copy-out.  Returns 1 when the grown list does not fit the memory left while
+// another batch is in its near stage (the batch waits for it), < 0 on an error.
+int Server::near_stage(Slot& s, std::string& err)
+{
+    const int64_t n = s.n;
+    const unsigned long long found = s.h_list->near_count;
+    hipError_t e = hipSuccess;
+    if (found > s.near_cap) {
+        if (found > kMaxNearPairs) {
+            err = "near pairs of a batch exceed 2^32 - 1";
+            return BEMC_E_LIMIT;
+        }
+        const unsigned long long cap = std::min(found + found / 4, kMaxNearPairs);
+        const size_t grown = batch_bytes(n, cap);
+        const size_t extra = grown - std::min(grown, s.bytes);
+        if (mem_used_ + extra > cfg_.mem_budget_bytes) {
+            // wait while another batch is in its near stage: it completes without further
+            // memory and releases its buffers.  Otherwise (the other batches in flight are
+            // waiting for their own pair counts or growths) grow beyond the budget: then this
+            // batch is in its near stage and the others wait for it, so at most one batch at a
+            // time exceeds the budget and no two batches wait for each other.
+            bool draining = false;
+            for (auto& o : slots_) draining |= (&o != &s && o.state == kNear);
+            if (draining) return 1;
+        }
+        free_async(s.d_near, s.stream);
+        near_work_free_async(s.nw, s.stream);
+        e = alloc_async(&s.d_near, (size_t)cap, s.stream);
+        if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, cap, 4, s.stream);
+        mem_used_ += extra;
+        s.bytes = grown;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            err = std::string("near-pair list could not be grown: ") + hipGetErrorString(e);
+            s.near_cap = 0;
+            return BEMC_E_OUT_OF_MEMORY;
+        }
+        s.near_cap = cap;
+        e = launch_reset_near_count(s.d_ctr, s.stream);
+        if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
+    }
+    const int64_t ne = env_.el.ne;
+    const double K = coulomb_constant();
     NearArgs na{};
     na.el = env_.el;
     na.rules = env_.rules;
@@ -250,12 +374,13 @@ bool Server::launch(Slot& s, std::string& err)
     na.near_list = s.d_near;
     na.near_cap = s.near_cap;
     na.slot = s.nw.slot;
+    na.order = s.nw.order;
     na.res = s.nw.res;
     na.ctr = s.d_ctr;
     na.near_dr2 = env_.near_dr * env_.near_dr;
     na.max_depth = env_.max_depth;
     na.visit_limit = 1ll << 22;
-    if (e == hipSuccess) e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.nw, s.stream);
+    if (e == hipSuccess) e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, s.stream);
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess)
         e = near_reduce(s.nw, n, kNearEval, s.d_phi, s.d_E, nullptr, env_.el.q, ne, 1, K, s.stream);
@@ -265,49 +390,33 @@ bool Server::launch(Slot& s, std::string& err)
     if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
     if (e != hipSuccess) {
         err = hipGetErrorString(e);
-        return false;
+        return BEMC_E_DEVICE;
     }
-    return true;
+    s.state = kNear;
+    return 0;
+}
+
+// Every query of the batch ends with `status`; the batch's buffers are released.
+void Server::fail_batch(Slot& s, int status, const std::string& err)
+{
+    (void)hipStreamSynchronize(s.stream);  // nothing of the batch may still use its buffers
+    free_batch(s);
+    std::lock_guard<std::mutex> lk(mu_);
+    err_ = err;
+    for (uint64_t id : s.queries) {
+        Query& q = queries_[id];
+        q.info.status = status;
+        q.info.done = 1;
+        q.info.end_s = now();
+    }
+    s.state = kIdle;
+    s.queries.clear();
+    done_cv_.notify_all();
 }
 
 void Server::complete(Slot& s)
 {
     const int64_t n = s.n;
-    if (s.h_ctr->near_count > s.near_cap) {
-        // near-pair list overflowed: grow it and run the batch again (synchronously)
-        const unsigned long long cap = s.h_ctr->near_count + s.h_ctr->near_count / 4;
-        (void)hipFree(s.d_near);
-        s.d_near = nullptr;
-        if (cap > kMaxNearPairs || hipMalloc(reinterpret_cast<void**>(&s.d_near), cap * sizeof(NearPair)) != hipSuccess ||
-            near_work_alloc(s.nw, cfg_.max_batch_points, cap, 4) != hipSuccess) {
-            (void)hipGetLastError();
-            s.near_cap = 0;
-        } else {
-            s.near_cap = cap;
-        }
-        std::string err;
-        bool relaunched = false;
-        if (s.near_cap) {
-            std::lock_guard<std::mutex> lk(mu_);
-            relaunched = launch(s, err);
-        }
-        if (relaunched && hipEventSynchronize(s.done) == hipSuccess && s.h_ctr->near_count <= s.near_cap) {
-            // fall through to the scatter below
-        } else {
-            std::lock_guard<std::mutex> lk(mu_);
-            err_ = "near-pair list could not be grown";
-            for (uint64_t id : s.queries) {
-                Query& q = queries_[id];
-                q.info.status = BEMC_E_OUT_OF_MEMORY;
-                q.info.done = 1;
-                q.info.end_s = now();
-            }
-            s.busy = false;
-            s.queries.clear();
-            done_cv_.notify_all();
-            return;
-        }
-    }
     std::vector<uint64_t> ids;
     {
         std::lock_guard<std::mutex> lk(mu_);
@@ -330,6 +439,7 @@ void Server::complete(Slot& s)
         }
         off += q->n;
     }
+    free_batch(s);
     const double t = now();
     std::lock_guard<std::mutex> lk(mu_);
     for (uint64_t id : ids) {
@@ -338,7 +448,7 @@ void Server::complete(Slot& s)
         q.info.done = 1;
         q.info.end_s = t;
     }
-    s.busy = false;
+    s.state = kIdle;
     s.queries.clear();
     done_cv_.notify_all();
 }
@@ -349,31 +459,39 @@ void Server::loop()
     std::unique_lock<std::mutex> lk(mu_);
     while (true) {
         bool progressed = false;
-        // completions
+        // completions and second phases (outside the lock: they copy results and enqueue)
         for (auto& s : slots_) {
-            if (!s.busy) continue;
-            if (hipEventQuery(s.done) == hipSuccess) {
+            if (s.state == kNear && hipEventQuery(s.done) == hipSuccess) {
                 lk.unlock();
                 complete(s);
                 lk.lock();
                 progressed = true;
+            } else if (s.state == kFar && hipEventQuery(s.listed) == hipSuccess) {
+                lk.unlock();
+                std::string err;
+                const int rc = near_stage(s, err);
+                if (rc < 0) fail_batch(s, rc, err);
+                lk.lock();
+                progressed |= rc != 1;
             }
         }
-        // admissions: each free slot takes the longest prefix of its queue that fits
+        // admissions: each free slot takes the longest prefix of its queue that fits one
+        // batch and the memory left
         for (auto& s : slots_) {
-            if (s.busy) continue;
+            if (s.state != kIdle) continue;
             std::deque<uint64_t>* wq = s.small_only ? &waiting_small_ : (waiting_.empty() ? &waiting_small_ : &waiting_);
             if (wq->empty()) continue;
             int64_t pts = 0;
-            s.queries.clear();
-            while (!wq->empty()) {
-                Query& q = queries_[wq->front()];
-                if (pts + q.n > cfg_.max_batch_points) break;
-                pts += q.n;
-                s.queries.push_back(q.id);
-                wq->pop_front();
+            size_t k = 0;
+            for (; k < wq->size(); ++k) {
+                const int64_t qn = queries_[(*wq)[k]].n;
+                if (pts + qn > cfg_.max_batch_points) break;
+                if (pts + qn > 0 && mem_used_ + batch_bytes(pts + qn, initial_near(pts + qn)) > cfg_.mem_budget_bytes) break;
+                pts += qn;
             }
-            if (s.queries.empty()) continue;
+            if (k == 0) continue;  // the first query waits for memory
+            s.queries.assign(wq->begin(), wq->begin() + (std::ptrdiff_t)k);
+            wq->erase(wq->begin(), wq->begin() + (std::ptrdiff_t)k);
             s.n = pts;
             s.batch_id = next_batch_++;
             const double t = now();
@@ -383,32 +501,22 @@ void Server::loop()
                 q.info.batch_id = s.batch_id;
                 q.info.batch_points = pts;
             }
-            s.busy = true;
-            std::string err;
-            bool launched;
-            if (pts == 0) {
-                launched = true;  // only empty queries: nothing to run
-                (void)hipEventRecord(s.done, s.stream);
-                std::memset(s.h_ctr, 0, sizeof(DevCounters));
-            } else {
-                launched = launch(s, err);
-            }
-            if (!launched) {
-                err_ = err;
-                for (uint64_t id : s.queries) {
-                    Query& q = queries_[id];
-                    q.info.status = BEMC_E_DEVICE;
-                    q.info.done = 1;
-                    q.info.end_s = now();
-                }
-                s.busy = false;
-                s.queries.clear();
-                done_cv_.notify_all();
-            }
             progressed = true;
+            std::string err;
+            if (pts == 0) {  // only empty queries: nothing to run
+                std::memset(s.h_ctr, 0, sizeof(DevCounters));
+                s.state = kNear;
+                if (hipEventRecord(s.done, s.stream) == hipSuccess) continue;
+                err = "hipEventRecord";
+            } else if (alloc_batch(s, err) && launch_far(s, err)) {
+                continue;
+            }
+            lk.unlock();
+            fail_batch(s, err.rfind("batch buffers", 0) == 0 ? BEMC_E_OUT_OF_MEMORY : BEMC_E_DEVICE, err);
+            lk.lock();
         }
         bool any_busy = false;
-        for (auto& s : slots_) any_busy |= s.busy;
+        for (auto& s : slots_) any_busy |= s.state != kIdle;
         if (stopping_ && waiting_.empty() && waiting_small_.empty() && !any_busy) break;
         if (!progressed) cv_.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 2000));
     }

@@ -46,32 +46,46 @@ private:
         bool small;
         bemc_query_info info;
     };
+    enum SlotState { kIdle = 0, kFar = 1, kNear = 2 };
     struct Slot {
         hipStream_t stream = nullptr;
+        hipEvent_t listed = nullptr;  // the near-pair list pass's count has reached h_list
         hipEvent_t done = nullptr;
+        int state = kIdle;  // kFar: far field enqueued, near-pair count pending; kNear: near field enqueued
+        // buffers of the batch in flight: stream-ordered allocations, released at completion
         double *d_pts = nullptr, *d_phi = nullptr, *d_E = nullptr, *d_partial = nullptr;
-        double *h_pts = nullptr, *h_out = nullptr;  // pinned staging: [3][M] in, [4][M] out
         NearPair* d_near = nullptr;
         unsigned long long near_cap = 0;
         NearWork nw{};  // per-point segments and per-pair results (near_cap pairs, 4 rows)
-        DevCounters *d_ctr = nullptr, *h_ctr = nullptr;
-        bool busy = false;
+        size_t bytes = 0;  // device bytes accounted to the batch
+        DevCounters* d_ctr = nullptr;                 // kept for the server's lifetime
+        double *h_pts = nullptr, *h_out = nullptr;    // pinned staging: [3][M] in, [4][M] out
+        DevCounters *h_ctr = nullptr, *h_list = nullptr;
         bool small_only = false;  // serves the short-query class only
         int64_t batch_id = -1;
         int64_t n = 0;
+        int n_split = 1;
         std::vector<uint64_t> queries;
     };
 
     Server() = default;
     bool init(const ServerEnv& env, const bemc_server_config& cfg, std::string& err);
     void loop();
-    bool launch(Slot& s, std::string& err);
+    int split_for(int64_t n) const;                  // element chunks of a batch of n points
+    size_t batch_bytes(int64_t n, unsigned long long near_pairs) const;
+    unsigned long long initial_near(int64_t n) const;  // near-pair list of a new batch
+    bool alloc_batch(Slot& s, std::string& err);     // stream-ordered, on the slot's stream
+    void free_batch(Slot& s);                        // stream-ordered
+    bool launch_far(Slot& s, std::string& err);      // copy-in, list pass, far field
+    int near_stage(Slot& s, std::string& err);       // 0 enqueued, 1 deferred (memory), < 0 error
     void complete(Slot& s);
+    void fail_batch(Slot& s, int status, const std::string& err);
     double now() const;
 
     ServerEnv env_{};
     bemc_server_config cfg_{};
     int max_split_ = 64;
+    size_t mem_used_ = 0;  // device bytes of the batches in flight (scheduler thread only)
     std::vector<Slot> slots_;
     std::mutex mu_;
     std::condition_variable cv_;       // scheduler wake-up

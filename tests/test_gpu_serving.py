@@ -115,3 +115,86 @@ def test_admission_and_latency_fields(setup):
         ctx.server_poll(123456)
     ctx.server_stop()
     ctx.close()
+
+
+def min_budget(ctx, max_batch, n_streams):
+    """The smallest budget server_start accepts: one batch of max_batch points (bisection)."""
+    lo, hi = 1 << 10, 1 << 34
+    while hi - lo > (1 << 12):
+        mid = (lo + hi) // 2
+        try:
+            ctx.server_start(mem_budget_bytes=mid, max_batch_points=max_batch, n_streams=n_streams, precision="fp64")
+        except bemc.BemcError as e:
+            assert e.code == bemc.E_INVALID_ARG
+            lo = mid
+            continue
+        ctx.server_stop()
+        hi = mid
+    return hi
+
+
+def check_oracle(w, qs, phis, Es, tol, rng):
+    sel = [rng.choice(len(q), 24, replace=False) for q in qs]
+    P = np.concatenate([q[s] for q, s in zip(qs, sel)])
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], P, oracle.params(33, 7), with_abs=True)
+    phi = np.concatenate([p[s] for p, s in zip(phis, sel)])
+    E = np.concatenate([e[s] for e, s in zip(Es, sel)])
+    ep = np.abs(phi - ref["phi"]) / ref["abs_phi"]
+    ee = np.sum(np.abs(E - ref["E"]), axis=1) / ref["abs_E"]
+    assert ep.max() <= tol and ee.max() <= tol
+    return ref
+
+
+def test_memory_budget_serialises_batches(setup):
+    """A budget of 1.5 batches of max_batch_points: with three streams, full batches still
+    run one at a time (each is admitted once the previous one has released its memory)."""
+    w, _ = setup
+    M = 4096
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    B = min_budget(ctx, M, 3)
+    ctx.server_start(mem_budget_bytes=int(1.5 * B), max_batch_points=M, n_streams=3, precision="fp64")
+    qs = [np.ascontiguousarray(W.track_points(M, np.random.default_rng([91, i]))) for i in range(4)]
+    phis = [np.full(M, np.nan) for _ in qs]
+    Es = [np.full((M, 3), np.nan) for _ in qs]
+    ts = [ctx.server_submit(q, p, e) for q, p, e in zip(qs, phis, Es)]
+    infos = [ctx.server_wait(t, 60.0) for t in ts]
+    ctx.server_stop()
+    ctx.close()
+    assert all(i["status"] == 0 for i in infos)
+    assert len({i["batch_id"] for i in infos}) == len(qs)  # a full batch each
+    spans = sorted((i["start_s"], i["end_s"]) for i in infos)
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0  # admitted after the previous batch completed
+    check_oracle(w, qs, phis, Es, 1e-12, np.random.default_rng(4))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_near_list_growth_under_a_tight_budget(setup, precision, tol):
+    """Two concurrent batches of points just above the elements, each with more near pairs
+    than its initial list, and a budget that holds both initial batches but not both grown:
+    the growths happen one after the other on the batches' own streams and every result
+    agrees with the oracle."""
+    w, _ = setup
+    M = 4096
+    rng = np.random.default_rng(92)
+    qs = []
+    for i in range(2):
+        idx = rng.integers(0, w.n_elements, M)
+        P, nrm, L = W.points_on_elements(w.tri, w.rect, idx, rng)
+        qs.append(np.ascontiguousarray(P + nrm * (1e-3 * L)[:, None]))
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    B = min_budget(ctx, M, 2)
+    ctx.server_start(mem_budget_bytes=int(2.05 * B), max_batch_points=M, n_streams=2, precision=precision)
+    phis = [np.full(M, np.nan) for _ in qs]
+    Es = [np.full((M, 3), np.nan) for _ in qs]
+    ts = [ctx.server_submit(q, p, e) for q, p, e in zip(qs, phis, Es)]
+    infos = [ctx.server_wait(t, 60.0) for t in ts]
+    ctx.server_stop()
+    ctx.close()
+    assert all(i["status"] == 0 for i in infos)
+    ref = check_oracle(w, qs, phis, Es, tol, np.random.default_rng(5))
+    assert ref["stats"]["near_pairs"] > 16 * 24 * 2  # more than the initial 16 per point
