@@ -749,7 +749,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     std::vector<double> geom(9 * (size_t)ne), cen(3 * (size_t)ne), thr2((size_t)ne), frame(9 * (size_t)ne),
-        loc(6 * (size_t)ne, 0.0), L((size_t)ne), area((size_t)ne), nrm(3 * (size_t)ne);
+        loc(9 * (size_t)ne, 0.0), L((size_t)ne), area((size_t)ne), nrm(3 * (size_t)ne);
     auto at = [ne](std::vector<double>& v, int comp, int64_t e) -> double& { return v[(size_t)comp * ne + e]; };
     for (int64_t e = 0; e < ne; ++e) {
         const bool is_tri = e < n_tri;
@@ -817,12 +817,23 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
                 const double d[3] = { g[3 * m] - C[0], g[3 * m + 1] - C[1], g[3 * m + 2] - C[2] };
                 at(loc, 2 * m, e) = dot(d, F1);
                 at(loc, 2 * m + 1, e) = dot(d, F2);
+                at(loc, 6 + m, e) = dot(d, N);  // rounding-level height: the frame of a sliver
+                                                 // is known only to eps x aspect ratio
             }
         } else {  // half sides: e1 / 2 = gamma F1 + beta F2, e2 / 2 = alpha F1
             const double h1[3] = { 0.5 * g[3], 0.5 * g[4], 0.5 * g[5] };
             at(loc, 0, e) = dot(h1, F1);
             at(loc, 1, e) = dot(h1, F2);
             at(loc, 2, e) = 0.5 * std::sqrt(dot(g + 6, g + 6));
+            // the corner P0 - c in the frame (c is the rounded centroid, so this is not exactly
+            // -e1/2 - e2/2, and the plane may pass beside c by a rounding of the coordinates),
+            // and the sides' rounding-level heights
+            const double d0[3] = { g[0] - C[0], g[1] - C[1], g[2] - C[2] };
+            at(loc, 3, e) = dot(d0, F1);
+            at(loc, 4, e) = dot(d0, F2);
+            at(loc, 5, e) = dot(d0, N);
+            at(loc, 6, e) = dot(g + 3, N);
+            at(loc, 7, e) = dot(g + 6, N);
         }
         area[(size_t)e] = a;
         L[(size_t)e] = Lh;

@@ -47,8 +47,10 @@ struct Elements {
     const double* thr2;  // [ne]     (near_dr * L)^2
     const double* frame; // [9][ne]  orthonormal frame f1, f2 (in the plane), f3 (normal);
                          //          rectangles: f1 along e2
-    const double* loc;   // [6][ne]  tri: in-plane coordinates (f1, f2) of A-c, B-c, C-c;
-                         //          rect: gamma = f1.e1/2, beta = f2.e1/2, alpha = |e2|/2, 0, 0, 0
+    const double* loc;   // [9][ne]  tri: in-plane coordinates (f1, f2) of A-c, B-c, C-c, then their
+                         //          f3 components (rounding-level heights, kept by the near field);
+                         //          rect: gamma = f1.e1/2, beta = f2.e1/2, alpha = |e2|/2, the corner
+                         //          P0 - c in the frame (3), the f3 components of e1 and e2, 0
     const double* L;     // [ne]     average side length
     const double* area;  // [ne]
     const double* nrm;   // [3][ne]  unit normal
@@ -188,7 +190,8 @@ size_t near_scan_temp_bytes(int64_t n);
 hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int rows);  // frees w first
 void near_work_free(NearWork& w);
 // stream-ordered allocation and release of one batch's buffers (w empty before the allocation)
-hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipStream_t s);
+hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipMemPool_t pool,
+                                 hipStream_t s);
 void near_work_free_async(NearWork& w, hipStream_t s);
 size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows);  // device bytes of those buffers
 // regroup the list (length read from ctr) into per-point segments sorted by element, and

@@ -1003,25 +1003,23 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             }
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (lvl[k] >= 0) {
-                    add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
-                    terms += (unsigned)nw;
-                    // the terms of the pair's own level (the per-pair choice)
-                    terms_pair += (unsigned)(lvl[k] == 0 ? o1 : (lvl[k] == 1 ? o2 - o1 : (lvl[k] == 2 ? o3 - o2 : nn - o3)));
-                }
+                if (lvl[k] >= 0) add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
+            // terms summed by the wavefront and the terms of the pairs' own levels (the
+            // per-pair choice), counted from ballots in scalar arithmetic
+            unsigned nc = 0, n0 = 0, n1 = 0, n2 = 0;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                nc += (unsigned)__popcll(__ballot(lvl[k] >= 0));
+                n0 += (unsigned)__popcll(__ballot(lvl[k] == 0));
+                n1 += (unsigned)__popcll(__ballot(lvl[k] == 1));
+                n2 += (unsigned)__popcll(__ballot(lvl[k] == 2));
+            }
+            terms += (unsigned long long)nc * (unsigned)nw;
+            terms_pair += (unsigned long long)n0 * (unsigned)o1 + (unsigned long long)n1 * (unsigned)(o2 - o1) +
+                          (unsigned long long)n2 * (unsigned)(o3 - o2) +
+                          (unsigned long long)(nc - n0 - n1 - n2) * (unsigned)(nn - o3);
         }
     }
-}
-
-// wavefront sum of a counter, added with one atomic per wavefront
-__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* dst)
-{
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned lo = __shfl_xor((unsigned)v, o);
-        const unsigned hi = __shfl_xor((unsigned)(v >> 32), o);
-        v += ((unsigned long long)hi << 32) | lo;
-    }
-    if (lane_id() == 0 && v) atomicAdd(dst, v);
 }
 
 // DR == false: one rule per kind, NT / NR nodes.  DR == true: levels (T0..T3 / R0..R3).
@@ -1059,8 +1057,11 @@ __global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
             far_eval_dr_range<NT, T1, T2, T3, true, MIXED, PPT, MODE>(a, s, P, e_lo, nt_end, terms, terms_pair);
         if (nr_begin < e_hi)
             far_eval_dr_range<NR, R1, R2, R3, false, MIXED, PPT, MODE>(a, s, P, nr_begin, e_hi, terms, terms_pair);
-        add_count(terms, &a.ctr->node_ints);
-        add_count(terms_pair, &a.ctr->node_ints_pair);
+        // wavefront totals: one atomic per wavefront
+        if (lane_id() == 0) {
+            if (terms) atomicAdd(&a.ctr->node_ints, terms);
+            if (terms_pair) atomicAdd(&a.ctr->node_ints_pair, terms_pair);
+        }
     } else {
         if (e_lo < nt_end) far_eval_range<NT, true, MIXED, PPT, MODE, (NT > 0)>(a, s, P, e_lo, nt_end);
         if (nr_begin < e_hi) far_eval_range<NR, false, MIXED, PPT, MODE, (NR > 0)>(a, s, P, nr_begin, e_hi);
@@ -1244,53 +1245,62 @@ __device__ __forceinline__ bool advance(NearState& s)
 }
 
 // The walk runs in the element's own frame (origin at the centroid, f1 and f2 in its plane,
-// f3 its normal; built at upload): the field point is p = (p1, p2, p3) and every node of the
-// subdivision is an in-plane pair, so a Gaussian point takes two-dimensional offsets
-// (p1 - a, p2 - b) and the shared height p3.  The pair's local sums are rotated back once.
+// f3 its normal; built at upload): the field point is p = (p1, p2, p3), and a Gaussian point
+// takes its offsets (da, db, dc) from the node coordinates in that frame.  The pair's local
+// sums are rotated back once.  The frame of a sliver triangle is known only to eps times its
+// aspect ratio, and the rounded centroid need not lie in the element's plane (a small element
+// far from the origin: by a rounding of its coordinates), so the vertices keep their third
+// coordinate in the frame (a rounding-level height) and a rectangle its corner relative to the
+// centroid: with them the nodes are the exact combinations of the vertices, as in three
+// dimensions.  A rectangle node's height varies across a cell only by rounding-level amounts
+// (the sides' heights): the cell centre's height serves all its Gaussian points.
 //
-// In-plane geometry of a node: a triangle node has a first vertex and two edge vectors
-// (lattice position (i, j) in units of h = 2^-level along the root's edges B - A and C - A;
-// an up node has vertices (i, j), (i+1, j), (i, j+1), a down node (i+1, j+1), (i, j+1),
-// (i+1, j)); a rectangle node is the cell (i, j) of the h-grid along e1 and e2.
+// Node geometry: a triangle node has a first vertex and two edge vectors (lattice position
+// (i, j) in units of h = 2^-level along the root's edges B - A and C - A; an up node has
+// vertices (i, j), (i+1, j), (i, j+1), a down node (i+1, j+1), (i, j+1), (i+1, j)); a
+// rectangle node is the cell (i, j) of the h-grid along e1 and e2.
 struct NearGeom {
-    double ax, ay;    // triangle: root vertex A; rectangle: corner P0 (in-plane, from the centroid)
-    double ux, uy;    // triangle: B - A; rectangle: e1 (in-plane)
-    double vx, vy;    // triangle: C - A; rectangle: e2 (in-plane)
+    double ax, ay, az;  // triangle: root vertex A; rectangle: corner P0 (from the centroid)
+    double ux, uy, uz;  // triangle: B - A; rectangle: e1 (in-plane, uz = 0)
+    double vx, vy, vz;  // triangle: C - A; rectangle: e2 (in-plane, vz = 0)
 };
 
 // Node s: its first vertex (triangle) or centre (rectangle) and, for triangles, its edge
-// vectors w1 = V1 - V0, w2 = V2 - V0; the node centroid (cx, cy).
-__device__ __forceinline__ void node_geometry(const NearState& s, const NearGeom& g, double h, double& x0, double& y0,
-                                              double& w1x, double& w1y, double& w2x, double& w2y, double& cx,
-                                              double& cy)
+// vectors w1 = V1 - V0, w2 = V2 - V0; the node centroid c.
+struct NodeGeom {
+    double x0, y0, z0, w1x, w1y, w1z, w2x, w2y, w2z, cx, cy, cz;
+};
+__device__ __forceinline__ void node_geometry(const NearState& s, const NearGeom& g, double h, NodeGeom& n)
 {
     if (s.kind == 0) {
         const double u = s.up ? s.i : s.i + 1, v = s.up ? s.j : s.j + 1, sg = s.up ? h : -h;
-        x0 = fma(u * h, g.ux, fma(v * h, g.vx, g.ax));
-        y0 = fma(u * h, g.uy, fma(v * h, g.vy, g.ay));
-        w1x = sg * g.ux; w1y = sg * g.uy;
-        w2x = sg * g.vx; w2y = sg * g.vy;
-        cx = fma(1.0 / 3.0, w1x + w2x, x0);
-        cy = fma(1.0 / 3.0, w1y + w2y, y0);
+        n.x0 = fma(u * h, g.ux, fma(v * h, g.vx, g.ax));
+        n.y0 = fma(u * h, g.uy, fma(v * h, g.vy, g.ay));
+        n.z0 = fma(u * h, g.uz, fma(v * h, g.vz, g.az));
+        n.w1x = sg * g.ux; n.w1y = sg * g.uy; n.w1z = sg * g.uz;
+        n.w2x = sg * g.vx; n.w2y = sg * g.vy; n.w2z = sg * g.vz;
+        n.cx = fma(1.0 / 3.0, n.w1x + n.w2x, n.x0);
+        n.cy = fma(1.0 / 3.0, n.w1y + n.w2y, n.y0);
+        n.cz = fma(1.0 / 3.0, n.w1z + n.w2z, n.z0);
     } else {
         const double ih = (s.i + 0.5) * h, jh = (s.j + 0.5) * h;
-        cx = fma(ih, g.ux, fma(jh, g.vx, g.ax));
-        cy = fma(ih, g.uy, fma(jh, g.vy, g.ay));
-        x0 = cx; y0 = cy;
-        w1x = w1y = w2x = w2y = 0.0;
+        n.cx = fma(ih, g.ux, fma(jh, g.vx, g.ax));
+        n.cy = fma(ih, g.uy, fma(jh, g.vy, g.ay));
+        n.cz = fma(ih, g.uz, fma(jh, g.vz, g.az));  // the height of the cell centre (rounding level)
+        n.x0 = n.cx; n.y0 = n.cy; n.z0 = n.cz;
+        n.w1x = n.w1y = n.w1z = n.w2x = n.w2y = n.w2z = 0.0;
     }
 }
 
-// Sums of one Gaussian point at in-plane offsets (da, db) and squared height p33, weight w
-// (unit element charge), in the element's frame:
-//   field:        f0 += w/r, f1 += w da/r^3, f2 += w db/r^3, f3 += w/r^3 (times p3 later);
+// Sums of one Gaussian point at offsets (da, db, dc) in the element's frame, weight w (unit
+// element charge):
+//   field:        f0 += w/r, (f1, f2, f3) += w (da, db, dc)/r^3;
 //   collocation:  f0 += w/r;
-//   gradient:     f0 += w/r^3, f1 += w/r^5, f2 += w da/r^5, f3 += w db/r^5, f4 += w da^2/r^5,
-//                 f5 += w db^2/r^5, f6 += w da db/r^5 (the local tensor follows per pair).
+//   gradient:     f0 += w/r^3, (f1 .. f6) += w (da^2, db^2, dc^2, da db, da dc, db dc)/r^5.
 template <int MODE>
-__device__ __forceinline__ void near_terms(double w, double da, double db, double p33, double (&f)[7])
+__device__ __forceinline__ void near_terms(double w, double da, double db, double dc, double (&f)[7])
 {
-    const double ri = rsqrt64(fma(da, da, fma(db, db, p33)));
+    const double ri = rsqrt64(fma(da, da, fma(db, db, dc * dc)));
     const double wr = w * ri;
     if constexpr (MODE == kNearColloc) {
         f[0] += wr;
@@ -1299,17 +1309,17 @@ __device__ __forceinline__ void near_terms(double w, double da, double db, doubl
         f[0] += wr;
         f[1] = fma(w3, da, f[1]);
         f[2] = fma(w3, db, f[2]);
-        f[3] += w3;
+        f[3] = fma(w3, dc, f[3]);
     } else {
         const double ri2 = ri * ri, w3 = wr * ri2, w5 = w3 * ri2;
-        const double ua = w5 * da, ub = w5 * db;
+        const double ua = w5 * da, ub = w5 * db, uc = w5 * dc;
         f[0] += w3;
-        f[1] += w5;
-        f[2] += ua;
-        f[3] += ub;
-        f[4] = fma(ua, da, f[4]);
-        f[5] = fma(ub, db, f[5]);
-        f[6] = fma(ua, db, f[6]);
+        f[1] = fma(ua, da, f[1]);
+        f[2] = fma(ub, db, f[2]);
+        f[3] = fma(uc, dc, f[3]);
+        f[4] = fma(ua, db, f[4]);
+        f[5] = fma(ua, dc, f[5]);
+        f[6] = fma(ub, dc, f[6]);
     }
 }
 
@@ -1333,7 +1343,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     uint32_t p = 0, e = 0;
     unsigned long long cur = 0;  // result slot of the pair in hand
     NearGeom g{};
-    double p1 = 0.0, p2 = 0.0, p3 = 0.0, p33 = 0.0;  // the field point in the element's frame
+    double p1 = 0.0, p2 = 0.0, p3 = 0.0;  // the field point in the element's frame
     double thr2 = 0.0, acc[7] = { 0, 0, 0, 0, 0, 0, 0 };
     int64_t visits = 0;
 
@@ -1370,16 +1380,14 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 p1 = fma(F[0], dxc, fma(F[1], dyc, F[2] * dzc));
                 p2 = fma(F[3], dxc, fma(F[4], dyc, F[5] * dzc));
                 p3 = fma(F[6], dxc, fma(F[7], dyc, F[8] * dzc));
-                p33 = p3 * p3;
-                if (st.kind == 0) {  // vertices A', B', C' in the plane
-                    g.ax = el.loc[e]; g.ay = el.loc[ne + e];
-                    g.ux = el.loc[2 * ne + e] - g.ax; g.uy = el.loc[3 * ne + e] - g.ay;
-                    g.vx = el.loc[4 * ne + e] - g.ax; g.vy = el.loc[5 * ne + e] - g.ay;
-                } else {  // e1 / 2 = (gamma, beta), e2 / 2 = (alpha, 0); corner -e1/2 - e2/2
-                    const double gm = el.loc[e], bt = el.loc[ne + e], al = el.loc[2 * ne + e];
-                    g.ux = 2.0 * gm; g.uy = 2.0 * bt;
-                    g.vx = 2.0 * al; g.vy = 0.0;
-                    g.ax = -(gm + al); g.ay = -bt;
+                if (st.kind == 0) {  // vertices A', B', C' in the frame
+                    g.ax = el.loc[e]; g.ay = el.loc[ne + e]; g.az = el.loc[6 * ne + e];
+                    g.ux = el.loc[2 * ne + e] - g.ax; g.uy = el.loc[3 * ne + e] - g.ay; g.uz = el.loc[7 * ne + e] - g.az;
+                    g.vx = el.loc[4 * ne + e] - g.ax; g.vy = el.loc[5 * ne + e] - g.ay; g.vz = el.loc[8 * ne + e] - g.az;
+                } else {  // e1 = (2 gamma, 2 beta, h1), e2 = (2 alpha, 0, h2); the corner P0 - c
+                    g.ux = 2.0 * el.loc[e]; g.uy = 2.0 * el.loc[ne + e]; g.uz = el.loc[6 * ne + e];
+                    g.vx = 2.0 * el.loc[2 * ne + e]; g.vy = 0.0; g.vz = el.loc[7 * ne + e];
+                    g.ax = el.loc[3 * ne + e]; g.ay = el.loc[4 * ne + e]; g.az = el.loc[5 * ne + e];
                 }
                 thr2 = el.thr2[e];
 #pragma unroll
@@ -1488,10 +1496,10 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         if (!active) continue;
         // ---- visit node st
         const double h = ldexp(1.0, -st.level);
-        double x0, y0, w1x, w1y, w2x, w2y, cx, cy;
-        node_geometry(st, g, h, x0, y0, w1x, w1y, w2x, w2y, cx, cy);
-        const double qx = p1 - cx, qy = p2 - cy;
-        const double D2 = fma(qx, qx, fma(qy, qy, p33));
+        NodeGeom nd;
+        node_geometry(st, g, h, nd);
+        const double qx = p1 - nd.cx, qy = p2 - nd.cy, qz = p3 - nd.cz;
+        const double D2 = fma(qx, qx, fma(qy, qy, qz * qz));
         const bool is_near = D2 < thr2 * h * h;
         ++visits;
         if (st.level > max_level) max_level = st.level;
@@ -1502,13 +1510,14 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         // leaf: the element's rule on this node, weights scaled by the area ratio h^2
         double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
         if (st.kind == 0) {
-            const double q1 = p1 - x0, q2 = p2 - y0;
+            const double q1 = p1 - nd.x0, q2 = p2 - nd.y0, q3 = p3 - nd.z0;
 #pragma unroll 4
             for (int i = 0; i < a.rules.nt; ++i) {
                 const double lb = a.rules.tri[4 * i + 1], lc = a.rules.tri[4 * i + 2], w = a.rules.tri[4 * i + 3];
-                const double da = fma(-lb, w1x, fma(-lc, w2x, q1));
-                const double db = fma(-lb, w1y, fma(-lc, w2y, q2));
-                near_terms<MODE>(w, da, db, p33, f);
+                const double da = fma(-lb, nd.w1x, fma(-lc, nd.w2x, q1));
+                const double db = fma(-lb, nd.w1y, fma(-lc, nd.w2y, q2));
+                const double dc = fma(-lb, nd.w1z, fma(-lc, nd.w2z, q3));
+                near_terms<MODE>(w, da, db, dc, f);
             }
         } else {
             const double H1x = h * (0.5 * g.ux), H1y = h * (0.5 * g.uy), H2x = h * (0.5 * g.vx);
@@ -1517,7 +1526,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 const double x = a.rules.rect[4 * i], y = a.rules.rect[4 * i + 1], w = a.rules.rect[4 * i + 2];
                 const double da = fma(-x, H1x, fma(-y, H2x, qx));
                 const double db = fma(-x, H1y, qy);
-                near_terms<MODE>(w, da, db, p33, f);
+                near_terms<MODE>(w, da, db, qz, f);
             }
         }
         const double h2 = h * h;
@@ -1546,10 +1555,11 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
 #pragma unroll
             for (int c = 0; c < 9; ++c) F[c] = el.frame[(int64_t)c * ne + e];
             if (GRAD) {
-                // local tensor m (d = (da, db, p3)), global M = F^T m F, dE_i/dx_j = q (delta_ij S3 - 3 M_ij)
-                const double m[3][3] = { { acc[4], acc[6], p3 * acc[2] },
-                                         { acc[6], acc[5], p3 * acc[3] },
-                                         { p3 * acc[2], p3 * acc[3], p33 * acc[1] } };
+                // local tensor m = sum w d d^T / r^5 (d = (da, db, dc)), global M = F^T m F,
+                // dE_i/dx_j = q (delta_ij S3 - 3 M_ij)
+                const double m[3][3] = { { acc[1], acc[4], acc[5] },
+                                         { acc[4], acc[2], acc[6] },
+                                         { acc[5], acc[6], acc[3] } };
                 double U[3][3];  // U[r][v] = sum_b m[r][b] F[b][v]
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
@@ -1561,12 +1571,11 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 r[1] = make_double2(Kq * fma(-3.0, M(2, 2), acc[0]), -3.0 * Kq * M(0, 1));
                 r[2] = make_double2(-3.0 * Kq * M(0, 2), -3.0 * Kq * M(1, 2));
             } else {
-                // local field (sum w da/r^3, sum w db/r^3, p3 sum w/r^3), rotated back
-                const double e3 = p3 * acc[3];
+                // local field sum w (da, db, dc)/r^3, rotated back
                 reinterpret_cast<double4*>(a.res)[cur] = make_double4(
-                    Kq * acc[0], Kq * fma(F[0], acc[1], fma(F[3], acc[2], F[6] * e3)),
-                    Kq * fma(F[1], acc[1], fma(F[4], acc[2], F[7] * e3)),
-                    Kq * fma(F[2], acc[1], fma(F[5], acc[2], F[8] * e3)));
+                    Kq * acc[0], Kq * fma(F[0], acc[1], fma(F[3], acc[2], F[6] * acc[3])),
+                    Kq * fma(F[1], acc[1], fma(F[4], acc[2], F[7] * acc[3])),
+                    Kq * fma(F[2], acc[1], fma(F[5], acc[2], F[8] * acc[3])));
             }
         }
         active = false;

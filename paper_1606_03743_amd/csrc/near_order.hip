@@ -267,8 +267,8 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
     return e;
 }
 
-// Stream-ordered variants (serving: buffers of one batch, allocated and released on the
-// batch's stream without waiting for other streams).
+// Stream-ordered variants (serving: buffers of one batch, allocated from the server's pool
+// and released on the batch's stream without waiting for other streams).
 void near_work_free_async(NearWork& w, hipStream_t s)
 {
     for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
@@ -285,23 +285,24 @@ size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows)
            3 * kCostClasses * sizeof(uint32_t) + near_scan_temp_bytes(std::max<int64_t>(n, 1));
 }
 
-hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipStream_t s)
+hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipMemPool_t pool,
+                                 hipStream_t s)
 {
     w = NearWork{};
     const size_t np = (size_t)std::max<int64_t>(n, 1), npairs = (size_t)std::max<unsigned long long>(pairs, 1);
     w.temp_bytes = near_scan_temp_bytes(std::max<int64_t>(n, 1));
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&w.count), np * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.start), np * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.cursor), np * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.grouped), npairs * sizeof(NearPair), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.origin), npairs * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.cost), npairs, s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMallocAsync(&w.temp, std::max<size_t>(w.temp_bytes, 1), s);
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.count), np * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.start), np * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.cursor), np * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.grouped), npairs * sizeof(NearPair), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.origin), npairs * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.cost), npairs, pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t), pool, s);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync(&w.temp, std::max<size_t>(w.temp_bytes, 1), pool, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         const size_t tb = w.temp_bytes;

@@ -36,9 +36,9 @@ constexpr int kPointsPerBlock = 512;  // nominal points per workgroup for sizing
 constexpr size_t kNearPairBytes = sizeof(NearPair) + kNearWorkBytesPerPair + 4 * sizeof(double);
 
 template <typename T>
-hipError_t alloc_async(T** p, size_t count, hipStream_t s)
+hipError_t alloc_async(T** p, size_t count, hipMemPool_t pool, hipStream_t s)
 {
-    return hipMallocAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), s);
+    return hipMallocFromPoolAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), pool, s);
 }
 template <typename T>
 void free_async(T*& p, hipStream_t s)
@@ -110,14 +110,29 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
         return false;
     }
     if (hipSetDevice(env.device) != hipSuccess) { err = "hipSetDevice"; return false; }
-    // keep released batch memory in the device's pool (up to the budget) instead of
-    // returning it to the driver at every synchronisation
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, env.device) == hipSuccess && pool) {
-        uint64_t thr = cfg.mem_budget_bytes;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    // the server's own memory pool: released batch memory stays in it (up to the budget)
+    // instead of going back to the driver at every synchronisation, and memory released on
+    // one stream is reused on another only once that release has completed (no dependency
+    // between the streams is ever inserted: a short batch never waits for a long one)
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = env.device;
+    if (hipMemPoolCreate(&pool_, &props) != hipSuccess) {
+        (void)hipGetLastError();
+        pool_ = nullptr;
+        err = "could not create the batch memory pool";
+        return false;
     }
-    (void)hipGetLastError();
+    uint64_t thr = cfg.mem_budget_bytes;
+    int no = 0;
+    if (hipMemPoolSetAttribute(pool_, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess ||
+        hipMemPoolSetAttribute(pool_, hipMemPoolReuseAllowInternalDependencies, &no) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "could not configure the batch memory pool";
+        return false;
+    }
     slots_.resize((size_t)cfg.n_streams);
     for (auto& s : slots_) {
         bool okk = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
@@ -225,6 +240,8 @@ void Server::stop()
         s = Slot{};
     }
     slots_.clear();
+    if (pool_) (void)hipMemPoolDestroy(pool_);  // every allocation of it has been released
+    pool_ = nullptr;
 }
 
 bool Server::alloc_batch(Slot& s, std::string& err)
@@ -232,12 +249,13 @@ bool Server::alloc_batch(Slot& s, std::string& err)
     const int64_t n = s.n;
     s.n_split = split_for(n);
     s.near_cap = initial_near(n);
-    hipError_t e = alloc_async(&s.d_pts, (size_t)n * 3, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_phi, (size_t)n, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_E, (size_t)n * 3, s.stream);
-    if (e == hipSuccess && s.n_split > 1) e = alloc_async(&s.d_partial, (size_t)s.n_split * 4 * (size_t)n, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_near, (size_t)s.near_cap, s.stream);
-    if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, s.near_cap, 4, s.stream);
+    hipError_t e = alloc_async(&s.d_pts, (size_t)n * 3, pool_, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_phi, (size_t)n, pool_, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_E, (size_t)n * 3, pool_, s.stream);
+    if (e == hipSuccess && s.n_split > 1)
+        e = alloc_async(&s.d_partial, (size_t)s.n_split * 4 * (size_t)n, pool_, s.stream);
+    if (e == hipSuccess) e = alloc_async(&s.d_near, (size_t)s.near_cap, pool_, s.stream);
+    if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, s.near_cap, 4, pool_, s.stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         err = std::string("batch buffers: ") + hipGetErrorString(e);
@@ -345,8 +363,8 @@ int Server::near_stage(Slot& s, std::string& err)
         }
         free_async(s.d_near, s.stream);
         near_work_free_async(s.nw, s.stream);
-        e = alloc_async(&s.d_near, (size_t)cap, s.stream);
-        if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, cap, 4, s.stream);
+        e = alloc_async(&s.d_near, (size_t)cap, pool_, s.stream);
+        if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, cap, 4, pool_, s.stream);
         mem_used_ += extra;
         s.bytes = grown;
         if (e != hipSuccess) {

@@ -86,6 +86,7 @@ private:
     bemc_server_config cfg_{};
     int max_split_ = 64;
     size_t mem_used_ = 0;  // device bytes of the batches in flight (scheduler thread only)
+    hipMemPool_t pool_ = nullptr;  // the batches' buffers (stream-ordered allocations)
     std::vector<Slot> slots_;
     std::mutex mu_;
     std::condition_variable cv_;       // scheduler wake-up
