@@ -280,14 +280,16 @@ int bemc_query_stats(bemc_handle h, bemc_stats* out);
  * them into one batch (one far-field launch over all their points, element-split when
  * the batch is small so the GPU stays full; fixed-order reduction of the element chunks;
  * then the FP64 near field) and copies each query's results to its host buffers when the
- * batch completes.  Batches on different streams overlap on the device.  Each batch
- * allocates its device buffers on its own stream when admitted (stream-ordered, from the
- * device's memory pool) and releases them when it completes; the scheduler accounts
- * them against mem_budget_bytes.  A batch's near-pair list starts at 16 pairs per point;
- * when its list pass finds more, the list grows on the batch's stream before the near
- * field (the far field is not repeated, no other stream waits).  A growth that does not
- * fit the budget waits while another batch is in its near stage; otherwise it proceeds,
- * so at most one batch at a time exceeds the budget, by its own growth.  With small_query_points > 0 and
+ * batch completes.  Batches on different streams overlap on the device.  Device memory:
+ * one allocation made at start (mem_budget_bytes, but at most twice what full batches on
+ * every stream need) is handed out per batch on the host: a block for the batch's per-point
+ * buffers and one for its near-pair list (16 pairs per point), taken at admission and given
+ * back at completion.  The whole batch is enqueued at admission; when its list pass finds
+ * more near pairs than the list holds, the far field is kept and the list grows -- a larger
+ * block, the list pass and the near stage again.  A growth that does not fit waits while
+ * another batch is running; otherwise the grown list goes outside the budget
+ * (stream-ordered allocation, released with the batch), so at most one batch at a time
+ * exceeds the budget, by its list.  With small_query_points > 0 and
  * at least two streams, queries of at most that many points wait in a queue of their
  * own, and one stream serves only that queue, so that short queries do not wait behind
  * long batches; the other streams take the long queue first and the short one when the

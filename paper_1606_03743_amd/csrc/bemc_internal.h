@@ -126,7 +126,9 @@ struct NearArgs {
     const NearPair* near_list;   // as the far kernel appended it
     unsigned long long near_cap;
     const uint32_t* slot;        // result slot of each list entry
-    const uint32_t* order;       // list indices in the order the lanes take them (costly first)
+    const uint32_t* order;       // list indices in the order the lanes take them (costly first;
+                                 // the pairs whose point lies on the element last)
+    const uint32_t* walk_end;    // device: entries of order that subdivide (near_walk_end)
     double* res;                 // per-pair result records at the pairs' slots: [slot][4] field,
                                  // [slot][6] gradient, [slot] collocation
     DevCounters* ctr;
@@ -148,6 +150,8 @@ hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows
                                 hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
 hipError_t launch_reset_near_count(DevCounters* c, hipStream_t s);  // near_count = 0 only
+// the list pass's and the near stage's counters = 0 (before the near stage runs again)
+hipError_t launch_reset_near_stage(DevCounters* c, hipStream_t s);
 // near-pair list: every pair with D^2 < (near_dr L)^2 of the n points pts[3][n]
 hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, NearPair* list, unsigned long long cap,
                             DevCounters* ctr, hipStream_t s);
@@ -183,25 +187,26 @@ struct NearWork {
     void* temp;                        // scan workspace
     size_t temp_bytes;
 };
-// cost classes of near pairs: 128 classes of the estimated subdivision depth x 2 element kinds
+// cost classes of near pairs: class 0 holds the pairs whose point lies on the element (exact
+// integral, no subdivision); classes 2 .. 255: 127 classes of the estimated subdivision depth x
+// 2 element kinds
 constexpr int kCostClasses = 256;
-constexpr size_t kNearWorkBytesPerPair = 2 * sizeof(NearPair) + 3 * sizeof(uint32_t) + 1;  // + rows x 8
+constexpr int kOnElementClass = 0;
 size_t near_scan_temp_bytes(int64_t n);
 hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int rows);  // frees w first
 void near_work_free(NearWork& w);
-// stream-ordered allocation and release of one batch's buffers (w empty before the allocation)
-hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipMemPool_t pool,
-                                 hipStream_t s);
-void near_work_free_async(NearWork& w, hipStream_t s);
-size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows);  // device bytes of those buffers
 // regroup the list (length read from ctr) into per-point segments sorted by element, and
 // order the list indices by estimated subdivision cost (w.order) for the near kernel;
 // pts [3][n] are the field points of the list (the centroids for collocation)
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
                       const double* pts, const Elements& el, const NearWork& w, hipStream_t s);
-// add each point's segment of per-pair result records to its outputs
+// entries of w.order that the subdivision walk takes (device pointer; set by near_order)
+inline const uint32_t* near_walk_end(const NearWork& w) { return w.buckets + kCostClasses + kOnElementClass; }
+// add each point's segment of per-pair result records to its outputs; base (field mode
+// only): rows [4][n] (phi, E) that the sums are added to instead (outputs = base + near)
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s,
+                       const double* base = nullptr);
 constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 
 // Allocation-free evaluation (noalloc.hip): a static device array per GPU, carved into the

@@ -14,13 +14,17 @@
 //                      subdivision of its pair depth first (triangle: four midpoint
 //                      children; rectangle: 2 x 2) using lattice coordinates instead of a
 //                      stack; a child at DR >= near_dr of its own (or at the depth cap) gets
-//                      the element's rule; a point lying on its element gets the exact
-//                      polar integral.  Lanes take pairs from a shared cursor, the most
+//                      the element's rule.  Lanes take pairs from a shared cursor, the most
 //                      expensive first (near_order.hip).  Each pair's result goes to its
-//                      own slot in
-//                      (point, element) order; the per-point sums are formed in that order
-//                      afterwards (near_order.hip), so results are reproducible bit for bit.
+//                      own slot in (point, element) order; the per-point sums are formed in
+//                      that order afterwards (near_order.hip), so results are reproducible
+//                      bit for bit.
+//  on_element_kernel   pairs whose point lies on the element (found by the cost pass, last in
+//                      the order): the exact polar integral, one lane per pair.  Kept out of
+//                      the walk so that the walk's register footprint stays at 128 VGPRs:
+//                      its workgroups then fit beside the far kernels of other streams.
 #include "bemc_internal.h"
+#include "on_element.h"
 
 namespace bemc {
 
@@ -1332,10 +1336,11 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     constexpr bool GRAD = MODE == kNearGrad;
     const Elements& el = a.el;
     const int64_t ne = el.ne;
-    const unsigned long long total = min(a.ctr->near_count, a.near_cap);
+    // the walks: the leading entries of the order (the points lying on their element follow)
+    const unsigned long long total = *a.walk_end;
     const int lane = lane_id();
 
-    unsigned long long n_leaves = 0, n_cap = 0, n_on = 0, n_limit = 0;
+    unsigned long long n_leaves = 0, n_cap = 0, n_limit = 0;
     int max_level = 0;
 
     bool active = false;
@@ -1396,100 +1401,8 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 active = true;
                 st.level = 0; st.i = 0; st.j = 0; st.up = true;
 
-                // ---- point on the element: exact polar integral about the point (in three
-                // dimensions, relative to the first vertex)
-                double G[9];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) G[c] = el.geom[(int64_t)c * ne + e];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) P[c] -= G[c];
-                const double L = el.L[e];
-                const double nx = el.nrm[e], ny = el.nrm[ne + e], nz = el.nrm[2 * ne + e];
-                const double dx = P[0] - (el.cen[e] - el.geom[e]);
-                const double dy = P[1] - (el.cen[ne + e] - el.geom[ne + e]);
-                const double dz = P[2] - (el.cen[2 * ne + e] - el.geom[2 * ne + e]);
-                bool on = fabs(nx * dx + ny * dy + nz * dz) <= 1e-12 * L;
-                double V[4][3];
-                int nv;
-                if (st.kind == 0) {
-                    nv = 3;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        V[0][c] = 0.0; V[1][c] = G[3 + c] - G[c]; V[2][c] = G[6 + c] - G[c]; V[3][c] = 0.0;
-                    }
-                } else {
-                    nv = 4;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        V[0][c] = 0.0; V[1][c] = G[3 + c];
-                        V[2][c] = G[3 + c] + G[6 + c]; V[3][c] = G[6 + c];
-                    }
-                }
-                if (on) {  // inside test
-                    if (st.kind == 0) {
-                        const double twoA = 2.0 * el.area[e];
-                        for (int k = 0; k < 3 && on; ++k) {
-                            const double* Va = V[(k + 1) % 3];
-                            const double* Vb = V[(k + 2) % 3];
-                            const double ax = Va[0] - P[0], ay = Va[1] - P[1], az = Va[2] - P[2];
-                            const double bx = Vb[0] - P[0], by = Vb[1] - P[1], bz = Vb[2] - P[2];
-                            const double cxp = ay * bz - az * by, cyp = az * bx - ax * bz, czp = ax * by - ay * bx;
-                            on = (nx * cxp + ny * cyp + nz * czp) / twoA >= -1e-12;
-                        }
-                    } else {
-                        const double x = 2.0 * (dx * G[3] + dy * G[4] + dz * G[5]) / (G[3] * G[3] + G[4] * G[4] + G[5] * G[5]);
-                        const double y = 2.0 * (dx * G[6] + dy * G[7] + dz * G[8]) / (G[6] * G[6] + G[7] * G[7] + G[8] * G[8]);
-                        on = fabs(x) <= 1.0 + 1e-12 && fabs(y) <= 1.0 + 1e-12;
-                    }
-                }
-                if (on) {
-                    // per edge at distance h with end offsets t1, t2 (rho^2 = h^2 + t^2):
-                    //   potential h [asinh(t/h)],  field -n [(t/rho)(1 + ln rho) - asinh(t/h)] + h t [(1 + ln rho)/rho]
-                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                    for (int k = 0; k < nv; ++k) {
-                        const double* Va = V[k];
-                        const double* Vb = V[(k + 1) % nv];
-                        double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
-                        const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
-                        tv[0] /= len; tv[1] /= len; tv[2] /= len;
-                        const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
-                        const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
-                        const double t2 = t1 + len;
-                        double fn[3] = { pa[0] - t1 * tv[0], pa[1] - t1 * tv[1], pa[2] - t1 * tv[2] };
-                        const double hh = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
-                        if (!(hh > 1e-14 * L)) continue;
-                        fn[0] /= hh; fn[1] /= hh; fn[2] /= hh;
-                        const double r1 = sqrt(hh * hh + t1 * t1), r2 = sqrt(hh * hh + t2 * t2);
-                        const double as = asinh(t2 / hh) - asinh(t1 / hh);
-                        s0 += hh * as;
-                        const double l1 = 1.0 + log(r1), l2 = 1.0 + log(r2);
-                        const double gn = (t2 / r2) * l2 - (t1 / r1) * l1 - as;
-                        const double gt = hh * (l2 / r2 - l1 / r1);
-                        s1 += -gn * fn[0] + gt * tv[0];
-                        s2 += -gn * fn[1] + gt * tv[1];
-                        s3 += -gn * fn[2] + gt * tv[2];
-                    }
-                    const double inv_area = 1.0 / el.area[e];
-                    const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
-                    if (COLLOC) {
-                        a.res[cur] = s0 * inv_area;
-                    } else if (GRAD) {  // the normal field jumps across the element: no gradient there
-                        const double nan = __builtin_nan("");
-                        double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
-                        r[0] = make_double2(nan, nan);
-                        r[1] = make_double2(nan, nan);
-                        r[2] = make_double2(nan, nan);
-                    } else {
-                        reinterpret_cast<double4*>(a.res)[cur] = make_double4(
-                            Kq * (s0 * inv_area), Kq * (s1 * inv_area), Kq * (s2 * inv_area), Kq * (s3 * inv_area));
-                    }
-                    n_on++;
-                    active = false;  // finished: the record is written
-                } else if (a.max_depth <= 0) {
-                    st.level = 0;  // evaluate the rule on the element itself (depth cap)
-                } else {
-                    st.level = 1; st.i = 0; st.j = 0; st.up = true;  // first child of the root
-                }
+                if (a.max_depth <= 0) st.level = 0;  // evaluate the rule on the element itself (depth cap)
+                else st.level = 1;                   // first child of the root
             }
         }
 
@@ -1585,9 +1498,82 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     // per-lane counters -> one atomic per counter per lane that has something to add
     if (n_leaves) atomicAdd(&a.ctr->leaves, n_leaves);
     if (n_cap) atomicAdd(&a.ctr->cap_hits, n_cap);
-    if (n_on) atomicAdd(&a.ctr->on_surface, n_on);
     if (n_limit) atomicAdd(&a.ctr->visit_limit_hits, n_limit);
     if (max_level) atomicMax(&a.ctr->max_depth, (unsigned long long)max_level);
+}
+
+// Pairs whose field point lies on the element (the trailing entries of the order, from
+// *walk_end to the pair count): the exact integral about the point, one lane per pair.  Per
+// edge at distance h from the point with end offsets t1, t2 along it (rho^2 = h^2 + t^2):
+// potential h [asinh(t/h)], field -n [(t/rho)(1 + ln rho) - asinh(t/h)] + h t [(1 + ln rho)/rho]
+// (n the unit vector from the point's foot on the edge line towards the point's side).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void on_element_kernel(NearArgs a)
+{
+    constexpr bool COLLOC = MODE == kNearColloc;
+    constexpr bool GRAD = MODE == kNearGrad;
+    const Elements& el = a.el;
+    const int64_t ne = el.ne;
+    const unsigned long long total = min(a.ctr->near_count, a.near_cap);
+    unsigned long long n_on = 0;
+    for (unsigned long long w = *a.walk_end + (unsigned long long)blockIdx.x * kBlock + threadIdx.x; w < total;
+         w += (unsigned long long)gridDim.x * kBlock) {
+        const uint32_t li = a.order[w];
+        const unsigned long long cur = a.slot[li];
+        const NearPair pr = a.near_list[li];
+        const int64_t e = pr.elem, p = pr.point;
+        const bool tri = e < el.n_tri;
+        double X[3];
+        if (COLLOC) {
+            X[0] = el.cen[p]; X[1] = el.cen[ne + p]; X[2] = el.cen[2 * ne + p];
+        } else {
+            X[0] = a.pts[p]; X[1] = a.pts[a.n + p]; X[2] = a.pts[2 * a.n + p];
+        }
+        double G[9], P[3], V[4][3];
+        point_on_element(el, e, tri, X, G, P);  // (true: the cost pass put the pair here)
+        const int nv = element_corners(el, e, tri, G, V);
+        const double L = el.L[e];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int k = 0; k < nv; ++k) {
+            const double* Va = V[k];
+            const double* Vb = V[(k + 1) % nv];
+            double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
+            const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+            tv[0] /= len; tv[1] /= len; tv[2] /= len;
+            const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
+            const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
+            const double t2 = t1 + len;
+            double fn[3] = { pa[0] - t1 * tv[0], pa[1] - t1 * tv[1], pa[2] - t1 * tv[2] };
+            const double hh = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
+            if (!(hh > 1e-14 * L)) continue;
+            fn[0] /= hh; fn[1] /= hh; fn[2] /= hh;
+            const double r1 = sqrt(hh * hh + t1 * t1), r2 = sqrt(hh * hh + t2 * t2);
+            const double as = asinh(t2 / hh) - asinh(t1 / hh);
+            s0 += hh * as;
+            const double l1 = 1.0 + log(r1), l2 = 1.0 + log(r2);
+            const double gn = (t2 / r2) * l2 - (t1 / r1) * l1 - as;
+            const double gt = hh * (l2 / r2 - l1 / r1);
+            s1 += -gn * fn[0] + gt * tv[0];
+            s2 += -gn * fn[1] + gt * tv[1];
+            s3 += -gn * fn[2] + gt * tv[2];
+        }
+        const double inv_area = 1.0 / el.area[e];
+        if (COLLOC) {
+            a.res[cur] = s0 * inv_area;
+        } else if (GRAD) {  // the normal field jumps across the element: no gradient there
+            const double nan = __builtin_nan("");
+            double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
+            r[0] = make_double2(nan, nan);
+            r[1] = make_double2(nan, nan);
+            r[2] = make_double2(nan, nan);
+        } else {
+            const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
+            reinterpret_cast<double4*>(a.res)[cur] = make_double4(
+                Kq * (s0 * inv_area), Kq * (s1 * inv_area), Kq * (s2 * inv_area), Kq * (s3 * inv_area));
+        }
+        n_on++;
+    }
+    if (n_on) atomicAdd(&a.ctr->on_surface, n_on);
 }
 
 // ---------------------------------------------------------------- small kernels -----
@@ -1734,11 +1720,17 @@ hipError_t launch_far_grad(const FarArgs& a, int precision, hipStream_t s)
 
 hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
 {
-    // persistent lanes; every lane leaves once the shared cursor passes the pair count
-    const int blocks = 1024;
+    // persistent lanes (no more than the list can hold pairs); every lane leaves once the
+    // shared cursor passes the pair count
+    const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>(1024, (a.near_cap + kBlock - 1) / kBlock));
     if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, 0, s>>>(a);
     else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, 0, s>>>(a);
     else near_kernel<kNearEval><<<blocks, kBlock, 0, s>>>(a);
+    // points on their element: rare for field points, one per element for collocation
+    const unsigned on_blocks = (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>(256, (a.near_cap + kBlock - 1) / kBlock));
+    if (mode == kNearColloc) on_element_kernel<kNearColloc><<<on_blocks, kBlock, 0, s>>>(a);
+    else if (mode == kNearGrad) on_element_kernel<kNearGrad><<<on_blocks, kBlock, 0, s>>>(a);
+    else on_element_kernel<kNearEval><<<on_blocks, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1859,6 +1851,24 @@ __global__ void divide_kernel(double* __restrict__ y, const double* __restrict__
 }
 
 __global__ void reset_near_count_kernel(DevCounters* c) { c->near_count = 0ull; }
+
+// everything the list pass and the near stage count; the far field's term counts stay
+__global__ void reset_near_stage_kernel(DevCounters* c)
+{
+    c->near_count = 0ull;
+    c->cursor = 0ull;
+    c->leaves = 0ull;
+    c->cap_hits = 0ull;
+    c->on_surface = 0ull;
+    c->max_depth = 0ull;
+    c->visit_limit_hits = 0ull;
+}
+
+hipError_t launch_reset_near_stage(DevCounters* c, hipStream_t s)
+{
+    reset_near_stage_kernel<<<1, 1, 0, s>>>(c);
+    return hipGetLastError();
+}
 
 hipError_t launch_reset_near_count(DevCounters* c, hipStream_t s)
 {

@@ -19,6 +19,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"
+#include "on_element.h"
 
 namespace bemc {
 
@@ -30,35 +31,6 @@ __device__ __forceinline__ unsigned long long pair_total(const DevCounters* ctr,
 {
     const unsigned long long c = ctr->near_count;
     return c < cap ? c : cap;
-}
-
-__global__ void zero_u32_kernel(uint32_t* __restrict__ a, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) a[i] = 0u;
-}
-
-__global__ void count_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
-                             unsigned long long cap, uint32_t* __restrict__ count)
-{
-    const unsigned long long total = pair_total(ctr, cap);
-    for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (unsigned long long)gridDim.x * kBlock)
-        atomicAdd(&count[list[i].point], 1u);
-}
-
-__global__ void scatter_pairs_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
-                                     unsigned long long cap, const uint32_t* __restrict__ start,
-                                     uint32_t* __restrict__ cursor, NearPair* __restrict__ grouped,
-                                     uint32_t* __restrict__ origin)
-{
-    const unsigned long long total = pair_total(ctr, cap);
-    for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (unsigned long long)gridDim.x * kBlock) {
-        const NearPair pr = list[i];
-        const uint32_t pos = start[pr.point] + atomicAdd(&cursor[pr.point], 1u);
-        grouped[pos] = pr;
-        origin[pos] = (uint32_t)i;
-    }
 }
 
 // Sorts each point's segment by element index, one wavefront per point: every entry's
@@ -91,12 +63,12 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
                                     int64_t n, const NearPair* __restrict__ sorted, const double* __restrict__ res,
                                     int mode, double* __restrict__ phi,
                                     double* __restrict__ E, double* __restrict__ G, const double* __restrict__ q,
-                                    int64_t ne, int n_rhs, double K)
+                                    int64_t ne, int n_rhs, double K, const double* __restrict__ base)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t s = start[p], k = count[p];
-    if (k == 0) return;
+    if (k == 0 && !base) return;
     if (mode == kNearColloc) {
         for (int r = 0; r < n_rhs; ++r) {
             double acc = 0.0;
@@ -110,24 +82,34 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
     for (int c = 0; c < rows; ++c) {
         double acc = 0.0;
         for (uint32_t m = 0; m < k; ++m) acc += res[(unsigned long long)(s + m) * rec + c];
-        if (mode == kNearGrad) G[(int64_t)c * n + p] += acc;
-        else if (c == 0) phi[p] += acc;
-        else E[(int64_t)(c - 1) * n + p] += acc;
+        if (mode == kNearGrad) {
+            G[(int64_t)c * n + p] += acc;
+        } else {
+            double* out = c == 0 ? phi + p : E + (int64_t)(c - 1) * n + p;
+            *out = (base ? base[(int64_t)c * n + p] : *out) + acc;
+        }
     }
 }
 
 // Cost class of a near pair (higher = more subdivision leaves expected): 4 classes per
 // octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the element's
 // plane, rho the in-plane distance from the centroid, R the distance of the farthest
-// vertex from it), times 2 for the element kind.  A point on the element (d = 0: the polar
-// integral, no subdivision) takes the cheapest class.
+// vertex from it), times 2 for the element kind; the costliest class where d vanishes
+// without the point lying on the element.  A point on the element (the closed-form
+// integral, no subdivision) takes class kOnElementClass, which the order puts last and the
+// subdivision walk leaves to the on-element kernel.
 __device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_t n, const Elements& el, NearPair pr)
 {
     const int64_t ne = el.ne, e = pr.elem, p = pr.point;
+    const bool tri = e < el.n_tri;
+    {
+        const double X[3] = { pts[p], pts[n + p], pts[2 * n + p] };
+        double G[9], P[3];
+        if (point_on_element(el, e, tri, X, G, P)) return kOnElementClass;
+    }
     const double dx = pts[p] - el.cen[e], dy = pts[n + p] - el.cen[ne + e], dz = pts[2 * n + p] - el.cen[2 * ne + e];
     const double h = fabs(dx * el.nrm[e] + dy * el.nrm[ne + e] + dz * el.nrm[2 * ne + e]);
     const double rho = sqrt(fmax(fma(dx, dx, fma(dy, dy, dz * dz)) - h * h, 0.0));
-    const bool tri = e < el.n_tri;
     double R2 = 0.0;
     if (tri) {
 #pragma unroll
@@ -145,16 +127,30 @@ __device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_
     const double out = fmax(rho - sqrt(R2), 0.0);
     const double d2 = fma(out, out, h * h);
     const double L = el.L[e];
-    int c = 0;
+    int c = 127;
     if (d2 > 1e-24 * L * L) c = min(127, max(1, (int)floor(4.0 * (log2(L) - 0.5 * log2(d2)) + 16.0)));
     return 2 * c + (tri ? 0 : 1);
 }
 
-// Per-class counts (per-workgroup histograms in LDS, one global atomic per class and
-// workgroup) and the class of every list index.
+// Clears the per-class counts and cursors (buckets) and the per-point counts and cursors.
+__global__ void clear_order_kernel(uint32_t* __restrict__ buckets, uint32_t* __restrict__ count,
+                                   uint32_t* __restrict__ cursor, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        count[i] = 0u;
+        cursor[i] = 0u;
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 3 * kCostClasses; i += kBlock) buckets[i] = 0u;
+}
+
+// The class of every list index and the per-class counts (per-workgroup histograms in LDS,
+// one global atomic per class and workgroup); the near pairs of each point.
 __global__ void cost_count_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
                                   unsigned long long cap, const double* __restrict__ pts, int64_t n, Elements el,
-                                  uint8_t* __restrict__ cost, uint32_t* __restrict__ count)
+                                  uint8_t* __restrict__ cost, uint32_t* __restrict__ buckets,
+                                  uint32_t* __restrict__ count)
 {
     __shared__ uint32_t hist[kCostClasses];
     hist[threadIdx.x] = 0u;  // kBlock == kCostClasses
@@ -162,36 +158,38 @@ __global__ void cost_count_kernel(const NearPair* __restrict__ list, const DevCo
     const unsigned long long total = pair_total(ctr, cap);
     for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (unsigned long long)gridDim.x * kBlock) {
-        const int c = cost_class(pts, n, el, list[i]);
+        const NearPair pr = list[i];
+        const int c = cost_class(pts, n, el, pr);
         cost[i] = (uint8_t)c;
         atomicAdd(&hist[c], 1u);
+        atomicAdd(&count[pr.point], 1u);
     }
     __syncthreads();
-    if (hist[threadIdx.x]) atomicAdd(&count[threadIdx.x], hist[threadIdx.x]);
+    if (hist[threadIdx.x]) atomicAdd(&buckets[threadIdx.x], hist[threadIdx.x]);
 }
 
-// Start of each class in the order, most expensive class first (one workgroup); cursors
-// cleared.
-__global__ void cost_scan_kernel(uint32_t* __restrict__ buckets)
-{
-    __shared__ uint32_t cnt[kCostClasses];
-    const int c = threadIdx.x;
-    cnt[c] = buckets[c];
-    __syncthreads();
-    uint32_t start = 0;
-    for (int k = kCostClasses - 1; k > c; --k) start += cnt[k];
-    buckets[kCostClasses + c] = start;
-    buckets[2 * kCostClasses + c] = 0u;
-}
-
-// order[start[class] + rank] = list index; ranks within a workgroup's chunk from LDS
-// atomics, one global atomic per class and chunk.
+// Both scatters of the list.  By cost: order[start[class] + rank] = list index, ranks within
+// a workgroup's chunk from LDS atomics, one global atomic per class and chunk (each workgroup
+// forms the class starts itself, most expensive class first; the first one stores them).  By
+// point: each pair to its point's segment (start from the scan of the per-point counts),
+// with its list index.
 constexpr int kCostItems = 8;  // list entries per thread and chunk
-__global__ void cost_scatter_kernel(const DevCounters* __restrict__ ctr, unsigned long long cap,
-                                    const uint8_t* __restrict__ cost, uint32_t* __restrict__ buckets,
-                                    uint32_t* __restrict__ order)
+__global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
+                               unsigned long long cap, const uint8_t* __restrict__ cost,
+                               uint32_t* __restrict__ buckets, uint32_t* __restrict__ order,
+                               const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
+                               NearPair* __restrict__ grouped, uint32_t* __restrict__ origin)
 {
-    __shared__ uint32_t hist[kCostClasses], base[kCostClasses];
+    __shared__ uint32_t hist[kCostClasses], base[kCostClasses], first[kCostClasses];
+    {
+        hist[threadIdx.x] = buckets[threadIdx.x];
+        __syncthreads();
+        uint32_t st = 0;
+        for (int k = kCostClasses - 1; k > (int)threadIdx.x; --k) st += hist[k];
+        first[threadIdx.x] = st;
+        if (blockIdx.x == 0) buckets[kCostClasses + threadIdx.x] = st;
+        __syncthreads();
+    }
     const unsigned long long total = pair_total(ctr, cap);
     const unsigned long long chunk = (unsigned long long)kBlock * kCostItems;
     for (unsigned long long c0 = (unsigned long long)blockIdx.x * chunk; c0 < total;
@@ -207,13 +205,15 @@ __global__ void cost_scatter_kernel(const DevCounters* __restrict__ ctr, unsigne
             if (i < total) {
                 cls[k] = cost[i];
                 rank[k] = atomicAdd(&hist[cls[k]], 1u);
+                const NearPair pr = list[i];
+                const uint32_t pos = start[pr.point] + atomicAdd(&cursor[pr.point], 1u);
+                grouped[pos] = pr;
+                origin[pos] = (uint32_t)i;
             }
         }
         __syncthreads();
         const uint32_t cnt = hist[threadIdx.x];
-        base[threadIdx.x] = cnt ? buckets[kCostClasses + threadIdx.x] +
-                                      atomicAdd(&buckets[2 * kCostClasses + threadIdx.x], cnt)
-                                : 0u;
+        base[threadIdx.x] = cnt ? first[threadIdx.x] + atomicAdd(&buckets[2 * kCostClasses + threadIdx.x], cnt) : 0u;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kCostItems; ++k) {
@@ -267,51 +267,6 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
     return e;
 }
 
-// Stream-ordered variants (serving: buffers of one batch, allocated from the server's pool
-// and released on the batch's stream without waiting for other streams).
-void near_work_free_async(NearWork& w, hipStream_t s)
-{
-    for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
-                       (void*)w.sorted, (void*)w.slot, (void*)w.res, (void*)w.cost, (void*)w.order,
-                       (void*)w.buckets, w.temp })
-        if (ptr) (void)hipFreeAsync(ptr, s);
-    w = NearWork{};
-}
-
-size_t near_work_bytes(int64_t n, unsigned long long pairs, int rows)
-{
-    const size_t np = (size_t)std::max<int64_t>(n, 1), npairs = (size_t)std::max<unsigned long long>(pairs, 1);
-    return np * 3 * sizeof(uint32_t) + npairs * (kNearWorkBytesPerPair + (size_t)rows * sizeof(double)) +
-           3 * kCostClasses * sizeof(uint32_t) + near_scan_temp_bytes(std::max<int64_t>(n, 1));
-}
-
-hipError_t near_work_alloc_async(NearWork& w, int64_t n, unsigned long long pairs, int rows, hipMemPool_t pool,
-                                 hipStream_t s)
-{
-    w = NearWork{};
-    const size_t np = (size_t)std::max<int64_t>(n, 1), npairs = (size_t)std::max<unsigned long long>(pairs, 1);
-    w.temp_bytes = near_scan_temp_bytes(std::max<int64_t>(n, 1));
-    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.count), np * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.start), np * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.cursor), np * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.grouped), npairs * sizeof(NearPair), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.origin), npairs * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.sorted), npairs * sizeof(NearPair), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.slot), npairs * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.cost), npairs, pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t), pool, s);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync(&w.temp, std::max<size_t>(w.temp_bytes, 1), pool, s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        const size_t tb = w.temp_bytes;
-        near_work_free_async(w, s);
-        w.temp_bytes = tb;
-    }
-    return e;
-}
-
 size_t near_scan_temp_bytes(int64_t n)
 {
     size_t bytes = 0;
@@ -322,24 +277,21 @@ size_t near_scan_temp_bytes(int64_t n)
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
                       const double* pts, const Elements& el, const NearWork& w, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
     static_assert(kBlock == kCostClasses, "one thread per cost class");
+    if (n <= 0) {  // no pairs: the walk's share (near_walk_end) is empty
+        clear_order_kernel<<<1, kBlock, 0, s>>>(w.buckets, w.count, w.cursor, 0);
+        return hipGetLastError();
+    }
     const unsigned lgrid = grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40));
-    zero_u32_kernel<<<1, kBlock, 0, s>>>(w.buckets, kCostClasses);
-    cost_count_kernel<<<lgrid, kBlock, 0, s>>>(list, ctr, cap, pts, n, el, w.cost, w.buckets);
-    cost_scan_kernel<<<1, kCostClasses, 0, s>>>(w.buckets);
-    cost_scatter_kernel<<<std::max(1u, lgrid / kCostItems), kBlock, 0, s>>>(ctr, cap, w.cost, w.buckets, w.order);
-    zero_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(w.count, n);
-    zero_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(w.cursor, n);
-    count_kernel<<<grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40)), kBlock, 0, s>>>(list, ctr, cap,
-                                                                                                  w.count);
+    clear_order_kernel<<<grid_for(n), kBlock, 0, s>>>(w.buckets, w.count, w.cursor, n);
+    cost_count_kernel<<<lgrid, kBlock, 0, s>>>(list, ctr, cap, pts, n, el, w.cost, w.buckets, w.count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t bytes = w.temp_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(w.temp, bytes, w.count, w.start, (int)n, s);
     if (e != hipSuccess) return e;
-    scatter_pairs_kernel<<<grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40)), kBlock, 0, s>>>(
-        list, ctr, cap, w.start, w.cursor, w.grouped, w.origin);
+    scatter_kernel<<<std::max(1u, lgrid / kCostItems), kBlock, 0, s>>>(list, ctr, cap, w.cost, w.buckets, w.order,
+                                                                       w.start, w.cursor, w.grouped, w.origin);
     const int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     rank_sort_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(w.start, w.count, n, w.grouped, w.origin, w.sorted, w.slot);
@@ -347,11 +299,13 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
 }
 
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s)
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s,
+                       const double* base)
 {
     if (n <= 0) return hipSuccess;
+    if (base && mode != kNearEval) return hipErrorInvalidValue;
     reduce_pairs_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K);
+        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K, base);
     return hipGetLastError();
 }
 

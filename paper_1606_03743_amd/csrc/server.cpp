@@ -2,25 +2,30 @@
 //
 // Geometry and densities stay resident; each free stream slot takes the longest prefix of
 // a waiting queue (arrival order) whose points fit into one batch and whose device memory
-// fits what the budget has left, runs one far-field launch over all of them (split over
-// element chunks when the batch is small, with a fixed-order reduction of the chunks), the
-// FP64 near field, and copies the results back.  Slots on different streams overlap on
-// the device; queries arriving while batches run are admitted as soon as a slot and memory
-// are free.  Optionally short queries have a queue and a slot of their own (the other slots
-// take them only when no long query waits).
+// fits what the memory budget has left, runs one far-field launch over all of them (split
+// over element chunks when the batch is small, with a fixed-order reduction of the
+// chunks), the FP64 near field, and copies the results back.  Slots on different streams
+// overlap on the device; queries arriving while batches run are admitted as soon as a slot
+// and memory are free.  Optionally short queries have a queue and a slot of their own (the
+// other slots take them only when no long query waits).
 //
-// Memory: each batch allocates its buffers on its own stream (stream-ordered allocation
-// from the device's pool) when it is admitted and releases them when it completes; the
-// scheduler accounts their bytes against the budget.  A batch runs in two phases: the
-// near-pair list pass, the far field and the chunk reduction are enqueued at admission;
-// once the list pass's pair count has reached the host (about a millisecond later, while
-// the far field runs), the near stage is enqueued -- after growing the batch's list on its
-// own stream when it was too short.  No host wait stalls the other slots, and the far
-// field is never repeated.
+// Memory: one device allocation made at start (the budget, at most twice what full batches
+// on every stream need) is handed out per batch by a first-fit list on the host; a batch
+// takes a block for its per-point buffers and one for its near-pair list when it is admitted
+// and gives both back when it completes; the list is sized from the near-pair density of the
+// batches before it (16 pairs per point at first, then 1.25 x the density seen, raised at
+// once and lowered slowly).  The whole
+// batch is enqueued at admission.  When its list pass found more near pairs than the list
+// holds, the completed batch's far field is kept, the list grows (a larger block) and only
+// the list pass and the near stage run again; a growth that does not fit waits while
+// another batch is running and will give memory back, and otherwise takes its block outside
+// the arena (stream-ordered), so at most one batch at a time exceeds the budget, by its
+// list.  No scheduler step waits on the device.
 #include "server.h"
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 
 namespace bemc {
@@ -30,24 +35,73 @@ namespace {
 // workgroup is short and a batch on another stream gets compute units within a few ms.
 constexpr int kWavesTarget = 16 * 1024;
 constexpr int kMaxServeSplit = 1024;  // element chunks of one serving launch
-constexpr int kSlotSplit = 256;       // partial-sum rows of a slot: kSlotSplit x max_batch_points
+constexpr int kSlotSplit = 256;       // partial-sum rows of a batch: kSlotSplit x max_batch_points
 constexpr int kPointsPerBlock = 512;  // nominal points per workgroup for sizing the split (the
                                        // far kernels hold 256-768, by precision and rule)
-constexpr size_t kNearPairBytes = sizeof(NearPair) + kNearWorkBytesPerPair + 4 * sizeof(double);
+constexpr size_t kGranule = 256;
 
-template <typename T>
-hipError_t alloc_async(T** p, size_t count, hipMemPool_t pool, hipStream_t s)
-{
-    return hipMallocFromPoolAsync(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T), pool, s);
-}
-template <typename T>
-void free_async(T*& p, hipStream_t s)
-{
-    if (p) (void)hipFreeAsync(p, s);
-    p = nullptr;
-}
+size_t up(size_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
 }  // namespace
 
+// ---------------------------------------------------------------------- arena -----
+hipError_t Arena::init(size_t bytes)
+{
+    bytes = up(bytes);
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(&base_), bytes);
+    if (e != hipSuccess) {
+        base_ = nullptr;
+        return e;
+    }
+    size_ = bytes;
+    used_ = 0;
+    free_.clear();
+    free_[0] = bytes;
+    return hipSuccess;
+}
+
+void Arena::destroy()
+{
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    size_ = used_ = 0;
+    free_.clear();
+}
+
+size_t Arena::take(size_t bytes)
+{
+    bytes = up(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        return off;
+    }
+    return kNone;
+}
+
+void Arena::give(size_t off, size_t bytes)
+{
+    if (off == kNone) return;
+    bytes = up(std::max<size_t>(bytes, 1));
+    used_ -= std::min(used_, bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        free_.erase(next);
+    }
+    if (it != free_.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+// --------------------------------------------------------------------- server -----
 double Server::now() const
 {
     using namespace std::chrono;
@@ -77,18 +131,70 @@ int Server::split_for(int64_t n) const
         1, std::min({ kWavesTarget / std::max<int64_t>(1, blocks), cap, env_.el.ne / 64, (int64_t)kMaxServeSplit }));
 }
 
-unsigned long long Server::initial_near(int64_t n) const
+unsigned long long Server::initial_near(int64_t n, bool base) const
 {
-    return (unsigned long long)std::max<int64_t>(4096, 16 * n);
+    const double pairs = std::ceil((base ? 16.0 : pairs_per_point_) * (double)n);
+    return (unsigned long long)std::min<double>(std::max<double>(4096.0, pairs), (double)kMaxNearPairs);
 }
 
-// points, potential and field, element-chunk partial sums, near-pair list with its
-// regrouping, cost order and result records, per-point segments and scan workspace
-size_t Server::batch_bytes(int64_t n, unsigned long long near_pairs) const
+// points, far results, far + near results, partial sums for the batch's element chunks, the
+// near stage's per-point segments and scan workspace
+size_t Server::fix_bytes(int64_t n) const
 {
     const int ns = split_for(n);
-    return (size_t)n * 8 * (3 + 1 + 3) + (ns > 1 ? (size_t)ns * 4 * 8 * (size_t)n : 0) +
-           near_pairs * sizeof(NearPair) + near_work_bytes(n, near_pairs, 4);
+    return up((size_t)n * 8 * 3) + 2 * up((size_t)n * 8 * 4) + (ns > 1 ? up((size_t)ns * 4 * 8 * (size_t)n) : 0) +
+           3 * up((size_t)n * 4) + up(near_scan_temp_bytes(std::max<int64_t>(n, 1)));
+}
+
+// the near-pair list, its regrouping, cost order and result records (4 rows)
+size_t Server::pair_bytes(int64_t, unsigned long long pairs)
+{
+    const size_t p = (size_t)pairs;
+    return up(p * sizeof(NearPair)) * 3 + up(p * 4) * 3 + up(p) + up(p * 4 * 8) + up(3 * kCostClasses * 4);
+}
+
+void Server::carve_fix(Slot& s)
+{
+    const int64_t n = s.n;
+    char* p = arena_.base() + s.fix_off;
+    auto take = [&](size_t b) { char* q = p; p += up(b); return q; };
+    s.d_pts = reinterpret_cast<double*>(take((size_t)n * 8 * 3));
+    s.d_far = reinterpret_cast<double*>(take((size_t)n * 8 * 4));
+    s.d_out = reinterpret_cast<double*>(take((size_t)n * 8 * 4));
+    s.d_partial = s.n_split > 1 ? reinterpret_cast<double*>(take((size_t)s.n_split * 4 * 8 * (size_t)n)) : nullptr;
+    s.nw.count = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
+    s.nw.start = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
+    s.nw.cursor = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
+    s.nw.temp_bytes = near_scan_temp_bytes(std::max<int64_t>(n, 1));
+    s.nw.temp = take(s.nw.temp_bytes);
+}
+
+// the near-pair arrays of a list of s.near_cap pairs in the block at base (pair_bytes of it)
+void Server::carve_pairs(Slot& s, char* base)
+{
+    const size_t c = (size_t)s.near_cap;
+    char* p = base;
+    auto take = [&](size_t b) { char* q = p; p += up(b); return q; };
+    s.d_near = reinterpret_cast<NearPair*>(take(c * sizeof(NearPair)));
+    s.nw.grouped = reinterpret_cast<NearPair*>(take(c * sizeof(NearPair)));
+    s.nw.sorted = reinterpret_cast<NearPair*>(take(c * sizeof(NearPair)));
+    s.nw.origin = reinterpret_cast<uint32_t*>(take(c * 4));
+    s.nw.slot = reinterpret_cast<uint32_t*>(take(c * 4));
+    s.nw.order = reinterpret_cast<uint32_t*>(take(c * 4));
+    s.nw.cost = reinterpret_cast<uint8_t*>(take(c));
+    s.nw.res = reinterpret_cast<double*>(take(c * 4 * 8));
+    s.nw.buckets = reinterpret_cast<uint32_t*>(take(3 * kCostClasses * 4));
+}
+
+void Server::release(Slot& s)
+{
+    arena_.give(s.fix_off, s.fix_bytes);
+    arena_.give(s.pair_off, s.pair_bytes);
+    if (s.spill) (void)hipFreeAsync(s.spill, s.stream);
+    s.spill = nullptr;
+    s.fix_off = s.pair_off = Arena::kNone;
+    s.fix_bytes = s.pair_bytes = 0;
+    s.near_cap = 0;
 }
 
 bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::string& err)
@@ -105,44 +211,28 @@ bool Server::init(const ServerEnv& env, const bemc_server_config& cfg, std::stri
     const int64_t M = cfg.max_batch_points;
     const int64_t blocks = (M + kPointsPerBlock - 1) / kPointsPerBlock;
     max_split_ = (int)std::max<int64_t>(1, std::min<int64_t>(kSlotSplit, kWavesTarget / std::max<int64_t>(1, blocks)));
-    if (batch_bytes(M, initial_near(M)) > cfg.mem_budget_bytes) {
+    const size_t full = fix_bytes(M) + pair_bytes(M, initial_near(M, true));
+    if (full > cfg.mem_budget_bytes) {
         err = "memory budget too small for one batch of max_batch_points";
         return false;
     }
     if (hipSetDevice(env.device) != hipSuccess) { err = "hipSetDevice"; return false; }
-    // the server's own memory pool: released batch memory stays in it (up to the budget)
-    // instead of going back to the driver at every synchronisation, and memory released on
-    // one stream is reused on another only once that release has completed (no dependency
-    // between the streams is ever inserted: a short batch never waits for a long one)
-    hipMemPoolProps props{};
-    props.allocType = hipMemAllocationTypePinned;
-    props.handleTypes = hipMemHandleTypeNone;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = env.device;
-    if (hipMemPoolCreate(&pool_, &props) != hipSuccess) {
+    // the budget, but no more than twice what full batches on every stream need (room for
+    // near-list growth)
+    const size_t arena = std::min<size_t>(cfg.mem_budget_bytes, 2 * full * (size_t)cfg.n_streams);
+    if (arena_.init(arena) != hipSuccess) {
         (void)hipGetLastError();
-        pool_ = nullptr;
-        err = "could not create the batch memory pool";
-        return false;
-    }
-    uint64_t thr = cfg.mem_budget_bytes;
-    int no = 0;
-    if (hipMemPoolSetAttribute(pool_, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess ||
-        hipMemPoolSetAttribute(pool_, hipMemPoolReuseAllowInternalDependencies, &no) != hipSuccess) {
-        (void)hipGetLastError();
-        err = "could not configure the batch memory pool";
+        err = "out of device memory for the batch arena";
         return false;
     }
     slots_.resize((size_t)cfg.n_streams);
     for (auto& s : slots_) {
         bool okk = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
-                   hipEventCreateWithFlags(&s.listed, hipEventDisableTiming) == hipSuccess &&
                    hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess &&
                    hipMalloc(reinterpret_cast<void**>(&s.d_ctr), sizeof(DevCounters)) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_pts), (size_t)M * 3 * 8, hipHostMallocDefault) == hipSuccess &&
                    hipHostMalloc(reinterpret_cast<void**>(&s.h_out), (size_t)M * 4 * 8, hipHostMallocDefault) == hipSuccess &&
-                   hipHostMalloc(reinterpret_cast<void**>(&s.h_ctr), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess &&
-                   hipHostMalloc(reinterpret_cast<void**>(&s.h_list), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess;
+                   hipHostMalloc(reinterpret_cast<void**>(&s.h_ctr), sizeof(DevCounters), hipHostMallocDefault) == hipSuccess;
         if (!okk) {
             (void)hipGetLastError();
             err = "out of device or pinned memory for the batch slots";
@@ -225,64 +315,65 @@ void Server::stop()
     if (thread_.joinable()) thread_.join();
     (void)hipSetDevice(env_.device);
     for (auto& s : slots_) {
-        if (s.stream) {
-            free_batch(s);
-            (void)hipStreamSynchronize(s.stream);
-        }
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
         if (s.d_ctr) (void)hipFree(s.d_ctr);
         if (s.h_pts) (void)hipHostFree(s.h_pts);
         if (s.h_out) (void)hipHostFree(s.h_out);
         if (s.h_ctr) (void)hipHostFree(s.h_ctr);
-        if (s.h_list) (void)hipHostFree(s.h_list);
-        if (s.listed) (void)hipEventDestroy(s.listed);
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         s = Slot{};
     }
     slots_.clear();
-    if (pool_) (void)hipMemPoolDestroy(pool_);  // every allocation of it has been released
-    pool_ = nullptr;
+    arena_.destroy();
 }
 
-bool Server::alloc_batch(Slot& s, std::string& err)
+// The near stage of the batch in s (its list holds near_cap pairs): the far field is
+// copied to the output, the near pairs regrouped and ordered, the near field added in
+// fixed order, the results and counters copied to pinned memory, the completion event.
+bool Server::near_stage(Slot& s, std::string& err)
 {
-    const int64_t n = s.n;
-    s.n_split = split_for(n);
-    s.near_cap = initial_near(n);
-    hipError_t e = alloc_async(&s.d_pts, (size_t)n * 3, pool_, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_phi, (size_t)n, pool_, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_E, (size_t)n * 3, pool_, s.stream);
-    if (e == hipSuccess && s.n_split > 1)
-        e = alloc_async(&s.d_partial, (size_t)s.n_split * 4 * (size_t)n, pool_, s.stream);
-    if (e == hipSuccess) e = alloc_async(&s.d_near, (size_t)s.near_cap, pool_, s.stream);
-    if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, s.near_cap, 4, pool_, s.stream);
+    const int64_t n = s.n, ne = env_.el.ne;
+    const double K = coulomb_constant();
+    NearArgs na{};
+    na.el = env_.el;
+    na.rules = env_.rules;
+    na.pts = s.d_pts;
+    na.n = n;
+    na.rhs = 0;
+    na.n_rhs = 1;
+    na.K = K;
+    na.phi = s.d_out;
+    na.E = s.d_out + n;
+    na.near_list = s.d_near;
+    na.near_cap = s.near_cap;
+    na.slot = s.nw.slot;
+    na.order = s.nw.order;
+    na.walk_end = near_walk_end(s.nw);
+    na.res = s.nw.res;
+    na.ctr = s.d_ctr;
+    na.near_dr2 = env_.near_dr * env_.near_dr;
+    na.max_depth = env_.max_depth;
+    na.visit_limit = 1ll << 22;
+    // d_out = d_far + the near field (d_far stays: a repeated near stage starts from it)
+    hipError_t e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, s.stream);
+    if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
+    if (e == hipSuccess)
+        e = near_reduce(s.nw, n, kNearEval, s.d_out, s.d_out + n, nullptr, env_.el.q, ne, 1, K, s.stream, s.d_far);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * 4 * 8, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
     if (e != hipSuccess) {
-        (void)hipGetLastError();
-        err = std::string("batch buffers: ") + hipGetErrorString(e);
-        free_batch(s);
+        err = hipGetErrorString(e);
         return false;
     }
-    s.bytes = batch_bytes(n, s.near_cap);
-    mem_used_ += s.bytes;
+    s.state = kRun;
     return true;
 }
 
-void Server::free_batch(Slot& s)
-{
-    free_async(s.d_pts, s.stream);
-    free_async(s.d_phi, s.stream);
-    free_async(s.d_E, s.stream);
-    free_async(s.d_partial, s.stream);
-    free_async(s.d_near, s.stream);
-    near_work_free_async(s.nw, s.stream);
-    mem_used_ -= std::min(mem_used_, s.bytes);
-    s.bytes = 0;
-    s.near_cap = 0;
-}
-
-// Phase 1, enqueued at admission: copy-in, near-pair list pass (its count copied to the
-// host and marked by s.listed), far field and chunk reduction.
-bool Server::launch_far(Slot& s, std::string& err)
+// The whole batch, enqueued at admission (its blocks are taken): copy-in, near-pair list,
+// far field and chunk reduction, near stage.
+bool Server::launch(Slot& s, std::string& err)
 {
     const int64_t n = s.n;
     // pack points SoA into pinned staging
@@ -301,8 +392,6 @@ bool Server::launch_far(Slot& s, std::string& err)
     hipError_t e = hipMemcpyAsync(s.d_pts, s.h_pts, (size_t)n * 3 * 8, hipMemcpyHostToDevice, s.stream);
     if (e == hipSuccess) e = launch_zero_counters(s.d_ctr, s.stream);
     if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_list, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess) e = hipEventRecord(s.listed, s.stream);
     FarArgs fa{};
     fa.el = env_.el;
     fa.rules = env_.rules;
@@ -311,8 +400,8 @@ bool Server::launch_far(Slot& s, std::string& err)
     fa.rhs = 0;
     fa.n_rhs = 1;
     fa.K = K;
-    fa.phi = s.d_phi;
-    fa.E = s.d_E;
+    fa.phi = s.d_far;
+    fa.E = s.d_far + n;
     fa.partial = s.n_split > 1 ? s.d_partial : nullptr;
     fa.elem_begin = 0;
     fa.elem_end = ne;
@@ -325,100 +414,69 @@ bool Server::launch_far(Slot& s, std::string& err)
     fa.lv = env_.lv;
     if (e == hipSuccess) e = launch_far_eval(fa, cfg_.precision, s.stream);
     if (e == hipSuccess && s.n_split > 1)
-        e = launch_reduce_split(s.d_partial, s.n_split, n, K, s.d_phi, s.d_E, s.stream);
+        e = launch_reduce_split(s.d_partial, s.n_split, n, K, s.d_far, s.d_far + n, s.stream);
     if (e != hipSuccess) {
         err = hipGetErrorString(e);
         return false;
     }
-    s.state = kFar;
-    return true;
+    return near_stage(s, err);
 }
 
-// Phase 2, once the list pass's count is on the host: grow the list on the batch's stream
-// if it was too short (and list again; the far field stays), then regrouping, near field,
-// ordered sums, copy-out.  Returns 1 when the grown list does not fit the memory left while
-// another batch is in its near stage (the batch waits for it), < 0 on an error.
-int Server::near_stage(Slot& s, std::string& err)
+// The batch's list overflowed (its stream is idle): give back the list's block, take one
+// for 1.25 x the pairs found, list again and repeat the near stage.  Returns 1 when the block
+// does not fit now (the batch waits), < 0 on an error.
+int Server::grow(Slot& s, std::string& err)
 {
-    const int64_t n = s.n;
-    const unsigned long long found = s.h_list->near_count;
-    hipError_t e = hipSuccess;
-    if (found > s.near_cap) {
-        if (found > kMaxNearPairs) {
-            err = "near pairs of a batch exceed 2^32 - 1";
-            return BEMC_E_LIMIT;
+    const unsigned long long found = s.h_ctr->near_count;
+    if (found > kMaxNearPairs) {
+        err = "near pairs of a batch exceed 2^32 - 1";
+        return BEMC_E_LIMIT;
+    }
+    arena_.give(s.pair_off, s.pair_bytes);
+    s.pair_off = Arena::kNone;
+    s.pair_bytes = 0;
+    if (s.spill) (void)hipFreeAsync(s.spill, s.stream);
+    s.spill = nullptr;
+    const unsigned long long cap = std::min(found + found / 4, kMaxNearPairs);
+    const size_t b = pair_bytes(s.n, cap);
+    const size_t off = arena_.take(b);
+    s.near_cap = cap;  // before carving: the arrays are laid out for it
+    if (off != Arena::kNone) {
+        s.pair_off = off;
+        s.pair_bytes = b;
+        carve_pairs(s, arena_.base() + off);
+    } else {
+        bool running = false;
+        for (auto& o : slots_) running |= (&o != &s && o.state == kRun);
+        if (running) {
+            s.near_cap = 0;  // no list while it waits (the count to grow to stays in h_ctr)
+            s.state = kGrow;
+            return 1;  // another batch will give memory back
         }
-        const unsigned long long cap = std::min(found + found / 4, kMaxNearPairs);
-        const size_t grown = batch_bytes(n, cap);
-        const size_t extra = grown - std::min(grown, s.bytes);
-        if (mem_used_ + extra > cfg_.mem_budget_bytes) {
-            // wait while another batch is in its near stage: it completes without further
-            // memory and releases its buffers.  Otherwise (the other batches in flight are
-            // waiting for their own pair counts or growths) grow beyond the budget: then this
-            // batch is in its near stage and the others wait for it, so at most one batch at a
-            // time exceeds the budget and no two batches wait for each other.
-            bool draining = false;
-            for (auto& o : slots_) draining |= (&o != &s && o.state == kNear);
-            if (draining) return 1;
-        }
-        free_async(s.d_near, s.stream);
-        near_work_free_async(s.nw, s.stream);
-        e = alloc_async(&s.d_near, (size_t)cap, pool_, s.stream);
-        if (e == hipSuccess) e = near_work_alloc_async(s.nw, n, cap, 4, pool_, s.stream);
-        mem_used_ += extra;
-        s.bytes = grown;
-        if (e != hipSuccess) {
+        // nothing can give memory back: this batch alone goes beyond the budget, by its list
+        if (hipMallocAsync(reinterpret_cast<void**>(&s.spill), b, s.stream) != hipSuccess) {
             (void)hipGetLastError();
-            err = std::string("near-pair list could not be grown: ") + hipGetErrorString(e);
-            s.near_cap = 0;
+            s.spill = nullptr;
+            err = "out of device memory for a batch's near-pair list";
             return BEMC_E_OUT_OF_MEMORY;
         }
-        s.near_cap = cap;
-        e = launch_reset_near_count(s.d_ctr, s.stream);
-        if (e == hipSuccess) e = launch_near_list(s.d_pts, n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
+        carve_pairs(s, s.spill);
     }
-    const int64_t ne = env_.el.ne;
-    const double K = coulomb_constant();
-    NearArgs na{};
-    na.el = env_.el;
-    na.rules = env_.rules;
-    na.pts = s.d_pts;
-    na.n = n;
-    na.rhs = 0;
-    na.n_rhs = 1;
-    na.K = K;
-    na.phi = s.d_phi;
-    na.E = s.d_E;
-    na.near_list = s.d_near;
-    na.near_cap = s.near_cap;
-    na.slot = s.nw.slot;
-    na.order = s.nw.order;
-    na.res = s.nw.res;
-    na.ctr = s.d_ctr;
-    na.near_dr2 = env_.near_dr * env_.near_dr;
-    na.max_depth = env_.max_depth;
-    na.visit_limit = 1ll << 22;
-    if (e == hipSuccess) e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, s.stream);
-    if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
-    if (e == hipSuccess)
-        e = near_reduce(s.nw, n, kNearEval, s.d_phi, s.d_E, nullptr, env_.el.q, ne, 1, K, s.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_phi, (size_t)n * 8, hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_out + n, s.d_E, (size_t)n * 3 * 8, hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+    hipError_t e = launch_reset_near_stage(s.d_ctr, s.stream);  // the near stage runs again from pair 0
+    if (e == hipSuccess) e = launch_near_list(s.d_pts, s.n, env_.el, s.d_near, s.near_cap, s.d_ctr, s.stream);
     if (e != hipSuccess) {
         err = hipGetErrorString(e);
         return BEMC_E_DEVICE;
     }
-    s.state = kNear;
+    if (!near_stage(s, err)) return BEMC_E_DEVICE;
     return 0;
 }
 
-// Every query of the batch ends with `status`; the batch's buffers are released.
+// Every query of the batch ends with `status`; the batch's blocks are given back.
 void Server::fail_batch(Slot& s, int status, const std::string& err)
 {
-    (void)hipStreamSynchronize(s.stream);  // nothing of the batch may still use its buffers
-    free_batch(s);
+    (void)hipStreamSynchronize(s.stream);  // nothing of the batch may still use its blocks
+    release(s);
     std::lock_guard<std::mutex> lk(mu_);
     err_ = err;
     for (uint64_t id : s.queries) {
@@ -435,6 +493,10 @@ void Server::fail_batch(Slot& s, int status, const std::string& err)
 void Server::complete(Slot& s)
 {
     const int64_t n = s.n;
+    if (n > 0) {  // the list size of the next batches follows the near-pair density seen
+        const double want = 1.25 * (double)s.h_ctr->near_count / (double)n;
+        pairs_per_point_ = want > pairs_per_point_ ? want : std::max(16.0, 0.99 * pairs_per_point_ + 0.01 * want);
+    }
     std::vector<uint64_t> ids;
     {
         std::lock_guard<std::mutex> lk(mu_);
@@ -457,7 +519,7 @@ void Server::complete(Slot& s)
         }
         off += q->n;
     }
-    free_batch(s);
+    release(s);
     const double t = now();
     std::lock_guard<std::mutex> lk(mu_);
     for (uint64_t id : ids) {
@@ -477,21 +539,21 @@ void Server::loop()
     std::unique_lock<std::mutex> lk(mu_);
     while (true) {
         bool progressed = false;
-        // completions and second phases (outside the lock: they copy results and enqueue)
+        // completions, list growths (outside the lock: they copy results and enqueue)
         for (auto& s : slots_) {
-            if (s.state == kNear && hipEventQuery(s.done) == hipSuccess) {
-                lk.unlock();
-                complete(s);
-                lk.lock();
-                progressed = true;
-            } else if (s.state == kFar && hipEventQuery(s.listed) == hipSuccess) {
-                lk.unlock();
+            const bool finished = s.state == kRun && hipEventQuery(s.done) == hipSuccess;
+            if (!finished && s.state != kGrow) continue;
+            lk.unlock();
+            if (s.n > 0 && s.h_ctr->near_count > s.near_cap) {  // the list overflowed
                 std::string err;
-                const int rc = near_stage(s, err);
+                const int rc = grow(s, err);
                 if (rc < 0) fail_batch(s, rc, err);
-                lk.lock();
                 progressed |= rc != 1;
+            } else {
+                complete(s);
+                progressed = true;
             }
+            lk.lock();
         }
         // admissions: each free slot takes the longest prefix of its queue that fits one
         // batch and the memory left
@@ -499,15 +561,39 @@ void Server::loop()
             if (s.state != kIdle) continue;
             std::deque<uint64_t>* wq = s.small_only ? &waiting_small_ : (waiting_.empty() ? &waiting_small_ : &waiting_);
             if (wq->empty()) continue;
+            // points of the longest prefix within max_batch_points, then shortened until its
+            // blocks fit the arena
             int64_t pts = 0;
             size_t k = 0;
             for (; k < wq->size(); ++k) {
                 const int64_t qn = queries_[(*wq)[k]].n;
                 if (pts + qn > cfg_.max_batch_points) break;
-                if (pts + qn > 0 && mem_used_ + batch_bytes(pts + qn, initial_near(pts + qn)) > cfg_.mem_budget_bytes) break;
                 pts += qn;
             }
-            if (k == 0) continue;  // the first query waits for memory
+            size_t fo = Arena::kNone, po = Arena::kNone, fb = 0, pb = 0;
+            unsigned long long cap = 0;
+            auto fits = [&](bool base) {
+                fb = fix_bytes(pts);
+                cap = initial_near(pts, base);
+                pb = pair_bytes(pts, cap);
+                fo = arena_.take(fb);
+                po = fo == Arena::kNone ? Arena::kNone : arena_.take(pb);
+                if (po != Arena::kNone) return true;
+                arena_.give(fo, fb);
+                fo = Arena::kNone;
+                return false;
+            };
+            while (k > 0 && pts > 0 && !fits(false)) pts -= queries_[(*wq)[--k]].n;
+            if (k == 0) {
+                // not even the first query with the density seen: with nothing in flight that
+                // could give memory back, it starts with the base list (which always fits)
+                bool busy = false;
+                for (auto& o : slots_) busy |= o.state != kIdle;
+                if (busy) continue;  // the first query waits for memory
+                k = 1;
+                pts = queries_[wq->front()].n;
+                if (!fits(true)) continue;  // (unreachable: one base batch fits the arena)
+            }
             s.queries.assign(wq->begin(), wq->begin() + (std::ptrdiff_t)k);
             wq->erase(wq->begin(), wq->begin() + (std::ptrdiff_t)k);
             s.n = pts;
@@ -523,14 +609,20 @@ void Server::loop()
             std::string err;
             if (pts == 0) {  // only empty queries: nothing to run
                 std::memset(s.h_ctr, 0, sizeof(DevCounters));
-                s.state = kNear;
+                s.state = kRun;
                 if (hipEventRecord(s.done, s.stream) == hipSuccess) continue;
                 err = "hipEventRecord";
-            } else if (alloc_batch(s, err) && launch_far(s, err)) {
-                continue;
+            } else {
+                s.fix_off = fo; s.fix_bytes = fb;
+                s.pair_off = po; s.pair_bytes = pb;
+                s.n_split = split_for(pts);
+                s.near_cap = cap;
+                carve_fix(s);
+                carve_pairs(s, arena_.base() + po);
+                if (launch(s, err)) continue;
             }
             lk.unlock();
-            fail_batch(s, err.rfind("batch buffers", 0) == 0 ? BEMC_E_OUT_OF_MEMORY : BEMC_E_DEVICE, err);
+            fail_batch(s, BEMC_E_DEVICE, err);
             lk.lock();
         }
         bool any_busy = false;
