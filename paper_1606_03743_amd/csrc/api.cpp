@@ -142,6 +142,7 @@ int noalloc_set(int device, NoAllocSet** out)
     W.nw.res = static_cast<double*>(take(C * 4 * 8));
     W.nw.cost = static_cast<uint8_t*>(take(C));
     W.nw.order = static_cast<uint32_t*>(take(C * 4));
+    W.nw.opair = static_cast<NearPair*>(take(C * sizeof(NearPair)));
     W.nw.buckets = static_cast<uint32_t*>(take(3 * kCostClasses * 4));
     W.nw.temp = take(kNoAllocTempBytes);
     W.nw.temp_bytes = kNoAllocTempBytes;
@@ -601,7 +602,8 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     na.el = el; na.rules = fa.rules; na.pts = colloc ? nullptr : pts; na.n = npts; na.rhs = rhs;
     na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_cap = W.near_cap;
     na.ctr = W.ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
-    na.near_list = W.near; na.slot = W.nw.slot; na.order = W.nw.order; na.walk_end = near_walk_end(W.nw);
+    na.near_list = W.near; na.slot = W.nw.slot; na.order = W.nw.order; na.opair = W.nw.opair;
+    na.walk_end = near_walk_end(W.nw);
     na.res = W.nw.res;
     HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, s));
     HIP_TRY(launch_near(na, mode, s));

@@ -128,6 +128,7 @@ struct NearArgs {
     const uint32_t* slot;        // result slot of each list entry
     const uint32_t* order;       // list indices in the order the lanes take them (costly first;
                                  // the pairs whose point lies on the element last)
+    const NearPair* opair;       // the pairs in that order
     const uint32_t* walk_end;    // device: entries of order that subdivide (near_walk_end)
     double* res;                 // per-pair result records at the pairs' slots: [slot][4] field,
                                  // [slot][6] gradient, [slot] collocation
@@ -183,13 +184,15 @@ struct NearWork {
     double* res;                       // [capacity][rows] per-pair result records of the near kernel
     uint8_t* cost;                     // [capacity] cost class of each list index (near_cost_order)
     uint32_t* order;                   // [capacity] list indices, most expensive pairs first
+    NearPair* opair;                   // [capacity] the pairs themselves in that order
     uint32_t* buckets;                 // [3][kCostClasses] count, start, cursor of each cost class
     void* temp;                        // scan workspace
     size_t temp_bytes;
 };
 // cost classes of near pairs: class 0 holds the pairs whose point lies on the element (exact
-// integral, no subdivision); classes 2 .. 255: 127 classes of the estimated subdivision depth x
-// 2 element kinds
+// integral, no subdivision); triangles take classes 1 .. 127 and rectangles 129 .. 255 by the
+// estimated subdivision depth (kind-major: the order runs through the rectangles, then the
+// triangles, each most expensive first)
 constexpr int kCostClasses = 256;
 constexpr int kOnElementClass = 0;
 size_t near_scan_temp_bytes(int64_t n);

@@ -1327,6 +1327,8 @@ __device__ __forceinline__ void near_terms(double w, double da, double db, doubl
     }
 }
 
+constexpr unsigned kNearWindow = 64;  // entries of the order a wavefront claims at a time
+
 // MODE: kNearEval (phi, E at field points), kNearColloc (phi at centroids, several density
 // vectors), kNearGrad (field gradient at field points; NaN for a point on its element).
 template <int MODE>
@@ -1339,6 +1341,17 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     // the walks: the leading entries of the order (the points lying on their element follow)
     const unsigned long long total = *a.walk_end;
     const int lane = lane_id();
+    // the rules' nodes in LDS: a leaf's loop reads them at one address for the whole wavefront
+    // (from global memory every node would be a vector load and a wait for it)
+    extern __shared__ double4 near_rule_nodes[];  // [nt] triangle (la, lb, lc, w), [nr] rectangle (x, y, w, 0)
+    const int nt = a.rules.nt, nr = a.rules.nr;
+    for (int i = threadIdx.x; i < nt + nr; i += kBlock) {
+        const double* src = i < nt ? a.rules.tri + 4 * i : a.rules.rect + 4 * (i - nt);
+        near_rule_nodes[i] = make_double4(src[0], src[1], src[2], src[3]);
+    }
+    __syncthreads();
+    const double4* __restrict__ tri_nodes = near_rule_nodes;
+    const double4* __restrict__ rect_nodes = near_rule_nodes + nt;
 
     unsigned long long n_leaves = 0, n_cap = 0, n_limit = 0;
     int max_level = 0;
@@ -1351,21 +1364,30 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     double p1 = 0.0, p2 = 0.0, p3 = 0.0;  // the field point in the element's frame
     double thr2 = 0.0, acc[7] = { 0, 0, 0, 0, 0, 0, 0 };
     int64_t visits = 0;
+    // the wavefront's window of the order (the same in every lane): kNearWindow consecutive
+    // entries claimed with one atomic, handed to its lanes as they need pairs; consecutive
+    // entries are pairs of one cost class, so the lanes walk trees of one kind and similar size
+    unsigned long long win = 0, win_end = 0;
 
     while (true) {
-        // ---- refill: one atomic per wavefront for all lanes that need a pair
+        // ---- refill from the window (a new window when it is used up)
         const unsigned long long need = __ballot(!active);
         if (need) {
-            const int first = __ffsll((long long)need) - 1;
-            unsigned long long b = 0;
-            if (lane == first) b = atomicAdd(&a.ctr->cursor, (unsigned long long)__popcll(need));
-            b = bcast_u64(b, first);
-            if (!active) {
-                const unsigned long long w = b + lanes_below(need);
+            if (win >= win_end) {
+                const int first = __ffsll((long long)need) - 1;
+                unsigned long long b = 0;
+                if (lane == first) b = atomicAdd(&a.ctr->cursor, (unsigned long long)kNearWindow);
+                win = bcast_u64(b, first);
+                win_end = win + kNearWindow;
+            }
+            const unsigned rank = lanes_below(need);
+            const unsigned long long avail = win_end - win, w = win + rank;
+            win += min(avail, (unsigned long long)__popcll(need));
+            // a lane without an entry (the window ran out) waits for the next one
+            if (!active && rank < avail) {
                 if (w >= total) break;
-                const uint32_t li = a.order[w];  // most expensive pairs first
-                cur = a.slot[li];
-                const NearPair pr = a.near_list[li];
+                const NearPair pr = a.opair[w];  // most expensive pairs first
+                cur = a.slot[a.order[w]];
                 p = pr.point;
                 e = pr.elem;
                 double P[3];
@@ -1407,26 +1429,30 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         }
 
         if (!active) continue;
-        // ---- visit node st
-        const double h = ldexp(1.0, -st.level);
+        // ---- visit nodes from st down to the next leaf (each lane on its own: internal nodes
+        // cost a distance test, so the lanes then take the leaf loop together)
+        double h, qx, qy, qz;
+        bool is_near;
         NodeGeom nd;
-        node_geometry(st, g, h, nd);
-        const double qx = p1 - nd.cx, qy = p2 - nd.cy, qz = p3 - nd.cz;
-        const double D2 = fma(qx, qx, fma(qy, qy, qz * qz));
-        const bool is_near = D2 < thr2 * h * h;
-        ++visits;
-        if (st.level > max_level) max_level = st.level;
-        if (is_near && st.level < a.max_depth && visits <= a.visit_limit) {
+        while (true) {
+            h = ldexp(1.0, -st.level);
+            node_geometry(st, g, h, nd);
+            qx = p1 - nd.cx; qy = p2 - nd.cy; qz = p3 - nd.cz;
+            const double D2 = fma(qx, qx, fma(qy, qy, qz * qz));
+            is_near = D2 < thr2 * h * h;
+            ++visits;
+            if (st.level > max_level) max_level = st.level;
+            if (!(is_near && st.level < a.max_depth && visits <= a.visit_limit)) break;
             to_child(st, 0);
-            continue;
         }
         // leaf: the element's rule on this node, weights scaled by the area ratio h^2
         double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
         if (st.kind == 0) {
             const double q1 = p1 - nd.x0, q2 = p2 - nd.y0, q3 = p3 - nd.z0;
 #pragma unroll 4
-            for (int i = 0; i < a.rules.nt; ++i) {
-                const double lb = a.rules.tri[4 * i + 1], lc = a.rules.tri[4 * i + 2], w = a.rules.tri[4 * i + 3];
+            for (int i = 0; i < nt; ++i) {
+                const double4 q = tri_nodes[i];
+                const double lb = q.y, lc = q.z, w = q.w;
                 const double da = fma(-lb, nd.w1x, fma(-lc, nd.w2x, q1));
                 const double db = fma(-lb, nd.w1y, fma(-lc, nd.w2y, q2));
                 const double dc = fma(-lb, nd.w1z, fma(-lc, nd.w2z, q3));
@@ -1435,8 +1461,9 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         } else {
             const double H1x = h * (0.5 * g.ux), H1y = h * (0.5 * g.uy), H2x = h * (0.5 * g.vx);
 #pragma unroll 4
-            for (int i = 0; i < a.rules.nr; ++i) {
-                const double x = a.rules.rect[4 * i], y = a.rules.rect[4 * i + 1], w = a.rules.rect[4 * i + 2];
+            for (int i = 0; i < nr; ++i) {
+                const double4 q = rect_nodes[i];
+                const double x = q.x, y = q.y, w = q.z;
                 const double da = fma(-x, H1x, fma(-y, H2x, qx));
                 const double db = fma(-x, H1y, qy);
                 near_terms<MODE>(w, da, db, qz, f);
@@ -1518,9 +1545,8 @@ __global__ __launch_bounds__(kBlock) void on_element_kernel(NearArgs a)
     unsigned long long n_on = 0;
     for (unsigned long long w = *a.walk_end + (unsigned long long)blockIdx.x * kBlock + threadIdx.x; w < total;
          w += (unsigned long long)gridDim.x * kBlock) {
-        const uint32_t li = a.order[w];
-        const unsigned long long cur = a.slot[li];
-        const NearPair pr = a.near_list[li];
+        const NearPair pr = a.opair[w];
+        const unsigned long long cur = a.slot[a.order[w]];
         const int64_t e = pr.elem, p = pr.point;
         const bool tri = e < el.n_tri;
         double X[3];
@@ -1723,9 +1749,10 @@ hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
     // persistent lanes (no more than the list can hold pairs); every lane leaves once the
     // shared cursor passes the pair count
     const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>(1024, (a.near_cap + kBlock - 1) / kBlock));
-    if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, 0, s>>>(a);
-    else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, 0, s>>>(a);
-    else near_kernel<kNearEval><<<blocks, kBlock, 0, s>>>(a);
+    const size_t lds = (size_t)(a.rules.nt + a.rules.nr) * sizeof(double4);
+    if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, lds, s>>>(a);
+    else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, lds, s>>>(a);
+    else near_kernel<kNearEval><<<blocks, kBlock, lds, s>>>(a);
     // points on their element: rare for field points, one per element for collocation
     const unsigned on_blocks = (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>(256, (a.near_cap + kBlock - 1) / kBlock));
     if (mode == kNearColloc) on_element_kernel<kNearColloc><<<on_blocks, kBlock, 0, s>>>(a);

@@ -91,11 +91,13 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
     }
 }
 
-// Cost class of a near pair (higher = more subdivision leaves expected): 4 classes per
-// octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the element's
-// plane, rho the in-plane distance from the centroid, R the distance of the farthest
-// vertex from it), times 2 for the element kind; the costliest class where d vanishes
-// without the point lying on the element.  A point on the element (the closed-form
+// Cost class of a near pair (higher = more subdivision leaves expected within a kind): 4
+// classes per octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the
+// element's plane, rho the in-plane distance from the centroid, R the distance of the farthest
+// vertex from it), rectangles above triangles; the costliest class of the kind where d
+// vanishes without the point lying on the element.  Kind-major classes keep the two rules
+// apart: the near kernel's wavefronts take windows of the order far apart in time, and a
+// wavefront whose lanes mix both kinds runs both rule loops.  A point on the element (the closed-form
 // integral, no subdivision) takes class kOnElementClass, which the order puts last and the
 // subdivision walk leaves to the on-element kernel.
 __device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_t n, const Elements& el, NearPair pr)
@@ -129,7 +131,7 @@ __device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_
     const double L = el.L[e];
     int c = 127;
     if (d2 > 1e-24 * L * L) c = min(127, max(1, (int)floor(4.0 * (log2(L) - 0.5 * log2(d2)) + 16.0)));
-    return 2 * c + (tri ? 0 : 1);
+    return tri ? c : 128 + c;
 }
 
 // Clears the per-class counts and cursors (buckets) and the per-point counts and cursors.
@@ -177,6 +179,7 @@ constexpr int kCostItems = 8;  // list entries per thread and chunk
 __global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
                                unsigned long long cap, const uint8_t* __restrict__ cost,
                                uint32_t* __restrict__ buckets, uint32_t* __restrict__ order,
+                               NearPair* __restrict__ opair,
                                const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
                                NearPair* __restrict__ grouped, uint32_t* __restrict__ origin)
 {
@@ -198,6 +201,7 @@ __global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCount
         __syncthreads();
         int cls[kCostItems];
         uint32_t rank[kCostItems];
+        NearPair prs[kCostItems];
 #pragma unroll
         for (int k = 0; k < kCostItems; ++k) {
             const unsigned long long i = c0 + (unsigned long long)k * kBlock + threadIdx.x;
@@ -206,6 +210,7 @@ __global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCount
                 cls[k] = cost[i];
                 rank[k] = atomicAdd(&hist[cls[k]], 1u);
                 const NearPair pr = list[i];
+                prs[k] = pr;
                 const uint32_t pos = start[pr.point] + atomicAdd(&cursor[pr.point], 1u);
                 grouped[pos] = pr;
                 origin[pos] = (uint32_t)i;
@@ -218,7 +223,10 @@ __global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCount
 #pragma unroll
         for (int k = 0; k < kCostItems; ++k) {
             const unsigned long long i = c0 + (unsigned long long)k * kBlock + threadIdx.x;
-            if (cls[k] >= 0) order[base[cls[k]] + rank[k]] = (uint32_t)i;
+            if (cls[k] >= 0) {
+                order[base[cls[k]] + rank[k]] = (uint32_t)i;
+                opair[base[cls[k]] + rank[k]] = prs[k];
+            }
         }
         __syncthreads();
     }
@@ -235,7 +243,7 @@ unsigned grid_for(int64_t n)
 void near_work_free(NearWork& w)
 {
     for (void* ptr : { (void*)w.count, (void*)w.start, (void*)w.cursor, (void*)w.grouped, (void*)w.origin,
-                       (void*)w.sorted, (void*)w.slot, (void*)w.res, (void*)w.cost, (void*)w.order,
+                       (void*)w.sorted, (void*)w.slot, (void*)w.res, (void*)w.cost, (void*)w.order, (void*)w.opair,
                        (void*)w.buckets, w.temp })
         if (ptr) (void)hipFree(ptr);
     w = NearWork{};
@@ -256,6 +264,7 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.res), npairs * (size_t)rows * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.cost), npairs);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.order), npairs * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.opair), npairs * sizeof(NearPair));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&w.buckets), 3 * kCostClasses * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&w.temp, std::max<size_t>(w.temp_bytes, 1));
     if (e != hipSuccess) {
@@ -291,7 +300,8 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
     e = hipcub::DeviceScan::ExclusiveSum(w.temp, bytes, w.count, w.start, (int)n, s);
     if (e != hipSuccess) return e;
     scatter_kernel<<<std::max(1u, lgrid / kCostItems), kBlock, 0, s>>>(list, ctr, cap, w.cost, w.buckets, w.order,
-                                                                       w.start, w.cursor, w.grouped, w.origin);
+                                                                       w.opair, w.start, w.cursor, w.grouped,
+                                                                       w.origin);
     const int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     rank_sort_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(w.start, w.count, n, w.grouped, w.origin, w.sorted, w.slot);

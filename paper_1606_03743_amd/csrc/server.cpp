@@ -150,7 +150,7 @@ size_t Server::fix_bytes(int64_t n) const
 size_t Server::pair_bytes(int64_t, unsigned long long pairs)
 {
     const size_t p = (size_t)pairs;
-    return up(p * sizeof(NearPair)) * 3 + up(p * 4) * 3 + up(p) + up(p * 4 * 8) + up(3 * kCostClasses * 4);
+    return up(p * sizeof(NearPair)) * 4 + up(p * 4) * 3 + up(p) + up(p * 4 * 8) + up(3 * kCostClasses * 4);
 }
 
 void Server::carve_fix(Slot& s)
@@ -181,6 +181,7 @@ void Server::carve_pairs(Slot& s, char* base)
     s.nw.origin = reinterpret_cast<uint32_t*>(take(c * 4));
     s.nw.slot = reinterpret_cast<uint32_t*>(take(c * 4));
     s.nw.order = reinterpret_cast<uint32_t*>(take(c * 4));
+    s.nw.opair = reinterpret_cast<NearPair*>(take(c * sizeof(NearPair)));
     s.nw.cost = reinterpret_cast<uint8_t*>(take(c));
     s.nw.res = reinterpret_cast<double*>(take(c * 4 * 8));
     s.nw.buckets = reinterpret_cast<uint32_t*>(take(3 * kCostClasses * 4));
@@ -349,6 +350,7 @@ bool Server::near_stage(Slot& s, std::string& err)
     na.near_cap = s.near_cap;
     na.slot = s.nw.slot;
     na.order = s.nw.order;
+    na.opair = s.nw.opair;
     na.walk_end = near_walk_end(s.nw);
     na.res = s.nw.res;
     na.ctr = s.d_ctr;
