@@ -546,9 +546,12 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
 
     double* user_phi = phi;
     double* user_E = E;
+    const bool ordered = !colloc && n > kOrderMinPoints;  // Morton order of the points
     if (!colloc) {
-        HIP_TRY(order_points(pts, n, W.ow, s));
-        pts = W.ow.pts;
+        if (ordered) {
+            HIP_TRY(order_points(pts, n, W.ow, s));
+            pts = W.ow.pts;
+        }
         phi = W.ow.res;
         E = E ? W.ow.res + n : nullptr;
     }
@@ -579,11 +582,8 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     HIP_TRY(colloc ? launch_far_colloc(fa, precision, s)
                    : (grad ? launch_far_grad(fa, precision, s) : launch_far_eval(fa, precision, s)));
     HIP_TRY(hipEventRecord(R.ev_far1, s));  // far_ms: the far-field kernel alone
-    if (n_split > 1) {
-        if (colloc) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, phi, s));
-        else if (grad) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, G, s));
-        else HIP_TRY(launch_reduce_split(W.partial, n_split, npts, fa.K, phi, E, s));
-    }
+    // (field and gradient: the chunks are added with the near sums at the end)
+    if (n_split > 1 && colloc) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, phi, s));
 
     if (near_grow && !noalloc) {
         // the far field runs meanwhile; the list pass finished long before it
@@ -607,16 +607,16 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     na.res = W.nw.res;
     HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, s));
     HIP_TRY(launch_near(na, mode, s));
-    HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, s));
-    HIP_TRY(hipEventRecord(R.ev_near1, s));
-    if (!colloc) {
-        if (grad) {
-            HIP_TRY(unorder_rows(W.ow, n, W.ow.res, 6, user_phi, s));
-        } else {
-            HIP_TRY(unorder_rows(W.ow, n, W.ow.res, 1, user_phi, s));
-            if (user_E) HIP_TRY(unorder_rows(W.ow, n, W.ow.res + n, 3, user_E, s));
-        }
+    if (colloc) {
+        HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, s));
+    } else {
+        // far field (chunk sums) + near sums, back to the caller's order, in one pass
+        const int orows = grad ? 6 : (user_E ? 4 : 1);
+        HIP_TRY(near_finish(W.nw, npts, mode, orows, n_split > 1 ? W.partial : nullptr, n_split, (int)rows,
+                            W.ow.res, fa.K, ordered ? W.ow.perm : nullptr, user_phi, grad ? user_phi + n : user_E,
+                            s));
     }
+    HIP_TRY(hipEventRecord(R.ev_near1, s));
     HIP_TRY(hipMemcpyAsync(R.h_ctr, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(R.ev_done, s));
     R.pending = true;

@@ -203,6 +203,13 @@ void near_work_free(NearWork& w);
 // pts [3][n] are the field points of the list (the centroids for collocation)
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
                       const double* pts, const Elements& el, const NearWork& w, hipStream_t s);
+// the final rows of a field or gradient evaluation, in one pass per point: the far field
+// (n_split > 1: K times the chunk partial sums partial[n_split][prow][n]; else far[rows][n])
+// plus the point's near-pair records, stored at perm[p] (or p) of row 0 in d0 and of row
+// r >= 1 in d1 + (r - 1) n
+hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const double* partial, int n_split,
+                       int prow, const double* far, double K, const uint32_t* perm, double* d0, double* d1,
+                       hipStream_t s);
 // entries of w.order that the subdivision walk takes (device pointer; set by near_order)
 inline const uint32_t* near_walk_end(const NearWork& w) { return w.buckets + kCostClasses + kOnElementClass; }
 // add each point's segment of per-pair result records to its outputs; base (field mode
@@ -224,7 +231,10 @@ constexpr int kNoAllocMaxDevices = 64;
 // device address of this GPU's array (device current); taken once per device and kept
 hipError_t noalloc_scratch(int device, void** ptr);
 
-// Morton ordering of field points (order.hip).  Buffers sized for n points.
+// Morton ordering of field points (order.hip).  Buffers sized for n points.  Evaluations of
+// at most kOrderMinPoints points keep the caller's order: the sort's launches would cost more
+// than the coherence it buys them.
+constexpr int64_t kOrderMinPoints = 4096;
 struct OrderWork {
     uint32_t *keys_in, *keys_out, *idx_in, *perm;
     void* temp;

@@ -19,10 +19,11 @@
 //                      own slot in (point, element) order; the per-point sums are formed in
 //                      that order afterwards (near_order.hip), so results are reproducible
 //                      bit for bit.
-//  on_element_kernel   pairs whose point lies on the element (found by the cost pass, last in
-//                      the order): the exact polar integral, one lane per pair.  Kept out of
-//                      the walk so that the walk's register footprint stays at 128 VGPRs:
-//                      its workgroups then fit beside the far kernels of other streams.
+//                      Pairs whose point lies on the element (found by the cost pass, last in
+//                      the order) get the exact polar integral, one lane per pair, after the
+//                      walk loop: kept out of the loop so that the walk's register footprint
+//                      stays near 128 VGPRs, and its workgroups fit beside the far kernels of
+//                      other streams.
 #include "bemc_internal.h"
 #include "on_element.h"
 
@@ -86,19 +87,21 @@ __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e
 // Every (point, element) pair with D^2 < (near_dr L)^2 (the distance-ratio switch, Sec. 2)
 // goes into the near-pair list, compacted per wavefront; pairs past the capacity are
 // counted, not stored.  A workgroup takes kListPoints consecutive points (Morton order:
-// neighbours in space) and bounds them by a box; an element takes the per-point test only
-// when its centroid lies within near_dr L of that box.  Collocation: the points are the
-// centroids themselves (the same [3][n] layout).
+// neighbours in space) and one chunk of the elements (more chunks when the points are few),
+// and bounds the points by a box; an element takes the per-point test only when its
+// centroid lies within near_dr L of that box.  Collocation: the points are the centroids
+// themselves (the same [3][n] layout).
 constexpr int kListPPT = 2;
 constexpr int kListPoints = kBlock * kListPPT;
 
 __global__ __launch_bounds__(kBlock) void near_list_kernel(const double* __restrict__ pts, int64_t n, Elements el,
                                                            NearPair* __restrict__ list, unsigned long long cap,
-                                                           DevCounters* __restrict__ ctr)
+                                                           DevCounters* __restrict__ ctr, int64_t chunk)
 {
     __shared__ double wbox[kBlock / 64][6];
     __shared__ double box[6];
     __shared__ uint32_t cand[kBlock];
+    __shared__ double4 cand_c[kBlock];  // the candidates' centroids and thresholds
     __shared__ int ncand;
     const int64_t ne = el.ne;
     double x[kListPPT], y[kListPPT], z[kListPPT];
@@ -138,28 +141,35 @@ __global__ __launch_bounds__(kBlock) void near_list_kernel(const double* __restr
     }
     __syncthreads();
     const double b0 = box[0], b1 = box[1], b2 = box[2], b3 = box[3], b4 = box[4], b5 = box[5];
-    for (int64_t c0 = 0; c0 < ne; c0 += kBlock) {
+    // this workgroup's chunk of the elements (blockIdx.y)
+    const int64_t e_begin = (int64_t)blockIdx.y * chunk, e_end = min(ne, e_begin + chunk);
+    for (int64_t c0 = e_begin; c0 < e_end; c0 += kBlock) {
         const int64_t e = c0 + threadIdx.x;
         bool hit = false;
-        if (e < ne) {
-            const double cx = el.cen[e], cy = el.cen[ne + e], cz = el.cen[2 * ne + e];
+        double cx = 0.0, cy = 0.0, cz = 0.0, t2 = 0.0;
+        if (e < e_end) {
+            cx = el.cen[e]; cy = el.cen[ne + e]; cz = el.cen[2 * ne + e]; t2 = el.thr2[e];
             const double dx = fmax(fmax(b0 - cx, cx - b3), 0.0);
             const double dy = fmax(fmax(b1 - cy, cy - b4), 0.0);
             const double dz = fmax(fmax(b2 - cz, cz - b5), 0.0);
-            hit = fma(dx, dx, fma(dy, dy, dz * dz)) < el.thr2[e];
+            hit = fma(dx, dx, fma(dy, dy, dz * dz)) < t2;
         }
         const unsigned long long m = __ballot(hit);
         if (m) {
             int base = 0;
             if (lane_id() == 0) base = atomicAdd(&ncand, __popcll(m));
             base = __shfl(base, 0);
-            if (hit) cand[base + (int)lanes_below(m)] = (uint32_t)e;
+            if (hit) {
+                cand[base + (int)lanes_below(m)] = (uint32_t)e;
+                cand_c[base + (int)lanes_below(m)] = make_double4(cx, cy, cz, t2);
+            }
         }
         __syncthreads();
         const int nc = ncand;
         for (int i = 0; i < nc; ++i) {
             const uint32_t ce = cand[i];
-            const double cx = el.cen[ce], cy = el.cen[ne + ce], cz = el.cen[2 * ne + ce], t2 = el.thr2[ce];
+            const double4 cc = cand_c[i];  // one LDS read for the whole wavefront
+            const double cx = cc.x, cy = cc.y, cz = cc.z, t2 = cc.w;
 #pragma unroll
             for (int k = 0; k < kListPPT; ++k) {
                 const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
@@ -1327,6 +1337,79 @@ __device__ __forceinline__ void near_terms(double w, double da, double db, doubl
     }
 }
 
+// Pairs whose field point lies on the element (the trailing entries of the order, from
+// *walk_end to the pair count): the exact integral about the point, one lane per pair; the
+// walk kernel's lanes take them once the walks are done (grid-stride from `first`).  Per
+// edge at distance h from the point with end offsets t1, t2 along it (rho^2 = h^2 + t^2):
+// potential h [asinh(t/h)], field -n [(t/rho)(1 + ln rho) - asinh(t/h)] + h t [(1 + ln rho)/rho]
+// (n the unit vector from the point's foot on the edge line towards the point's side).
+template <int MODE>
+__device__ __forceinline__ void on_element_pairs(const NearArgs& a, unsigned long long first, unsigned long long stride)
+{
+    constexpr bool COLLOC = MODE == kNearColloc;
+    constexpr bool GRAD = MODE == kNearGrad;
+    const Elements& el = a.el;
+    const int64_t ne = el.ne;
+    const unsigned long long total = min(a.ctr->near_count, a.near_cap);
+    unsigned long long n_on = 0;
+    for (unsigned long long w = *a.walk_end + first; w < total; w += stride) {
+        const NearPair pr = a.opair[w];
+        const unsigned long long cur = a.slot[a.order[w]];
+        const int64_t e = pr.elem, p = pr.point;
+        const bool tri = e < el.n_tri;
+        double X[3];
+        if (COLLOC) {
+            X[0] = el.cen[p]; X[1] = el.cen[ne + p]; X[2] = el.cen[2 * ne + p];
+        } else {
+            X[0] = a.pts[p]; X[1] = a.pts[a.n + p]; X[2] = a.pts[2 * a.n + p];
+        }
+        double G[9], P[3], V[4][3];
+        point_on_element(el, e, tri, X, G, P);  // (true: the cost pass put the pair here)
+        const int nv = element_corners(el, e, tri, G, V);
+        const double L = el.L[e];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int k = 0; k < nv; ++k) {
+            const double* Va = V[k];
+            const double* Vb = V[(k + 1) % nv];
+            double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
+            const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+            tv[0] /= len; tv[1] /= len; tv[2] /= len;
+            const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
+            const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
+            const double t2 = t1 + len;
+            double fn[3] = { pa[0] - t1 * tv[0], pa[1] - t1 * tv[1], pa[2] - t1 * tv[2] };
+            const double hh = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
+            if (!(hh > 1e-14 * L)) continue;
+            fn[0] /= hh; fn[1] /= hh; fn[2] /= hh;
+            const double r1 = sqrt(hh * hh + t1 * t1), r2 = sqrt(hh * hh + t2 * t2);
+            const double as = asinh(t2 / hh) - asinh(t1 / hh);
+            s0 += hh * as;
+            const double l1 = 1.0 + log(r1), l2 = 1.0 + log(r2);
+            const double gn = (t2 / r2) * l2 - (t1 / r1) * l1 - as;
+            const double gt = hh * (l2 / r2 - l1 / r1);
+            s1 += -gn * fn[0] + gt * tv[0];
+            s2 += -gn * fn[1] + gt * tv[1];
+            s3 += -gn * fn[2] + gt * tv[2];
+        }
+        const double inv_area = 1.0 / el.area[e];
+        if (COLLOC) {
+            a.res[cur] = s0 * inv_area;
+        } else if (GRAD) {  // the normal field jumps across the element: no gradient there
+            const double nan = __builtin_nan("");
+            double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
+            r[0] = make_double2(nan, nan);
+            r[1] = make_double2(nan, nan);
+            r[2] = make_double2(nan, nan);
+        } else {
+            const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
+            reinterpret_cast<double4*>(a.res)[cur] = make_double4(
+                Kq * (s0 * inv_area), Kq * (s1 * inv_area), Kq * (s2 * inv_area), Kq * (s3 * inv_area));
+        }
+        n_on++;
+    }
+    if (n_on) atomicAdd(&a.ctr->on_surface, n_on);
+}
+
 constexpr unsigned kNearWindow = 64;  // entries of the order a wavefront claims at a time
 
 // MODE: kNearEval (phi, E at field points), kNearColloc (phi at centroids, several density
@@ -1527,79 +1610,11 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     if (n_cap) atomicAdd(&a.ctr->cap_hits, n_cap);
     if (n_limit) atomicAdd(&a.ctr->visit_limit_hits, n_limit);
     if (max_level) atomicMax(&a.ctr->max_depth, (unsigned long long)max_level);
-}
 
-// Pairs whose field point lies on the element (the trailing entries of the order, from
-// *walk_end to the pair count): the exact integral about the point, one lane per pair.  Per
-// edge at distance h from the point with end offsets t1, t2 along it (rho^2 = h^2 + t^2):
-// potential h [asinh(t/h)], field -n [(t/rho)(1 + ln rho) - asinh(t/h)] + h t [(1 + ln rho)/rho]
-// (n the unit vector from the point's foot on the edge line towards the point's side).
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void on_element_kernel(NearArgs a)
-{
-    constexpr bool COLLOC = MODE == kNearColloc;
-    constexpr bool GRAD = MODE == kNearGrad;
-    const Elements& el = a.el;
-    const int64_t ne = el.ne;
-    const unsigned long long total = min(a.ctr->near_count, a.near_cap);
-    unsigned long long n_on = 0;
-    for (unsigned long long w = *a.walk_end + (unsigned long long)blockIdx.x * kBlock + threadIdx.x; w < total;
-         w += (unsigned long long)gridDim.x * kBlock) {
-        const NearPair pr = a.opair[w];
-        const unsigned long long cur = a.slot[a.order[w]];
-        const int64_t e = pr.elem, p = pr.point;
-        const bool tri = e < el.n_tri;
-        double X[3];
-        if (COLLOC) {
-            X[0] = el.cen[p]; X[1] = el.cen[ne + p]; X[2] = el.cen[2 * ne + p];
-        } else {
-            X[0] = a.pts[p]; X[1] = a.pts[a.n + p]; X[2] = a.pts[2 * a.n + p];
-        }
-        double G[9], P[3], V[4][3];
-        point_on_element(el, e, tri, X, G, P);  // (true: the cost pass put the pair here)
-        const int nv = element_corners(el, e, tri, G, V);
-        const double L = el.L[e];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int k = 0; k < nv; ++k) {
-            const double* Va = V[k];
-            const double* Vb = V[(k + 1) % nv];
-            double tv[3] = { Vb[0] - Va[0], Vb[1] - Va[1], Vb[2] - Va[2] };
-            const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
-            tv[0] /= len; tv[1] /= len; tv[2] /= len;
-            const double pa[3] = { Va[0] - P[0], Va[1] - P[1], Va[2] - P[2] };
-            const double t1 = pa[0] * tv[0] + pa[1] * tv[1] + pa[2] * tv[2];
-            const double t2 = t1 + len;
-            double fn[3] = { pa[0] - t1 * tv[0], pa[1] - t1 * tv[1], pa[2] - t1 * tv[2] };
-            const double hh = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
-            if (!(hh > 1e-14 * L)) continue;
-            fn[0] /= hh; fn[1] /= hh; fn[2] /= hh;
-            const double r1 = sqrt(hh * hh + t1 * t1), r2 = sqrt(hh * hh + t2 * t2);
-            const double as = asinh(t2 / hh) - asinh(t1 / hh);
-            s0 += hh * as;
-            const double l1 = 1.0 + log(r1), l2 = 1.0 + log(r2);
-            const double gn = (t2 / r2) * l2 - (t1 / r1) * l1 - as;
-            const double gt = hh * (l2 / r2 - l1 / r1);
-            s1 += -gn * fn[0] + gt * tv[0];
-            s2 += -gn * fn[1] + gt * tv[1];
-            s3 += -gn * fn[2] + gt * tv[2];
-        }
-        const double inv_area = 1.0 / el.area[e];
-        if (COLLOC) {
-            a.res[cur] = s0 * inv_area;
-        } else if (GRAD) {  // the normal field jumps across the element: no gradient there
-            const double nan = __builtin_nan("");
-            double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
-            r[0] = make_double2(nan, nan);
-            r[1] = make_double2(nan, nan);
-            r[2] = make_double2(nan, nan);
-        } else {
-            const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
-            reinterpret_cast<double4*>(a.res)[cur] = make_double4(
-                Kq * (s0 * inv_area), Kq * (s1 * inv_area), Kq * (s2 * inv_area), Kq * (s3 * inv_area));
-        }
-        n_on++;
-    }
-    if (n_on) atomicAdd(&a.ctr->on_surface, n_on);
+    // then the pairs whose point lies on the element (after the walk loop: none of its
+    // state is live here, so the closed form does not add to the walk's registers)
+    on_element_pairs<MODE>(a, (unsigned long long)blockIdx.x * kBlock + threadIdx.x,
+                           (unsigned long long)gridDim.x * kBlock);
 }
 
 // ---------------------------------------------------------------- small kernels -----
@@ -1753,11 +1768,6 @@ hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
     if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, lds, s>>>(a);
     else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, lds, s>>>(a);
     else near_kernel<kNearEval><<<blocks, kBlock, lds, s>>>(a);
-    // points on their element: rare for field points, one per element for collocation
-    const unsigned on_blocks = (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>(256, (a.near_cap + kBlock - 1) / kBlock));
-    if (mode == kNearColloc) on_element_kernel<kNearColloc><<<on_blocks, kBlock, 0, s>>>(a);
-    else if (mode == kNearGrad) on_element_kernel<kNearGrad><<<on_blocks, kBlock, 0, s>>>(a);
-    else on_element_kernel<kNearEval><<<on_blocks, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1767,7 +1777,13 @@ hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, Ne
     if (n <= 0 || el.ne <= 0) return hipSuccess;
     const int64_t blocks = (n + kListPoints - 1) / kListPoints;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    near_list_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(pts, n, el, list, cap, ctr);
+    // few point blocks (a small evaluation): split the elements into chunks of at least one
+    // candidate pass each, up to about 2048 workgroups in all
+    const int64_t passes = (el.ne + kBlock - 1) / kBlock;
+    const int64_t split = std::max<int64_t>(1, std::min<int64_t>({ (2048 + blocks - 1) / blocks, passes, 65535 }));
+    const int64_t chunk = ((passes + split - 1) / split) * kBlock;
+    const int64_t chunks = (el.ne + chunk - 1) / chunk;
+    near_list_kernel<<<dim3((unsigned)blocks, (unsigned)chunks), kBlock, 0, s>>>(pts, n, el, list, cap, ctr, chunk);
     return hipGetLastError();
 }
 

@@ -91,6 +91,47 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
     }
 }
 
+// The final value of each point (field or gradient rows): its far field (K times the element
+// chunks' partial sums in chunk order, or the far kernel's own row) plus its near-pair records
+// in element order, stored at the point's place in the caller's order.  The same operations
+// in the same order as the separate chunk reduction, ordered sums and unordering, in one pass.
+__global__ void finish_points_kernel(const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
+                                     int64_t n, const double* __restrict__ res, int rec, int rows, int prow,
+                                     const double* __restrict__ partial, int n_split, const double* __restrict__ far,
+                                     double K, const uint32_t* __restrict__ perm, double* __restrict__ d0,
+                                     double* __restrict__ d1)
+{
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t s = start[p], k = count[p];
+    const int64_t q = perm ? (int64_t)perm[p] : p;
+    double v[6], acc[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) { v[c] = 0.0; acc[c] = 0.0; }
+    if (n_split > 1) {  // each row summed in chunk order; the rows side by side
+        for (int j = 0; j < n_split; ++j)
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                if (c < rows) v[c] += partial[((int64_t)j * prow + c) * n + p];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = K * v[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (c < rows) v[c] = far[(int64_t)c * n + p];
+    }
+    for (uint32_t m = 0; m < k; ++m)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (c < rows) acc[c] += res[(unsigned long long)(s + m) * rec + c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if (c >= rows) break;
+        (c == 0 ? d0 : d1 + (int64_t)(c - 1) * n)[q] = k > 0 ? v[c] + acc[c] : v[c];
+    }
+}
+
 // Cost class of a near pair (higher = more subdivision leaves expected within a kind): 4
 // classes per octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the
 // element's plane, rho the in-plane distance from the centroid, R the distance of the farthest
@@ -305,6 +346,17 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
     const int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     rank_sort_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(w.start, w.count, n, w.grouped, w.origin, w.sorted, w.slot);
+    return hipGetLastError();
+}
+
+hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const double* partial, int n_split,
+                       int prow, const double* far, double K, const uint32_t* perm, double* d0, double* d1,
+                       hipStream_t s)
+{
+    if (n <= 0 || rows <= 0) return hipSuccess;
+    if (mode == kNearColloc) return hipErrorInvalidValue;
+    finish_points_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        w.start, w.count, n, w.res, mode == kNearGrad ? 6 : 4, rows, prow, partial, n_split, far, K, perm, d0, d1);
     return hipGetLastError();
 }
 
