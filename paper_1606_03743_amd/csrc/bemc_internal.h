@@ -145,8 +145,6 @@ hipError_t launch_far_grad(const FarArgs& a, int precision, hipStream_t s);
 enum NearMode { kNearEval = 0, kNearColloc = 1, kNearGrad = 2 };
 hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s);
 hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s);
-hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
-                               hipStream_t s);
 hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows, int64_t n, double K, double* out,
                                 hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);
@@ -212,11 +210,10 @@ hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const d
                        hipStream_t s);
 // entries of w.order that the subdivision walk takes (device pointer; set by near_order)
 inline const uint32_t* near_walk_end(const NearWork& w) { return w.buckets + kCostClasses + kOnElementClass; }
-// add each point's segment of per-pair result records to its outputs; base (field mode
-// only): rows [4][n] (phi, E) that the sums are added to instead (outputs = base + near)
+// add each point's segment of per-pair result records to its outputs (collocation; field and
+// gradient evaluations use near_finish)
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s,
-                       const double* base = nullptr);
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
 constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 
 // Allocation-free evaluation (noalloc.hip): a static device array per GPU, carved into the

@@ -1625,22 +1625,6 @@ __global__ void charges_kernel(const double* sigma, const double* area, double* 
     q[i] = sigma[i] * area[i % ne];
 }
 
-__global__ void reduce_split_kernel(const double* partial, int n_split, int64_t n, double K, double* phi, double* E)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    double s[4] = { 0, 0, 0, 0 };
-    for (int k = 0; k < n_split; ++k)  // fixed order: independent of timing
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s[c] += partial[((int64_t)k * 4 + c) * n + p];
-    phi[p] = K * s[0];
-    if (E) {
-        E[p] = K * s[1];
-        E[n + p] = K * s[2];
-        E[2 * n + p] = K * s[3];
-    }
-}
-
 // out[m][p] = K * sum over the element chunks k (fixed order) of partial[k][m][p]
 __global__ void reduce_chunks_kernel(const double* partial, int n_split, int64_t rows, int64_t n, double K,
                                      double* out)
@@ -1792,14 +1776,6 @@ hipError_t launch_charges(const double* sigma, const double* area, double* q, in
     const int64_t tot = ne * n_rhs;
     if (tot <= 0) return hipSuccess;
     charges_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(sigma, area, q, ne, n_rhs);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_split(const double* partial, int n_split, int64_t n, double K, double* phi, double* E,
-                               hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    reduce_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, n_split, n, K, phi, E);
     return hipGetLastError();
 }
 

@@ -63,12 +63,12 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
                                     int64_t n, const NearPair* __restrict__ sorted, const double* __restrict__ res,
                                     int mode, double* __restrict__ phi,
                                     double* __restrict__ E, double* __restrict__ G, const double* __restrict__ q,
-                                    int64_t ne, int n_rhs, double K, const double* __restrict__ base)
+                                    int64_t ne, int n_rhs, double K)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t s = start[p], k = count[p];
-    if (k == 0 && !base) return;
+    if (k == 0) return;
     if (mode == kNearColloc) {
         for (int r = 0; r < n_rhs; ++r) {
             double acc = 0.0;
@@ -82,12 +82,9 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
     for (int c = 0; c < rows; ++c) {
         double acc = 0.0;
         for (uint32_t m = 0; m < k; ++m) acc += res[(unsigned long long)(s + m) * rec + c];
-        if (mode == kNearGrad) {
-            G[(int64_t)c * n + p] += acc;
-        } else {
-            double* out = c == 0 ? phi + p : E + (int64_t)(c - 1) * n + p;
-            *out = (base ? base[(int64_t)c * n + p] : *out) + acc;
-        }
+        if (mode == kNearGrad) G[(int64_t)c * n + p] += acc;
+        else if (c == 0) phi[p] += acc;
+        else E[(int64_t)(c - 1) * n + p] += acc;
     }
 }
 
@@ -361,13 +358,11 @@ hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const d
 }
 
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s,
-                       const double* base)
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (base && mode != kNearEval) return hipErrorInvalidValue;
     reduce_pairs_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K, base);
+        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K);
     return hipGetLastError();
 }
 

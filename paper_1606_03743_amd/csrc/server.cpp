@@ -357,11 +357,13 @@ bool Server::near_stage(Slot& s, std::string& err)
     na.near_dr2 = env_.near_dr * env_.near_dr;
     na.max_depth = env_.max_depth;
     na.visit_limit = 1ll << 22;
-    // d_out = d_far + the near field (d_far stays: a repeated near stage starts from it)
+    // d_out = the far field (the element-chunk partial sums, or d_far with one chunk) + the near
+    // field; both stay, so a repeated near stage starts from them again
     hipError_t e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, s.stream);
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess)
-        e = near_reduce(s.nw, n, kNearEval, s.d_out, s.d_out + n, nullptr, env_.el.q, ne, 1, K, s.stream, s.d_far);
+        e = near_finish(s.nw, n, kNearEval, 4, s.n_split > 1 ? s.d_partial : nullptr, s.n_split, 4, s.d_far, K,
+                        nullptr, s.d_out, s.d_out + n, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * 4 * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
@@ -374,7 +376,7 @@ bool Server::near_stage(Slot& s, std::string& err)
 }
 
 // The whole batch, enqueued at admission (its blocks are taken): copy-in, near-pair list,
-// far field and chunk reduction, near stage.
+// far field (chunk partial sums, or the far results with one chunk), near stage.
 bool Server::launch(Slot& s, std::string& err)
 {
     const int64_t n = s.n;
@@ -415,8 +417,6 @@ bool Server::launch(Slot& s, std::string& err)
     fa.dr_rules = env_.dr_rules;
     fa.lv = env_.lv;
     if (e == hipSuccess) e = launch_far_eval(fa, cfg_.precision, s.stream);
-    if (e == hipSuccess && s.n_split > 1)
-        e = launch_reduce_split(s.d_partial, s.n_split, n, K, s.d_far, s.d_far + n, s.stream);
     if (e != hipSuccess) {
         err = hipGetErrorString(e);
         return false;

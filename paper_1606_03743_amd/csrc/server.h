@@ -78,7 +78,8 @@ private:
         char* spill = nullptr;  // a grown list's block outside the arena (nothing could give
                                 // memory back): stream-ordered allocation, released with the batch
         double *d_pts = nullptr;   // [3][n]
-        double *d_far = nullptr;   // [4][n] far field (phi, E), kept for a repeated near stage
+        double *d_far = nullptr;   // [4][n] far field (phi, E) of a one-chunk batch (else the
+                                   // partial sums hold it); kept for a repeated near stage
         double *d_out = nullptr;   // [4][n] far + near
         double *d_partial = nullptr;
         NearPair* d_near = nullptr;
