@@ -326,16 +326,20 @@ __device__ __forceinline__ void stage_tile(TileLds<MIXED, NRHS>& s, const Elemen
             const double la = R.tri[4 * i], lb = R.tri[4 * i + 1], lc = R.tri[4 * i + 2];
             w = R.tri[4 * i + 3];
             if (i < nfold) {
-                int l = 0;
-                while (l + 1 < tf.nlev && i >= tf.off[l + 1]) ++l;
-                const int il = i - tf.off[l];
-                if (il < tf.nc[l] + tf.n21[l]) {
+                // the level of node i (selects, not indexing: the forms stay in registers)
+                int off_l = tf.off[0], nc_l = tf.nc[0], n21_l = tf.n21[0];
+#pragma unroll
+                for (int q = 1; q < 4; ++q)
+                    if (q < tf.nlev && i >= tf.off[q]) { off_l = tf.off[q]; nc_l = tf.nc[q]; n21_l = tf.n21[q]; }
+                const int il = i - off_l;
+                if (il < nc_l + n21_l) {
                     const double iw2 = 1.0 / (w * w);
                     double v0 = 0.0, v1 = 0.0;
-                    if (il >= tf.nc[l]) {  // S21: the distinct coordinate at vertex kk
-                        const int kk = (il - tf.nc[l]) % 3;
-                        const double lam[3] = { la, lb, lc };
-                        const double sv = lam[kk] - lam[(kk + 1) % 3];
+                    if (il >= nc_l) {  // S21: the distinct coordinate at vertex kk
+                        const int kk = (il - nc_l) % 3;
+                        const double lk = kk == 0 ? la : (kk == 1 ? lb : lc);
+                        const double lk1 = kk == 0 ? lb : (kk == 1 ? lc : la);
+                        const double sv = lk - lk1;
                         const double na = sv * el.loc[(int64_t)(2 * kk) * ne + e], nb = sv * el.loc[(int64_t)(2 * kk + 1) * ne + e];
                         v0 = sv * iw2;
                         v1 = fma(na, na, nb * nb) * iw2;
