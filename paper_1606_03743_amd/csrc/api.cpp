@@ -192,6 +192,7 @@ struct bemc_context {
     // elements (device)
     int64_t n_tri = 0, n_rect = 0, ne = 0;
     std::vector<double> h_area, h_L;  // host copies
+    double* d_nrec = nullptr;  // near-walk records, packed on the device from the arrays below
     double *d_geom = nullptr, *d_cen = nullptr, *d_thr2 = nullptr, *d_frame = nullptr, *d_loc = nullptr,
            *d_L = nullptr, *d_area = nullptr, *d_nrm = nullptr, *d_q = nullptr, *d_qc = nullptr;
     int n_rhs = 0;
@@ -233,7 +234,7 @@ struct bemc_context {
 Elements bemc_context::elements() const
 {
     Elements e{};
-    e.geom = d_geom; e.cen = d_cen; e.thr2 = d_thr2; e.frame = d_frame; e.loc = d_loc; e.L = d_L;
+    e.geom = d_geom; e.cen = d_cen; e.thr2 = d_thr2; e.frame = d_frame; e.loc = d_loc; e.nrec = d_nrec; e.L = d_L;
     e.area = d_area; e.nrm = d_nrm; e.q = d_q; e.ne = ne; e.n_tri = (int)n_tri; e.n_rhs = n_rhs;
     return e;
 }
@@ -676,6 +677,7 @@ int bemc_create(int device, bemc_handle* out)
 static void free_elements(bemc_context* h)
 {
     dev_free(h->d_geom); dev_free(h->d_cen); dev_free(h->d_thr2); dev_free(h->d_frame); dev_free(h->d_loc);
+    dev_free(h->d_nrec);
     dev_free(h->d_L); dev_free(h->d_area); dev_free(h->d_nrm); dev_free(h->d_q); dev_free(h->d_qc);
     h->n_rhs = 0;
     h->have_geometry = false;
@@ -736,6 +738,8 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
         HIP_TRY(hipSetDevice(h->device));
         if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
         HIP_TRY(hipMemcpy(h->d_thr2, thr.data(), thr.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(launch_pack_near_records(h->elements(), h->d_nrec, nullptr));
+        HIP_TRY(hipDeviceSynchronize());
     }
     return ok();
 }
@@ -852,7 +856,8 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     h->ne = ne;
     if (dev_alloc(&h->d_geom, geom.size()) || dev_alloc(&h->d_cen, cen.size()) || dev_alloc(&h->d_thr2, thr2.size()) ||
         dev_alloc(&h->d_frame, frame.size()) || dev_alloc(&h->d_loc, loc.size()) || dev_alloc(&h->d_L, L.size()) ||
-        dev_alloc(&h->d_area, area.size()) || dev_alloc(&h->d_nrm, nrm.size())) {
+        dev_alloc(&h->d_area, area.size()) || dev_alloc(&h->d_nrm, nrm.size()) ||
+        dev_alloc(&h->d_nrec, (size_t)std::max<int64_t>(ne, 1) * kNearRec)) {
         (void)hipGetLastError();
         free_elements(h);
         return fail(BEMC_E_OUT_OF_MEMORY, "element arrays for %lld elements", (long long)ne);
@@ -865,6 +870,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
     HIP_TRY(hipMemcpyAsync(h->d_L, L.data(), L.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_area, area.data(), area.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h->d_nrm, nrm.data(), nrm.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_pack_near_records(h->elements(), h->d_nrec, s));
     HIP_TRY(hipStreamSynchronize(s));
     h->h_area = area;
     h->h_L = L;

@@ -51,6 +51,8 @@ struct Elements {
                          //          f3 components (rounding-level heights, kept by the near field);
                          //          rect: gamma = f1.e1/2, beta = f2.e1/2, alpha = |e2|/2, the corner
                          //          P0 - c in the frame (3), the f3 components of e1 and e2, 0
+    const double* nrec;  // [ne][kNearRec] the near walk's record of each element in one place:
+                         //          centroid (3), frame (9), loc (9), thr2, 2 unused
     const double* L;     // [ne]     average side length
     const double* area;  // [ne]
     const double* nrm;   // [3][ne]  unit normal
@@ -59,6 +61,8 @@ struct Elements {
     int n_tri;
     int n_rhs;
 };
+
+constexpr int kNearRec = 24;  // doubles per near-walk record (192 B)
 
 // Rule choice by distance ratio: four levels per element kind, coarsest first
 // (triangles 7/12/19/tri_rule points, rectangles Tables B2/B3/B4 then the rectangle rule).
@@ -145,6 +149,9 @@ hipError_t launch_far_grad(const FarArgs& a, int precision, hipStream_t s);
 enum NearMode { kNearEval = 0, kNearColloc = 1, kNearGrad = 2 };
 hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s);
 hipError_t launch_charges(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs, hipStream_t s);
+// the near walk's records nrec[ne][kNearRec] from el.cen, el.frame, el.loc and el.thr2 (after an
+// upload, and after the thresholds change)
+hipError_t launch_pack_near_records(const Elements& el, double* nrec, hipStream_t s);
 hipError_t launch_reduce_chunks(const double* partial, int n_split, int64_t rows, int64_t n, double K, double* out,
                                 hipStream_t s);
 hipError_t launch_zero_counters(DevCounters* c, hipStream_t s);

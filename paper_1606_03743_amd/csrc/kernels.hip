@@ -1484,26 +1484,36 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                     P[0] = a.pts[p]; P[1] = a.pts[a.n + p]; P[2] = a.pts[2 * a.n + p];
                 }
                 st.kind = (int64_t)e < el.n_tri ? 0 : 1;
+                // the element's record: centroid, frame F, loc, thr2
+                double R[kNearRec];
+                {
+                    const double2* rec = reinterpret_cast<const double2*>(el.nrec + (int64_t)e * kNearRec);
+#pragma unroll
+                    for (int c = 0; c < 11; ++c) {
+                        const double2 v = rec[c];
+                        R[2 * c] = v.x;
+                        R[2 * c + 1] = v.y;
+                    }
+                }
+                const double* F = R + 3;
+                const double* lc = R + 12;
                 // the point in the element's frame (offset from the centroid: numbers of the
                 // element's size, accurate for points very close to a small element far from
                 // the origin)
-                const double dxc = P[0] - el.cen[e], dyc = P[1] - el.cen[ne + e], dzc = P[2] - el.cen[2 * ne + e];
-                double F[9];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) F[c] = el.frame[(int64_t)c * ne + e];
+                const double dxc = P[0] - R[0], dyc = P[1] - R[1], dzc = P[2] - R[2];
                 p1 = fma(F[0], dxc, fma(F[1], dyc, F[2] * dzc));
                 p2 = fma(F[3], dxc, fma(F[4], dyc, F[5] * dzc));
                 p3 = fma(F[6], dxc, fma(F[7], dyc, F[8] * dzc));
                 if (st.kind == 0) {  // vertices A', B', C' in the frame
-                    g.ax = el.loc[e]; g.ay = el.loc[ne + e]; g.az = el.loc[6 * ne + e];
-                    g.ux = el.loc[2 * ne + e] - g.ax; g.uy = el.loc[3 * ne + e] - g.ay; g.uz = el.loc[7 * ne + e] - g.az;
-                    g.vx = el.loc[4 * ne + e] - g.ax; g.vy = el.loc[5 * ne + e] - g.ay; g.vz = el.loc[8 * ne + e] - g.az;
+                    g.ax = lc[0]; g.ay = lc[1]; g.az = lc[6];
+                    g.ux = lc[2] - g.ax; g.uy = lc[3] - g.ay; g.uz = lc[7] - g.az;
+                    g.vx = lc[4] - g.ax; g.vy = lc[5] - g.ay; g.vz = lc[8] - g.az;
                 } else {  // e1 = (2 gamma, 2 beta, h1), e2 = (2 alpha, 0, h2); the corner P0 - c
-                    g.ux = 2.0 * el.loc[e]; g.uy = 2.0 * el.loc[ne + e]; g.uz = el.loc[6 * ne + e];
-                    g.vx = 2.0 * el.loc[2 * ne + e]; g.vy = 0.0; g.vz = el.loc[7 * ne + e];
-                    g.ax = el.loc[3 * ne + e]; g.ay = el.loc[4 * ne + e]; g.az = el.loc[5 * ne + e];
+                    g.ux = 2.0 * lc[0]; g.uy = 2.0 * lc[1]; g.uz = lc[6];
+                    g.vx = 2.0 * lc[2]; g.vy = 0.0; g.vz = lc[7];
+                    g.ax = lc[3]; g.ay = lc[4]; g.az = lc[5];
                 }
-                thr2 = el.thr2[e];
+                thr2 = R[21];
 #pragma unroll
                 for (int c = 0; c < 7; ++c) acc[c] = 0.0;
                 visits = 0;
@@ -1579,8 +1589,11 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         } else {
             const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
             double F[9];
+            {
+                const double* rec = el.nrec + (int64_t)e * kNearRec + 3;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) F[c] = el.frame[(int64_t)c * ne + e];
+                for (int c = 0; c < 9; ++c) F[c] = rec[c];
+            }
             if (GRAD) {
                 // local tensor m = sum w d d^T / r^5 (d = (da, db, dc)), global M = F^T m F,
                 // dE_i/dx_j = q (delta_ij S3 - 3 M_ij)
@@ -1622,6 +1635,28 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
 }
 
 // ---------------------------------------------------------------- small kernels -----
+// One 192-byte record per element with what the near walk reads when it takes a pair (three
+// 64-byte lines instead of 22 from the separate arrays): centroid, frame, loc, thr2.
+__global__ void pack_near_records_kernel(Elements el, double* __restrict__ nrec)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ne = el.ne;
+    if (e >= ne) return;
+    double r[kNearRec];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = el.cen[c * ne + e];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) r[3 + c] = el.frame[c * ne + e];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) r[12 + c] = el.loc[c * ne + e];
+    r[21] = el.thr2[e];
+    r[22] = 0.0;
+    r[23] = 0.0;
+    double2* out = reinterpret_cast<double2*>(nrec + e * kNearRec);
+#pragma unroll
+    for (int c = 0; c < kNearRec / 2; ++c) out[c] = make_double2(r[2 * c], r[2 * c + 1]);
+}
+
 __global__ void charges_kernel(const double* sigma, const double* area, double* q, int64_t ne, int n_rhs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1772,6 +1807,13 @@ hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, Ne
     const int64_t chunk = ((passes + split - 1) / split) * kBlock;
     const int64_t chunks = (el.ne + chunk - 1) / chunk;
     near_list_kernel<<<dim3((unsigned)blocks, (unsigned)chunks), kBlock, 0, s>>>(pts, n, el, list, cap, ctr, chunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_near_records(const Elements& el, double* nrec, hipStream_t s)
+{
+    if (el.ne <= 0) return hipSuccess;
+    pack_near_records_kernel<<<(unsigned)((el.ne + kBlock - 1) / kBlock), kBlock, 0, s>>>(el, nrec);
     return hipGetLastError();
 }
 
