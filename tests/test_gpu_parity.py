@@ -171,16 +171,21 @@ def test_fixed_near_list_overflow_is_reported(cyl):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("near_dr", [2.0, 10.0])
-def test_other_near_thresholds(precision, near_dr):
+@pytest.mark.parametrize("near_dr,after_upload", [(2.0, False), (10.0, False), (10.0, True)])
+def test_other_near_thresholds(precision, near_dr, after_upload):
     """The distance-ratio switch at 2 (the smallest accepted: far sums expanded about the
-    centroid down to DR 2) and at 10, against the oracle with the same threshold."""
+    centroid down to DR 2) and at 10, against the oracle with the same threshold; also set
+    after the geometry is resident (the thresholds and the near walk's element records are
+    then rewritten on the device)."""
     w = W.cylinder_workload(40, 30, 1200, n_points=1500, near_frac=0.3, seed=23)
     ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7, near_dr=near_dr), with_abs=True)
     ctx = bemc.Context(0)
-    ctx.set_rules(33, 7, near_dr)
+    ctx.set_rules(33, 7, 3.0 if after_upload else near_dr)
     ctx.upload_geometry(w.tri, w.rect)
     ctx.upload_densities(w.sigma)
+    if after_upload:
+        run_gpu(ctx, w.points, precision)  # at 3 first
+        ctx.set_rules(33, 7, near_dr)
     phi, E, rc = run_gpu(ctx, w.points, precision)
     st = ctx.stats()
     with pytest.raises(bemc.BemcError):
