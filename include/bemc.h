@@ -131,8 +131,8 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_rule, double near_dr, i
  * uses Tables B2 / B3 / B4 for DR >= rect_dr[0..2], else the rectangle rule.  NULL
  * arrays select the defaults {100, 25, 10} and {150, 40, 15} (the paper's triangle
  * potential limits x 1.25; the rectangle tables' field-accuracy limits).  For each
- * element a wavefront of 128 neighbouring points (bemc_eval works on the points in Morton
- * order) uses the finest of the rules its pairs need (never
+ * element a wavefront of 128 points (neighbours: bemc_eval works on more than 4,096 points
+ * in Morton order) uses the finest of the rules its pairs need (never
  * a coarser rule than a pair's own distance ratio asks for); results are returned in the
  * caller's order.  Near pairs and collocation are unaffected.  The rules of
  * bemc_set_rules must be at least as fine as the third level (>= 19 triangle points,
@@ -163,9 +163,13 @@ int bemc_upload_densities(bemc_handle h, const double* sigma, int n_rhs, int sig
 /* Potential phi[n] (device) and, if E is not NULL, field E[3][n] (device) at the n field
  * points pts[3][n] (device), from density vector `rhs` (0 <= rhs < n_rhs).  Outputs are
  * overwritten.  precision = BEMC_FP64 or BEMC_MIXED.  n = 0 is a no-op.
- * The points are processed in Morton (Z-curve) order, which keeps the points of a
- * wavefront close together; results are returned in the caller's order and do not depend
- * on that order.  The ordering workspace (about 110 bytes per point) is kept by the context.
+ * More than 4,096 points are processed in Morton (Z-curve) order, which keeps the points
+ * of a wavefront close together; fewer keep the caller's order (the sort would cost more
+ * than it saves).  Results are returned in the caller's order.  With one rule per element
+ * kind they do not depend on the processing order; with the rule choice by distance ratio
+ * the rule level a wavefront picks does (an accuracy-level difference, never a coarser
+ * rule than a pair needs).  The ordering workspace (about 110 bytes per point) is kept by
+ * the context.
  * The call enqueues on `stream` the near-pair list (every pair with D < near_dr L, by a
  * classification pass), the far-field kernel (point-charge sums of the other pairs) and the
  * FP64 near field, and returns without waiting for them.  With a growing near-pair list
