@@ -1456,7 +1456,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     // entries are pairs of one cost class, so the lanes walk trees of one kind and similar size
     unsigned long long win = 0, win_end = 0;
 
-    while (true) {
+    while (total > 0) {
         // ---- refill from the window (a new window when it is used up)
         const unsigned long long need = __ballot(!active);
         if (need) {
@@ -1800,11 +1800,11 @@ hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, Ne
     if (n <= 0 || el.ne <= 0) return hipSuccess;
     const int64_t blocks = (n + kListPoints - 1) / kListPoints;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    // few point blocks (a small evaluation): split the elements into chunks of at least one
-    // candidate pass each, up to about 2048 workgroups in all
-    const int64_t passes = (el.ne + kBlock - 1) / kBlock;
-    const int64_t split = std::max<int64_t>(1, std::min<int64_t>({ (2048 + blocks - 1) / blocks, passes, 65535 }));
-    const int64_t chunk = ((passes + split - 1) / split) * kBlock;
+    // few point blocks (a small evaluation): split the elements into chunks (multiples of 64
+    // elements), up to about 2048 workgroups in all
+    const int64_t units = (el.ne + 63) / 64;
+    const int64_t split = std::max<int64_t>(1, std::min<int64_t>({ (2048 + blocks - 1) / blocks, units, 65535 }));
+    const int64_t chunk = ((units + split - 1) / split) * 64;
     const int64_t chunks = (el.ne + chunk - 1) / chunk;
     near_list_kernel<<<dim3((unsigned)blocks, (unsigned)chunks), kBlock, 0, s>>>(pts, n, el, list, cap, ctr, chunk);
     return hipGetLastError();

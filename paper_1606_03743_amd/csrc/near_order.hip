@@ -99,34 +99,28 @@ __global__ void finish_points_kernel(const uint32_t* __restrict__ start, const u
                                      double* __restrict__ d1)
 {
 #pragma clang fp contract(off)
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
+    // one thread per (row, point)
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (int64_t)rows * n) return;
+    const int c = (int)(i / n);
+    const int64_t p = i - (int64_t)c * n;
     const uint32_t s = start[p], k = count[p];
-    const int64_t q = perm ? (int64_t)perm[p] : p;
-    double v[6], acc[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) { v[c] = 0.0; acc[c] = 0.0; }
-    if (n_split > 1) {  // each row summed in chunk order; the rows side by side
-        for (int j = 0; j < n_split; ++j)
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-                if (c < rows) v[c] += partial[((int64_t)j * prow + c) * n + p];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = K * v[c];
+    double v;
+    if (n_split > 1) {  // the row summed in chunk order
+        v = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < n_split; ++j) v += partial[((int64_t)j * prow + c) * n + p];
+        v = K * v;
     } else {
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-            if (c < rows) v[c] = far[(int64_t)c * n + p];
+        v = far[(int64_t)c * n + p];
     }
-    for (uint32_t m = 0; m < k; ++m)
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-            if (c < rows) acc[c] += res[(unsigned long long)(s + m) * rec + c];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        if (c >= rows) break;
-        (c == 0 ? d0 : d1 + (int64_t)(c - 1) * n)[q] = k > 0 ? v[c] + acc[c] : v[c];
+    if (k > 0) {
+        double acc = 0.0;
+        for (uint32_t m = 0; m < k; ++m) acc += res[(unsigned long long)(s + m) * rec + c];
+        v = v + acc;
     }
+    const int64_t q = perm ? (int64_t)perm[p] : p;
+    (c == 0 ? d0 : d1 + (int64_t)(c - 1) * n)[q] = v;
 }
 
 // Cost class of a near pair (higher = more subdivision leaves expected within a kind): 4
@@ -352,7 +346,9 @@ hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const d
 {
     if (n <= 0 || rows <= 0) return hipSuccess;
     if (mode == kNearColloc) return hipErrorInvalidValue;
-    finish_points_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+    const int64_t threads = (int64_t)rows * n;
+    if ((threads + kBlock - 1) / kBlock > 0x7fffffff) return hipErrorInvalidValue;
+    finish_points_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(
         w.start, w.count, n, w.res, mode == kNearGrad ? 6 : 4, rows, prow, partial, n_split, far, K, perm, d0, d1);
     return hipGetLastError();
 }
