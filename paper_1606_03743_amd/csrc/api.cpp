@@ -528,7 +528,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     // balances the tail; the chunk partial sums are reduced in fixed order
     const int64_t blocks = (npts + 511) / 512;  // nominal 512 points per workgroup (256-768 in fact)
     int n_split = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (kSplitTargetBlocks + blocks - 1) / blocks));
-    n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 64));  // chunks of >= 64 elements
+    n_split = (int)std::min<int64_t>(n_split, std::max<int64_t>(1, ne / 16));  // chunks of >= 16 elements
     const int64_t rows = colloc ? n_rhs_colloc : (grad ? 6 : 4);
     if (n_split > 1) {
         const size_t need = (size_t)n_split * (size_t)rows * (size_t)npts;
