@@ -249,7 +249,5 @@ struct OrderWork {
 };
 size_t order_temp_bytes(int64_t n);
 hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStream_t s);
-// dst[r][perm[i]] = src[r][i] for r < rows (src rows in sorted order, n points)
-hipError_t unorder_rows(const OrderWork& w, int64_t n, const double* src, int rows, double* dst, hipStream_t s);
 
 }  // namespace bemc

@@ -1,7 +1,7 @@
 // Field-point ordering: points are sorted along a Morton (Z-order) curve so that the
 // points of one wavefront lie close together, mostly choose the same rule level for a
 // given element (rule choice by distance ratio) and are near the same elements.  Results
-// are scattered back to the caller's order afterwards.
+// are stored back in the caller's order by the evaluation's last kernel (finish_points_kernel).
 #include <hipcub/hipcub.hpp>
 
 #include "bemc_internal.h"
@@ -91,15 +91,6 @@ __global__ void gather_kernel(const double* __restrict__ pts, int64_t n, const u
     for (int c = 0; c < 3; ++c) out[c * n + i] = pts[c * n + j];
 }
 
-__global__ void scatter_kernel(const double* __restrict__ src, int rows, int64_t n, const uint32_t* __restrict__ perm,
-                               double* __restrict__ dst)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t j = perm[i];
-    for (int r = 0; r < rows; ++r) dst[r * n + j] = src[r * n + i];
-}
-
 }  // namespace
 
 size_t order_temp_bytes(int64_t n)
@@ -124,13 +115,6 @@ hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStr
     e = hipcub::DeviceRadixSort::SortPairs(w.temp, bytes, w.keys_in, w.keys_out, w.idx_in, w.perm, (int)n, 0, 30, s);
     if (e != hipSuccess) return e;
     gather_kernel<<<blocks, kBlock, 0, s>>>(pts, n, w.perm, w.pts);
-    return hipGetLastError();
-}
-
-hipError_t unorder_rows(const OrderWork& w, int64_t n, const double* src, int rows, double* dst, hipStream_t s)
-{
-    if (n <= 0 || rows <= 0) return hipSuccess;
-    scatter_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(src, rows, n, w.perm, dst);
     return hipGetLastError();
 }
 
