@@ -245,7 +245,7 @@ struct OrderWork {
     size_t temp_bytes;
     double* bbox;    // [1024][6]
     double* pts;     // [3][n] points in sorted order
-    double* res;     // [6][n] results in sorted order (phi, E or the gradient rows)
+    double* res;     // [6][n] far-field rows in processing order (phi, E or the gradient rows)
 };
 size_t order_temp_bytes(int64_t n);
 hipError_t order_points(const double* pts, int64_t n, const OrderWork& w, hipStream_t s);
