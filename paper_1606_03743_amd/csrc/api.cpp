@@ -604,7 +604,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     na.n_rhs = n_rhs_colloc; na.K = fa.K; na.phi = phi; na.E = E; na.G = G; na.near_cap = W.near_cap;
     na.ctr = W.ctr; na.near_dr2 = near_dr * near_dr; na.max_depth = max_depth; na.visit_limit = 1ll << 22;
     na.near_list = W.near; na.slot = W.nw.slot; na.order = W.nw.order; na.opair = W.nw.opair;
-    na.walk_end = near_walk_end(W.nw);
+    na.walk_end = near_walk_end(W.nw); na.heavy_end = near_heavy_end(W.nw); na.deep = 1;
     na.res = W.nw.res;
     HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, s));
     HIP_TRY(launch_near(na, mode, s));

@@ -91,6 +91,7 @@ struct DevCounters {
     unsigned long long visit_limit_hits;
     unsigned long long node_ints;  // point-charge terms summed (rule choice by distance ratio)
     unsigned long long node_ints_pair;  // the terms each far pair's own level would sum
+    unsigned long long heavy_cursor;    // work cursor of the near kernel's deep pairs
 };
 
 // Arguments of the far-field kernels.
@@ -134,6 +135,9 @@ struct NearArgs {
                                  // the pairs whose point lies on the element last)
     const NearPair* opair;       // the pairs in that order
     const uint32_t* walk_end;    // device: entries of order that subdivide (near_walk_end)
+    const uint32_t* heavy_end;   // device: the leading entries with deep subdivisions (near_heavy_end)
+    int deep;                    // field mode: 1 walks those breadth first, a wavefront each (more
+                                 // registers); 0 walks every pair depth first in one lane
     double* res;                 // per-pair result records at the pairs' slots: [slot][4] field,
                                  // [slot][6] gradient, [slot] collocation
     DevCounters* ctr;
@@ -195,11 +199,13 @@ struct NearWork {
     size_t temp_bytes;
 };
 // cost classes of near pairs: class 0 holds the pairs whose point lies on the element (exact
-// integral, no subdivision); triangles take classes 1 .. 127 and rectangles 129 .. 255 by the
-// estimated subdivision depth (kind-major: the order runs through the rectangles, then the
-// triangles, each most expensive first)
+// integral, no subdivision); the others are deep (128 ..) or not, then rectangles (+ 64) or
+// triangles, then 63 steps of the estimated subdivision depth.  The order runs most expensive
+// class first: deep rectangles, deep triangles, the other rectangles, the other triangles.
 constexpr int kCostClasses = 256;
 constexpr int kOnElementClass = 0;
+constexpr int kDeepClass = 128;      // first class of the deep pairs
+constexpr int kDeepCost = 32;        // estimated-cost step from which a pair is deep (d <= L / 16)
 size_t near_scan_temp_bytes(int64_t n);
 hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int rows);  // frees w first
 void near_work_free(NearWork& w);
@@ -217,6 +223,8 @@ hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const d
                        hipStream_t s);
 // entries of w.order that the subdivision walk takes (device pointer; set by near_order)
 inline const uint32_t* near_walk_end(const NearWork& w) { return w.buckets + kCostClasses + kOnElementClass; }
+// entries of w.order with deep subdivisions (all classes from kDeepClass up come first)
+inline const uint32_t* near_heavy_end(const NearWork& w) { return w.buckets + kCostClasses + (kDeepClass - 1); }
 // add each point's segment of per-pair result records to its outputs (collocation; field and
 // gradient evaluations use near_finish)
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,

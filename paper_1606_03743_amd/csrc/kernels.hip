@@ -1415,22 +1415,350 @@ __device__ __forceinline__ void on_element_pairs(const NearArgs& a, unsigned lon
 }
 
 constexpr unsigned kNearWindow = 64;  // entries of the order a wavefront claims at a time
+constexpr int kNearWaves = kBlock / 64;
+constexpr int kFront = 128;  // near nodes of one level of a breadth-first walk (per wavefront)
+constexpr int kLeafQ = 128;  // leaves waiting for the rule: a batch of 64 and one chunk's more
+
+// A pair's walk set-up from the element's record: the element kind, its node geometry in the
+// element's frame, the field point in that frame (offset from the centroid: numbers of the
+// element's size, accurate for points very close to a small element far from the origin)
+// and the threshold (near_dr L)^2.
+template <int MODE>
+__device__ __forceinline__ void pair_setup(const NearArgs& a, uint32_t p, uint32_t e, int& kind, NearGeom& g,
+                                           double& p1, double& p2, double& p3, double& thr2)
+{
+    const Elements& el = a.el;
+    const int64_t ne = el.ne;
+    double P[3];
+    if (MODE == kNearColloc) {
+        P[0] = el.cen[p]; P[1] = el.cen[ne + p]; P[2] = el.cen[2 * ne + p];
+    } else {
+        P[0] = a.pts[p]; P[1] = a.pts[a.n + p]; P[2] = a.pts[2 * a.n + p];
+    }
+    kind = (int64_t)e < el.n_tri ? 0 : 1;
+    double R[kNearRec];  // centroid, frame F, loc, thr2
+    {
+        const double2* rec = reinterpret_cast<const double2*>(el.nrec + (int64_t)e * kNearRec);
+#pragma unroll
+        for (int c = 0; c < 11; ++c) {
+            const double2 v = rec[c];
+            R[2 * c] = v.x;
+            R[2 * c + 1] = v.y;
+        }
+    }
+    const double* F = R + 3;
+    const double* lc = R + 12;
+    const double dxc = P[0] - R[0], dyc = P[1] - R[1], dzc = P[2] - R[2];
+    p1 = fma(F[0], dxc, fma(F[1], dyc, F[2] * dzc));
+    p2 = fma(F[3], dxc, fma(F[4], dyc, F[5] * dzc));
+    p3 = fma(F[6], dxc, fma(F[7], dyc, F[8] * dzc));
+    if (kind == 0) {  // vertices A', B', C' in the frame
+        g.ax = lc[0]; g.ay = lc[1]; g.az = lc[6];
+        g.ux = lc[2] - g.ax; g.uy = lc[3] - g.ay; g.uz = lc[7] - g.az;
+        g.vx = lc[4] - g.ax; g.vy = lc[5] - g.ay; g.vz = lc[8] - g.az;
+    } else {  // e1 = (2 gamma, 2 beta, h1), e2 = (2 alpha, 0, h2); the corner P0 - c
+        g.ux = 2.0 * lc[0]; g.uy = 2.0 * lc[1]; g.uz = lc[6];
+        g.vx = 2.0 * lc[2]; g.vy = 0.0; g.vz = lc[7];
+        g.ax = lc[3]; g.ay = lc[4]; g.az = lc[5];
+    }
+    thr2 = R[21];
+}
+
+// The distance test of node s: its scale h = 2^-level, its geometry, and whether the point is
+// within near_dr times the node's own L of its centroid.
+__device__ __forceinline__ bool visit_node(const NearState& s, const NearGeom& g, double p1, double p2, double p3,
+                                           double thr2, double& h, NodeGeom& nd)
+{
+    h = ldexp(1.0, -s.level);
+    node_geometry(s, g, h, nd);
+    const double qx = p1 - nd.cx, qy = p2 - nd.cy, qz = p3 - nd.cz;
+    const double D2 = fma(qx, qx, fma(qy, qy, qz * qz));
+    return D2 < thr2 * h * h;
+}
+
+// The element's rule on leaf node nd (scale h), weights scaled by the area ratio h^2, added to
+// acc (the sums of near_terms in the element's frame).
+template <int MODE>
+__device__ __forceinline__ void leaf_add(int kind, const NearGeom& g, double p1, double p2, double p3,
+                                         const NodeGeom& nd, double h, const double4* __restrict__ tri_nodes,
+                                         const double4* __restrict__ rect_nodes, int nt, int nr, double (&acc)[7])
+{
+    double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
+    if (kind == 0) {
+        const double q1 = p1 - nd.x0, q2 = p2 - nd.y0, q3 = p3 - nd.z0;
+#pragma unroll 4
+        for (int i = 0; i < nt; ++i) {
+            const double4 q = tri_nodes[i];
+            const double lb = q.y, lc = q.z, w = q.w;
+            const double da = fma(-lb, nd.w1x, fma(-lc, nd.w2x, q1));
+            const double db = fma(-lb, nd.w1y, fma(-lc, nd.w2y, q2));
+            const double dc = fma(-lb, nd.w1z, fma(-lc, nd.w2z, q3));
+            near_terms<MODE>(w, da, db, dc, f);
+        }
+    } else {
+        const double qx = p1 - nd.cx, qy = p2 - nd.cy, qz = p3 - nd.cz;
+        const double H1x = h * (0.5 * g.ux), H1y = h * (0.5 * g.uy), H2x = h * (0.5 * g.vx);
+#pragma unroll 4
+        for (int i = 0; i < nr; ++i) {
+            const double4 q = rect_nodes[i];
+            const double x = q.x, y = q.y, w = q.z;
+            const double da = fma(-x, H1x, fma(-y, H2x, qx));
+            const double db = fma(-x, H1y, qy);
+            near_terms<MODE>(w, da, db, qz, f);
+        }
+    }
+    const double h2 = h * h;
+    constexpr int NS = MODE == kNearGrad ? 7 : (MODE == kNearColloc ? 1 : 4);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) acc[c] = fma(h2, f[c], acc[c]);
+}
+
+// The pair's own result record at its slot (32 bytes for the field, 48 for the gradient);
+// collocation keeps the unit-density potential (the densities are applied per right-hand
+// side when the sums are formed).
+template <int MODE>
+__device__ __forceinline__ void write_record(const NearArgs& a, uint32_t e, unsigned long long cur,
+                                             const double (&acc)[7])
+{
+    const Elements& el = a.el;
+    if (MODE == kNearColloc) {
+        a.res[cur] = acc[0];
+        return;
+    }
+    const double Kq = a.K * el.q[(int64_t)a.rhs * el.ne + e];
+    double F[9];
+    {
+        const double* rec = el.nrec + (int64_t)e * kNearRec + 3;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) F[c] = rec[c];
+    }
+    if (MODE == kNearGrad) {
+        // local tensor m = sum w d d^T / r^5 (d = (da, db, dc)), global M = F^T m F,
+        // dE_i/dx_j = q (delta_ij S3 - 3 M_ij)
+        const double m[3][3] = { { acc[1], acc[4], acc[5] },
+                                 { acc[4], acc[2], acc[6] },
+                                 { acc[5], acc[6], acc[3] } };
+        double U[3][3];  // U[r][v] = sum_b m[r][b] F[b][v]
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) U[r][v] = fma(m[r][0], F[v], fma(m[r][1], F[3 + v], m[r][2] * F[6 + v]));
+        auto M = [&](int u, int v) { return fma(F[u], U[0][v], fma(F[3 + u], U[1][v], F[6 + u] * U[2][v])); };
+        double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
+        r[0] = make_double2(Kq * fma(-3.0, M(0, 0), acc[0]), Kq * fma(-3.0, M(1, 1), acc[0]));
+        r[1] = make_double2(Kq * fma(-3.0, M(2, 2), acc[0]), -3.0 * Kq * M(0, 1));
+        r[2] = make_double2(-3.0 * Kq * M(0, 2), -3.0 * Kq * M(1, 2));
+    } else {
+        // local field sum w (da, db, dc)/r^3, rotated back
+        reinterpret_cast<double4*>(a.res)[cur] = make_double4(
+            Kq * acc[0], Kq * fma(F[0], acc[1], fma(F[3], acc[2], F[6] * acc[3])),
+            Kq * fma(F[1], acc[1], fma(F[4], acc[2], F[7] * acc[3])),
+            Kq * fma(F[2], acc[1], fma(F[5], acc[2], F[8] * acc[3])));
+    }
+}
+
+// A node of a breadth-first walk in one 64-bit word: i, j (24 bits each: depth cap <= 24),
+// orientation, level.
+__device__ __forceinline__ uint64_t pack_node(const NearState& s)
+{
+    return (uint64_t)(uint32_t)s.i | ((uint64_t)(uint32_t)s.j << 24) | ((uint64_t)(s.up ? 1 : 0) << 48) |
+           ((uint64_t)(uint32_t)s.level << 49);
+}
+__device__ __forceinline__ NearState unpack_node(uint64_t v, int kind)
+{
+    NearState s;
+    s.kind = kind;
+    s.i = (int)(v & 0xffffffull);
+    s.j = (int)((v >> 24) & 0xffffffull);
+    s.up = ((v >> 48) & 1ull) != 0;
+    s.level = (int)(v >> 49);
+    return s;
+}
+
+// LDS written by some lanes of a wavefront, read by others: finish the writes first.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Move to the next node of a depth-first walk of the subtree below `root` (level) after
+// finishing node s; false when the walk has returned to the subtree's root.
+__device__ __forceinline__ bool advance_within(NearState& s, int root)
+{
+    while (s.level > root) {
+        const int c = child_index(s);  // s is now the parent
+        if (c < 3) {
+            to_child(s, c + 1);
+            return true;
+        }
+    }
+    return false;
+}
+
+// One lane walks the subtree below the near node s (above the depth cap) depth first.
+template <int MODE>
+__device__ void walk_subtree(NearState s, const NearGeom& g, double p1, double p2, double p3, double thr2,
+                             int max_depth, const double4* __restrict__ tri_nodes,
+                             const double4* __restrict__ rect_nodes, int nt, int nr, double (&acc)[7],
+                             unsigned long long& n_leaves, unsigned long long& n_cap, int& max_level)
+{
+    const int root = s.level;
+    to_child(s, 0);
+    while (true) {
+        double h;
+        NodeGeom nd;
+        const bool near = visit_node(s, g, p1, p2, p3, thr2, h, nd);
+        if (s.level > max_level) max_level = s.level;
+        if (near && s.level < max_depth) {
+            to_child(s, 0);
+            continue;
+        }
+        leaf_add<MODE>(s.kind, g, p1, p2, p3, nd, h, tri_nodes, rect_nodes, nt, nr, acc);
+        n_leaves++;
+        if (near) n_cap++;
+        if (!advance_within(s, root)) break;
+    }
+}
+
+// A pair with a deep subdivision (the leading cost classes), walked by a whole wavefront
+// breadth first: per level, the children of the level's near nodes are tested 64 at a time,
+// the near ones (above the depth cap) form the next level, the others are leaves; leaves
+// wait in LDS until 64 of them can take the rule loop together, one per lane.  A point very
+// close to an element has a near region of some 65 nodes at every level (three node sizes
+// around its foot), so its depth-first walk would take thousands of visits in one lane.
+// Each lane sums its leaves in a fixed order; the lanes' sums are added by a fixed butterfly,
+// so results are reproducible.  More near nodes in a level than kFront: the lane that found
+// one walks its subtree depth first itself.  The visit limit ends the walk after the level in
+// which the pair's visits pass it.
+template <int MODE>
+__device__ void heavy_pair(const NearArgs& a, unsigned long long w, uint64_t* front, uint64_t* leafq,
+                           const double4* __restrict__ tri_nodes, const double4* __restrict__ rect_nodes, int nt,
+                           int nr, int lane, unsigned long long& n_leaves, unsigned long long& n_cap,
+                           unsigned long long& n_limit, int& max_level)
+{
+    const NearPair pr = a.opair[w];
+    const unsigned long long cur = a.slot[a.order[w]];
+    int kind;
+    NearGeom g;
+    double p1, p2, p3, thr2;
+    pair_setup<MODE>(a, pr.point, pr.elem, kind, g, p1, p2, p3, thr2);
+    double acc[7] = { 0, 0, 0, 0, 0, 0, 0 };
+    // the same in every lane: the current level's near nodes (nF, in cur_f), the next level's
+    // (nN), the next child of the level to test (base), the queued leaves (nq), the visits
+    uint64_t* cur_f = front;
+    uint64_t* nxt_f = front + kFront;
+    int nF = 1, nN = 0, base = 0, nq = 0;
+    long long visits = 0;
+    bool done = false;
+    if (a.max_depth <= 0) {  // the rule on the element itself (depth cap 0): the root is the leaf
+        if (lane == 0) {
+            const NearState s{ kind, 0, 0, 0, true };
+            double h;
+            NodeGeom nd;
+            n_leaves++;
+            if (visit_node(s, g, p1, p2, p3, thr2, h, nd)) n_cap++;
+            leafq[0] = pack_node(s);
+        }
+        nq = 1;
+        done = true;
+    } else if (lane == 0) {
+        cur_f[0] = pack_node(NearState{ kind, 0, 0, 0, true });
+    }
+    wave_lds_sync();
+    while (true) {
+        if (!done && base >= 4 * nF) {  // the level is tested: on to the next one
+            uint64_t* t = cur_f;
+            cur_f = nxt_f;
+            nxt_f = t;
+            nF = nN;
+            nN = 0;
+            base = 0;
+            if (nF == 0) {
+                done = true;
+            } else if (visits > a.visit_limit) {  // the limit ends the walk here
+                if (lane == 0) n_limit++;
+                done = true;
+            }
+        }
+        if (nq >= 64 || (done && nq > 0)) {  // a batch of leaves, one per lane
+            const int k = min(nq, 64);
+            if (lane < k) {
+                const NearState t = unpack_node(leafq[lane], kind);
+                double h;
+                NodeGeom nd;
+                (void)visit_node(t, g, p1, p2, p3, thr2, h, nd);
+                leaf_add<MODE>(kind, g, p1, p2, p3, nd, h, tri_nodes, rect_nodes, nt, nr, acc);
+            }
+            const uint64_t rest = lane < nq - k ? leafq[k + lane] : 0ull;
+            wave_lds_sync();
+            if (lane < nq - k) leafq[lane] = rest;
+            wave_lds_sync();
+            nq -= k;
+            continue;
+        }
+        if (done) break;
+        // the next 64 children of the level's near nodes
+        const int c = base + lane;
+        const bool valid = c < 4 * nF;
+        NearState s{ kind, 0, 0, 0, true };
+        bool near = false;
+        if (valid) {
+            s = unpack_node(cur_f[c >> 2], kind);
+            to_child(s, c & 3);
+            double h;
+            NodeGeom nd;
+            near = visit_node(s, g, p1, p2, p3, thr2, h, nd);
+            if (s.level > max_level) max_level = s.level;
+        }
+        visits += (long long)__popcll(__ballot(valid));
+        const bool desc = valid && near && s.level < a.max_depth;
+        const bool leaf = valid && !desc;
+        if (leaf) {
+            n_leaves++;
+            if (near) n_cap++;
+        }
+        // descending children: the next level (index order); past kFront a lane walks its
+        // child's subtree itself
+        const unsigned long long dm = __ballot(desc);
+        const int pos = nN + (int)lanes_below(dm);
+        const bool spill = desc && pos >= kFront;
+        if (desc && !spill) nxt_f[pos] = pack_node(s);
+        nN = min(kFront, nN + (int)__popcll(dm));
+        // leaves: the queue (fewer than 64 wait when a chunk adds at most 64)
+        const unsigned long long lm = __ballot(leaf);
+        if (leaf) leafq[nq + (int)lanes_below(lm)] = pack_node(s);
+        nq += (int)__popcll(lm);
+        base += 64;
+        wave_lds_sync();
+        if (spill)
+            walk_subtree<MODE>(s, g, p1, p2, p3, thr2, a.max_depth, tri_nodes, rect_nodes, nt, nr, acc, n_leaves,
+                               n_cap, max_level);
+    }
+    wave_lds_sync();  // the queue and the levels are reused by the next pair
+    // the lanes' sums added by a fixed butterfly (every lane ends with the same total)
+#pragma unroll
+    for (int c = 0; c < 7; ++c)
+        for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o);
+    if (lane == 0) write_record<MODE>(a, pr.elem, cur, acc);
+}
 
 // MODE: kNearEval (phi, E at field points), kNearColloc (phi at centroids, several density
 // vectors), kNearGrad (field gradient at field points; NaN for a point on its element).
-template <int MODE>
+template <int MODE, bool DEEP>
 __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
 {
-    constexpr bool COLLOC = MODE == kNearColloc;
-    constexpr bool GRAD = MODE == kNearGrad;
-    const Elements& el = a.el;
-    const int64_t ne = el.ne;
-    // the walks: the leading entries of the order (the points lying on their element follow)
-    const unsigned long long total = *a.walk_end;
+    // the walks: the leading entries of the order (the points lying on their element follow);
+    // the first `heavy` of them have deep subdivisions (DEEP: walked breadth first, a wavefront
+    // each; else depth first like the others)
+    const unsigned long long total = *a.walk_end, heavy = DEEP ? *a.heavy_end : 0ull;
     const int lane = lane_id();
     // the rules' nodes in LDS: a leaf's loop reads them at one address for the whole wavefront
     // (from global memory every node would be a vector load and a wait for it)
     extern __shared__ double4 near_rule_nodes[];  // [nt] triangle (la, lb, lc, w), [nr] rectangle (x, y, w, 0)
+    __shared__ uint64_t near_front[kNearWaves][2 * kFront];
+    __shared__ uint64_t near_leafq[kNearWaves][kLeafQ];
     const int nt = a.rules.nt, nr = a.rules.nr;
     for (int i = threadIdx.x; i < nt + nr; i += kBlock) {
         const double* src = i < nt ? a.rules.tri + 4 * i : a.rules.rect + 4 * (i - nt);
@@ -1443,9 +1771,20 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     unsigned long long n_leaves = 0, n_cap = 0, n_limit = 0;
     int max_level = 0;
 
+    // ---- the deep pairs, one per wavefront at a time
+    while (DEEP) {
+        unsigned long long hw = 0;
+        if (lane == 0) hw = atomicAdd(&a.ctr->heavy_cursor, 1ull);
+        hw = bcast_u64(hw, 0);
+        if (hw >= heavy) break;
+        heavy_pair<MODE>(a, hw, near_front[threadIdx.x / 64], near_leafq[threadIdx.x / 64], tri_nodes, rect_nodes,
+                         nt, nr, lane, n_leaves, n_cap, n_limit, max_level);
+    }
+
+    // ---- the other pairs, one per lane, depth first
     bool active = false;
     NearState st{ 0, 0, 0, 0, true };
-    uint32_t p = 0, e = 0;
+    uint32_t e = 0;
     unsigned long long cur = 0;  // result slot of the pair in hand
     NearGeom g{};
     double p1 = 0.0, p2 = 0.0, p3 = 0.0;  // the field point in the element's frame
@@ -1456,7 +1795,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     // entries are pairs of one cost class, so the lanes walk trees of one kind and similar size
     unsigned long long win = 0, win_end = 0;
 
-    while (total > 0) {
+    while (total > heavy) {
         // ---- refill from the window (a new window when it is used up)
         const unsigned long long need = __ballot(!active);
         if (need) {
@@ -1464,7 +1803,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 const int first = __ffsll((long long)need) - 1;
                 unsigned long long b = 0;
                 if (lane == first) b = atomicAdd(&a.ctr->cursor, (unsigned long long)kNearWindow);
-                win = bcast_u64(b, first);
+                win = heavy + bcast_u64(b, first);
                 win_end = win + kNearWindow;
             }
             const unsigned rank = lanes_below(need);
@@ -1475,51 +1814,13 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
                 if (w >= total) break;
                 const NearPair pr = a.opair[w];  // most expensive pairs first
                 cur = a.slot[a.order[w]];
-                p = pr.point;
                 e = pr.elem;
-                double P[3];
-                if (COLLOC) {
-                    P[0] = el.cen[p]; P[1] = el.cen[ne + p]; P[2] = el.cen[2 * ne + p];
-                } else {
-                    P[0] = a.pts[p]; P[1] = a.pts[a.n + p]; P[2] = a.pts[2 * a.n + p];
-                }
-                st.kind = (int64_t)e < el.n_tri ? 0 : 1;
-                // the element's record: centroid, frame F, loc, thr2
-                double R[kNearRec];
-                {
-                    const double2* rec = reinterpret_cast<const double2*>(el.nrec + (int64_t)e * kNearRec);
-#pragma unroll
-                    for (int c = 0; c < 11; ++c) {
-                        const double2 v = rec[c];
-                        R[2 * c] = v.x;
-                        R[2 * c + 1] = v.y;
-                    }
-                }
-                const double* F = R + 3;
-                const double* lc = R + 12;
-                // the point in the element's frame (offset from the centroid: numbers of the
-                // element's size, accurate for points very close to a small element far from
-                // the origin)
-                const double dxc = P[0] - R[0], dyc = P[1] - R[1], dzc = P[2] - R[2];
-                p1 = fma(F[0], dxc, fma(F[1], dyc, F[2] * dzc));
-                p2 = fma(F[3], dxc, fma(F[4], dyc, F[5] * dzc));
-                p3 = fma(F[6], dxc, fma(F[7], dyc, F[8] * dzc));
-                if (st.kind == 0) {  // vertices A', B', C' in the frame
-                    g.ax = lc[0]; g.ay = lc[1]; g.az = lc[6];
-                    g.ux = lc[2] - g.ax; g.uy = lc[3] - g.ay; g.uz = lc[7] - g.az;
-                    g.vx = lc[4] - g.ax; g.vy = lc[5] - g.ay; g.vz = lc[8] - g.az;
-                } else {  // e1 = (2 gamma, 2 beta, h1), e2 = (2 alpha, 0, h2); the corner P0 - c
-                    g.ux = 2.0 * lc[0]; g.uy = 2.0 * lc[1]; g.uz = lc[6];
-                    g.vx = 2.0 * lc[2]; g.vy = 0.0; g.vz = lc[7];
-                    g.ax = lc[3]; g.ay = lc[4]; g.az = lc[5];
-                }
-                thr2 = R[21];
+                pair_setup<MODE>(a, pr.point, pr.elem, st.kind, g, p1, p2, p3, thr2);
 #pragma unroll
                 for (int c = 0; c < 7; ++c) acc[c] = 0.0;
                 visits = 0;
                 active = true;
-                st.level = 0; st.i = 0; st.j = 0; st.up = true;
-
+                st.i = 0; st.j = 0; st.up = true;
                 if (a.max_depth <= 0) st.level = 0;  // evaluate the rule on the element itself (depth cap)
                 else st.level = 1;                   // first child of the root
             }
@@ -1528,48 +1829,17 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
         if (!active) continue;
         // ---- visit nodes from st down to the next leaf (each lane on its own: internal nodes
         // cost a distance test, so the lanes then take the leaf loop together)
-        double h, qx, qy, qz;
+        double h;
         bool is_near;
         NodeGeom nd;
         while (true) {
-            h = ldexp(1.0, -st.level);
-            node_geometry(st, g, h, nd);
-            qx = p1 - nd.cx; qy = p2 - nd.cy; qz = p3 - nd.cz;
-            const double D2 = fma(qx, qx, fma(qy, qy, qz * qz));
-            is_near = D2 < thr2 * h * h;
+            is_near = visit_node(st, g, p1, p2, p3, thr2, h, nd);
             ++visits;
             if (st.level > max_level) max_level = st.level;
             if (!(is_near && st.level < a.max_depth && visits <= a.visit_limit)) break;
             to_child(st, 0);
         }
-        // leaf: the element's rule on this node, weights scaled by the area ratio h^2
-        double f[7] = { 0, 0, 0, 0, 0, 0, 0 };
-        if (st.kind == 0) {
-            const double q1 = p1 - nd.x0, q2 = p2 - nd.y0, q3 = p3 - nd.z0;
-#pragma unroll 4
-            for (int i = 0; i < nt; ++i) {
-                const double4 q = tri_nodes[i];
-                const double lb = q.y, lc = q.z, w = q.w;
-                const double da = fma(-lb, nd.w1x, fma(-lc, nd.w2x, q1));
-                const double db = fma(-lb, nd.w1y, fma(-lc, nd.w2y, q2));
-                const double dc = fma(-lb, nd.w1z, fma(-lc, nd.w2z, q3));
-                near_terms<MODE>(w, da, db, dc, f);
-            }
-        } else {
-            const double H1x = h * (0.5 * g.ux), H1y = h * (0.5 * g.uy), H2x = h * (0.5 * g.vx);
-#pragma unroll 4
-            for (int i = 0; i < nr; ++i) {
-                const double4 q = rect_nodes[i];
-                const double x = q.x, y = q.y, w = q.z;
-                const double da = fma(-x, H1x, fma(-y, H2x, qx));
-                const double db = fma(-x, H1y, qy);
-                near_terms<MODE>(w, da, db, qz, f);
-            }
-        }
-        const double h2 = h * h;
-        constexpr int NS = GRAD ? 7 : (COLLOC ? 1 : 4);
-#pragma unroll
-        for (int c = 0; c < NS; ++c) acc[c] = fma(h2, f[c], acc[c]);
+        leaf_add<MODE>(st.kind, g, p1, p2, p3, nd, h, tri_nodes, rect_nodes, nt, nr, acc);
         n_leaves++;
         if (is_near) n_cap++;
         bool finished;
@@ -1580,44 +1850,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
             finished = !advance(st);
         }
         if (!finished) continue;
-
-        // ---- the pair's own result record at its slot, written at once (32 bytes for the
-        // field, 48 for the gradient); collocation keeps the unit-density potential (the
-        // densities are applied per right-hand side when the sums are formed)
-        if (COLLOC) {
-            a.res[cur] = acc[0];
-        } else {
-            const double Kq = a.K * el.q[(int64_t)a.rhs * ne + e];
-            double F[9];
-            {
-                const double* rec = el.nrec + (int64_t)e * kNearRec + 3;
-#pragma unroll
-                for (int c = 0; c < 9; ++c) F[c] = rec[c];
-            }
-            if (GRAD) {
-                // local tensor m = sum w d d^T / r^5 (d = (da, db, dc)), global M = F^T m F,
-                // dE_i/dx_j = q (delta_ij S3 - 3 M_ij)
-                const double m[3][3] = { { acc[1], acc[4], acc[5] },
-                                         { acc[4], acc[2], acc[6] },
-                                         { acc[5], acc[6], acc[3] } };
-                double U[3][3];  // U[r][v] = sum_b m[r][b] F[b][v]
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int v = 0; v < 3; ++v) U[r][v] = fma(m[r][0], F[v], fma(m[r][1], F[3 + v], m[r][2] * F[6 + v]));
-                auto M = [&](int u, int v) { return fma(F[u], U[0][v], fma(F[3 + u], U[1][v], F[6 + u] * U[2][v])); };
-                double2* r = reinterpret_cast<double2*>(a.res + 6 * cur);
-                r[0] = make_double2(Kq * fma(-3.0, M(0, 0), acc[0]), Kq * fma(-3.0, M(1, 1), acc[0]));
-                r[1] = make_double2(Kq * fma(-3.0, M(2, 2), acc[0]), -3.0 * Kq * M(0, 1));
-                r[2] = make_double2(-3.0 * Kq * M(0, 2), -3.0 * Kq * M(1, 2));
-            } else {
-                // local field sum w (da, db, dc)/r^3, rotated back
-                reinterpret_cast<double4*>(a.res)[cur] = make_double4(
-                    Kq * acc[0], Kq * fma(F[0], acc[1], fma(F[3], acc[2], F[6] * acc[3])),
-                    Kq * fma(F[1], acc[1], fma(F[4], acc[2], F[7] * acc[3])),
-                    Kq * fma(F[2], acc[1], fma(F[5], acc[2], F[8] * acc[3])));
-            }
-        }
+        write_record<MODE>(a, e, cur, acc);
         active = false;
         st.level = 0;
     }
@@ -1788,9 +2021,10 @@ hipError_t launch_near(const NearArgs& a, int mode, hipStream_t s)
     // shared cursor passes the pair count
     const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>(1024, (a.near_cap + kBlock - 1) / kBlock));
     const size_t lds = (size_t)(a.rules.nt + a.rules.nr) * sizeof(double4);
-    if (mode == kNearColloc) near_kernel<kNearColloc><<<blocks, kBlock, lds, s>>>(a);
-    else if (mode == kNearGrad) near_kernel<kNearGrad><<<blocks, kBlock, lds, s>>>(a);
-    else near_kernel<kNearEval><<<blocks, kBlock, lds, s>>>(a);
+    if (mode == kNearColloc) near_kernel<kNearColloc, true><<<blocks, kBlock, lds, s>>>(a);
+    else if (mode == kNearGrad) near_kernel<kNearGrad, true><<<blocks, kBlock, lds, s>>>(a);
+    else if (a.deep) near_kernel<kNearEval, true><<<blocks, kBlock, lds, s>>>(a);
+    else near_kernel<kNearEval, false><<<blocks, kBlock, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1927,6 +2161,7 @@ __global__ void reset_near_stage_kernel(DevCounters* c)
     c->on_surface = 0ull;
     c->max_depth = 0ull;
     c->visit_limit_hits = 0ull;
+    c->heavy_cursor = 0ull;
 }
 
 hipError_t launch_reset_near_stage(DevCounters* c, hipStream_t s)

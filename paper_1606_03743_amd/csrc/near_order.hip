@@ -123,47 +123,73 @@ __global__ void finish_points_kernel(const uint32_t* __restrict__ start, const u
     (c == 0 ? d0 : d1 + (int64_t)(c - 1) * n)[q] = v;
 }
 
-// Cost class of a near pair (higher = more subdivision leaves expected within a kind): 4
-// classes per octave of L / d with d^2 = h^2 + max(0, rho - R)^2 (h the height above the
-// element's plane, rho the in-plane distance from the centroid, R the distance of the farthest
-// vertex from it), rectangles above triangles; the costliest class of the kind where d
-// vanishes without the point lying on the element.  Kind-major classes keep the two rules
-// apart: the near kernel's wavefronts take windows of the order far apart in time, and a
-// wavefront whose lanes mix both kinds runs both rule loops.  A point on the element (the closed-form
-// integral, no subdivision) takes class kOnElementClass, which the order puts last and the
-// subdivision walk leaves to the on-element kernel.
+__device__ __forceinline__ double dot3(const double* a, const double* b) { return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2])); }
+
+// Squared distance from p to the triangle (0, b, c) (p, b, c relative to its first vertex):
+// the closest point by the Voronoi regions of the vertices, the edges and the face.
+__device__ __forceinline__ double triangle_distance2(const double (&p)[3], const double* b, const double* c)
+{
+    double q[3];  // the closest point
+    const double d1 = dot3(b, p), d2 = dot3(c, p);
+    const double bp[3] = { p[0] - b[0], p[1] - b[1], p[2] - b[2] };
+    const double d3 = dot3(b, bp), d4 = dot3(c, bp);
+    const double cp[3] = { p[0] - c[0], p[1] - c[1], p[2] - c[2] };
+    const double d5 = dot3(b, cp), d6 = dot3(c, cp);
+    const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        q[0] = q[1] = q[2] = 0.0;
+    } else if (d3 >= 0.0 && d4 <= d3) {
+        q[0] = b[0]; q[1] = b[1]; q[2] = b[2];
+    } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        const double t = d1 / (d1 - d3);
+        q[0] = t * b[0]; q[1] = t * b[1]; q[2] = t * b[2];
+    } else if (d6 >= 0.0 && d5 <= d6) {
+        q[0] = c[0]; q[1] = c[1]; q[2] = c[2];
+    } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        const double t = d2 / (d2 - d6);
+        q[0] = t * c[0]; q[1] = t * c[1]; q[2] = t * c[2];
+    } else if (va <= 0.0 && d4 - d3 >= 0.0 && d5 - d6 >= 0.0) {
+        const double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        q[0] = fma(t, c[0] - b[0], b[0]); q[1] = fma(t, c[1] - b[1], b[1]); q[2] = fma(t, c[2] - b[2], b[2]);
+    } else {
+        const double den = 1.0 / (va + vb + vc), v = vb * den, w = vc * den;
+        q[0] = fma(v, b[0], w * c[0]); q[1] = fma(v, b[1], w * c[1]); q[2] = fma(v, b[2], w * c[2]);
+    }
+    const double r[3] = { p[0] - q[0], p[1] - q[1], p[2] - q[2] };
+    return dot3(r, r);
+}
+
+// Cost class of a near pair (higher = more subdivision leaves expected): 4 steps per octave of
+// L / d, d the distance from the point to the element (its closest point), the costliest step
+// where d vanishes without the point lying on the element.  Deep pairs (d <= L / 16: a near
+// region at some five levels or more) come first, walked by a wavefront each; then the
+// others.  Rectangles come before triangles in each group: the near kernel's wavefronts take
+// windows of the order far apart in time, and a wavefront whose lanes mix both kinds runs
+// both rule loops.
 __device__ __forceinline__ int cost_class(const double* __restrict__ pts, int64_t n, const Elements& el, NearPair pr)
 {
-    const int64_t ne = el.ne, e = pr.elem, p = pr.point;
+    const int64_t e = pr.elem, p = pr.point;
     const bool tri = e < el.n_tri;
-    {
-        const double X[3] = { pts[p], pts[n + p], pts[2 * n + p] };
-        double G[9], P[3];
-        if (point_on_element(el, e, tri, X, G, P)) return kOnElementClass;
-    }
-    const double dx = pts[p] - el.cen[e], dy = pts[n + p] - el.cen[ne + e], dz = pts[2 * n + p] - el.cen[2 * ne + e];
-    const double h = fabs(dx * el.nrm[e] + dy * el.nrm[ne + e] + dz * el.nrm[2 * ne + e]);
-    const double rho = sqrt(fmax(fma(dx, dx, fma(dy, dy, dz * dz)) - h * h, 0.0));
-    double R2 = 0.0;
+    const double X[3] = { pts[p], pts[n + p], pts[2 * n + p] };
+    double G[9], P[3];
+    if (point_on_element(el, e, tri, X, G, P)) return kOnElementClass;
+    double d2;
     if (tri) {
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const double vx = el.geom[(3 * m) * ne + e] - el.cen[e];
-            const double vy = el.geom[(3 * m + 1) * ne + e] - el.cen[ne + e];
-            const double vz = el.geom[(3 * m + 2) * ne + e] - el.cen[2 * ne + e];
-            R2 = fmax(R2, fma(vx, vx, fma(vy, vy, vz * vz)));
-        }
-    } else {  // half diagonal
-        const double vx = el.geom[3 * ne + e] + el.geom[6 * ne + e], vy = el.geom[4 * ne + e] + el.geom[7 * ne + e],
-                     vz = el.geom[5 * ne + e] + el.geom[8 * ne + e];
-        R2 = 0.25 * fma(vx, vx, fma(vy, vy, vz * vz));
+        const double b[3] = { G[3] - G[0], G[4] - G[1], G[5] - G[2] };
+        const double c[3] = { G[6] - G[0], G[7] - G[1], G[8] - G[2] };
+        d2 = triangle_distance2(P, b, c);
+    } else {  // P0 + u e1 + v e2 with u, v clamped to [0, 1] (orthogonal sides)
+        const double* e1 = G + 3;
+        const double* e2 = G + 6;
+        const double u = fmin(fmax(dot3(P, e1) / dot3(e1, e1), 0.0), 1.0);
+        const double v = fmin(fmax(dot3(P, e2) / dot3(e2, e2), 0.0), 1.0);
+        const double r[3] = { P[0] - u * e1[0] - v * e2[0], P[1] - u * e1[1] - v * e2[1], P[2] - u * e1[2] - v * e2[2] };
+        d2 = dot3(r, r);
     }
-    const double out = fmax(rho - sqrt(R2), 0.0);
-    const double d2 = fma(out, out, h * h);
     const double L = el.L[e];
-    int c = 127;
-    if (d2 > 1e-24 * L * L) c = min(127, max(1, (int)floor(4.0 * (log2(L) - 0.5 * log2(d2)) + 16.0)));
-    return tri ? c : 128 + c;
+    int c = 63;
+    if (d2 > 1e-24 * L * L) c = min(63, max(1, (int)floor(4.0 * (log2(L) - 0.5 * log2(d2)) + 16.0)));
+    return (c >= kDeepCost ? kDeepClass : 0) + (tri ? 0 : 64) + c;
 }
 
 // Clears the per-class counts and cursors (buckets) and the per-point counts and cursors.

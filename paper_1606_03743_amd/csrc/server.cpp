@@ -352,6 +352,10 @@ bool Server::near_stage(Slot& s, std::string& err)
     na.order = s.nw.order;
     na.opair = s.nw.opair;
     na.walk_end = near_walk_end(s.nw);
+    na.heavy_end = near_heavy_end(s.nw);
+    // depth first only: the breadth-first walk needs more registers than a finished far-field
+    // wave of another stream frees, so its workgroups would wait for a long batch to drain
+    na.deep = 0;
     na.res = s.nw.res;
     na.ctr = s.d_ctr;
     na.near_dr2 = env_.near_dr * env_.near_dr;
