@@ -269,7 +269,7 @@ def main():
         "node_interactions_per_s": node_int * args.steps / dt64,
         "near": {"pairs": st64["near_pairs"], "leaves": st64["leaves"], "max_depth": st64["max_depth"],
                  "cap_hits": st64["cap_hits"], "stage_ms": st64["near_ms"],
-                 "near_kernel_rocprof_ms": trace_avg_ms("near_kernel<0>"),
+                 "near_kernel_rocprof_ms": trace_avg_ms("near_kernel<0, true>"),
                  "near_list_kernel_rocprof_ms": trace_avg_ms("near_list_kernel"),
                  "near_kernel_write_bytes": profile_value(TRAFFIC_FILE, "near_field_write_bytes_per_launch"),
                  "near_kernel_read_bytes": profile_value(TRAFFIC_FILE, "near_field_read_bytes_per_launch"),
