@@ -1771,8 +1771,9 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
     unsigned long long n_leaves = 0, n_cap = 0, n_limit = 0;
     int max_level = 0;
 
-    // ---- the deep pairs, one per wavefront at a time
-    while (DEEP) {
+    // ---- the deep pairs, one per wavefront at a time (no claim at all without them: a
+    // launch's thousand wavefronts claiming one counter cost microseconds)
+    while (DEEP && heavy > 0) {
         unsigned long long hw = 0;
         if (lane == 0) hw = atomicAdd(&a.ctr->heavy_cursor, 1ull);
         hw = bcast_u64(hw, 0);
