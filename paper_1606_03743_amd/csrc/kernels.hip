@@ -1944,6 +1944,12 @@ hipError_t far_eval_dispatch(const FarArgs& a, hipStream_t s)
         return far_eval_launch<true, 0, 0, 0, 0, 0, 0, 0, 0, MIXED, PPT, false>(a, s);
     }
     const int nt = a.rules.nt, nr = a.rules.nr;
+    // a small evaluation (fewer than 1024 workgroups at three points per lane: under one
+    // wavefront per SIMD and four per CU) takes one point per lane: more wavefronts hide the
+    // latency of the dependent FP64 chains
+    const bool small = !MIXED && (a.n + 3 * kBlock - 1) / (3 * kBlock) * a.n_split < 1024;
+    if (small && nr == 49 && nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, 1, false>(a, s);
+    if (small && nr == 49 && nt == 33) return far_eval_launch<false, 33, 49, 0, 0, 0, 0, 0, 0, MIXED, 1, false>(a, s);
     if (nr == 49) {
         if (nt == 7) return far_eval_launch<false, 7, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
         if (nt == 12) return far_eval_launch<false, 12, 49, 0, 0, 0, 0, 0, 0, MIXED, PPT_LONG, false>(a, s);
@@ -2035,11 +2041,11 @@ hipError_t launch_near_list(const double* pts, int64_t n, const Elements& el, Ne
     if (n <= 0 || el.ne <= 0) return hipSuccess;
     const int64_t blocks = (n + kListPoints - 1) / kListPoints;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    // few point blocks (a small evaluation): split the elements into chunks (multiples of 64
+    // few point blocks (a small evaluation): split the elements into chunks (multiples of 16
     // elements), up to about 2048 workgroups in all
-    const int64_t units = (el.ne + 63) / 64;
+    const int64_t units = (el.ne + 15) / 16;
     const int64_t split = std::max<int64_t>(1, std::min<int64_t>({ (2048 + blocks - 1) / blocks, units, 65535 }));
-    const int64_t chunk = ((units + split - 1) / split) * 64;
+    const int64_t chunk = ((units + split - 1) / split) * 16;
     const int64_t chunks = (el.ne + chunk - 1) / chunk;
     near_list_kernel<<<dim3((unsigned)blocks, (unsigned)chunks), kBlock, 0, s>>>(pts, n, el, list, cap, ctr, chunk);
     return hipGetLastError();

@@ -242,11 +242,21 @@ __global__ void scatter_kernel(const NearPair* __restrict__ list, const DevCount
                                NearPair* __restrict__ grouped, uint32_t* __restrict__ origin)
 {
     __shared__ uint32_t hist[kCostClasses], base[kCostClasses], first[kCostClasses];
+    __shared__ uint32_t wave_total[kWavesPerBlock];
     {
-        hist[threadIdx.x] = buckets[threadIdx.x];
+        // the class starts: the counts of all higher classes (a suffix sum, by the wavefronts'
+        // shuffles and their totals)
+        const uint32_t v = buckets[threadIdx.x];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        uint32_t inc = v;  // v and the counts of the higher classes of this wavefront
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_down(inc, o);
+            if (lane + o < 64) inc += t;
+        }
+        if (lane == 0) wave_total[wave] = inc;
         __syncthreads();
-        uint32_t st = 0;
-        for (int k = kCostClasses - 1; k > (int)threadIdx.x; --k) st += hist[k];
+        uint32_t st = inc - v;
+        for (int w = wave + 1; w < kWavesPerBlock; ++w) st += wave_total[w];
         first[threadIdx.x] = st;
         if (blockIdx.x == 0) buckets[kCostClasses + threadIdx.x] = st;
         __syncthreads();
