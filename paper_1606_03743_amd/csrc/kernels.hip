@@ -53,6 +53,11 @@ __device__ __forceinline__ float rsqrt32(float x) { return __builtin_amdgcn_rsqf
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
+// The lanes of the wavefront for which pred holds.  A comparison's own lane mask: __ballot
+// takes an int, and turning the comparison into one and back costs two more vector
+// instructions per call.
+__device__ __forceinline__ unsigned long long lane_mask(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
+
 // number of set bits of m below this lane
 __device__ __forceinline__ unsigned lanes_below(unsigned long long m)
 {
@@ -71,7 +76,7 @@ __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v, in
 __device__ __forceinline__ void record_near(bool is_near, uint32_t p, uint32_t e, NearPair* list,
                                             unsigned long long cap, DevCounters* ctr)
 {
-    const unsigned long long m = __ballot(is_near);
+    const unsigned long long m = lane_mask(is_near);
     if (m == 0ull) return;
     const int first = __ffsll((long long)m) - 1;
     unsigned long long base = 0;
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void near_list_kernel(const double* __restr
             const double dz = fmax(fmax(b2 - cz, cz - b5), 0.0);
             hit = fma(dx, dx, fma(dy, dy, dz * dz)) < t2;
         }
-        const unsigned long long m = __ballot(hit);
+        const unsigned long long m = lane_mask(hit);
         if (m) {
             int base = 0;
             if (lane_id() == 0) base = atomicAdd(&ncand, __popcll(m));
@@ -956,6 +961,20 @@ __device__ __forceinline__ void exp_to_rows(const Local<PPT, T>& L, T (&o)[4][PP
 // N0..N3 > 0: compile-time counts (the levels' weights are then all positive).
 // Triangles take the expanded form throughout; rectangles the rows form for a 7 x 7 last
 // level, the expanded form (turned into the rows form's local field) for the others.
+// Terms summed by the wavefront (w: pairs at each wavefront level) and at the pairs' own
+// levels (n: pairs at levels 0, 1, 2 of nc in all), the levels having o1, o2 - o1, o3 - o2 and
+// nn - o3 nodes.
+__device__ __forceinline__ void add_terms(unsigned w0, unsigned w1, unsigned w2, unsigned w3, unsigned nc,
+                                          unsigned n0, unsigned n1, unsigned n2, int o1, int o2, int o3, int nn,
+                                          unsigned long long& terms, unsigned long long& terms_pair)
+{
+    terms += (unsigned long long)w0 * (unsigned)o1 + (unsigned long long)w1 * (unsigned)(o2 - o1) +
+             (unsigned long long)w2 * (unsigned)(o3 - o2) + (unsigned long long)w3 * (unsigned)(nn - o3);
+    terms_pair += (unsigned long long)n0 * (unsigned)o1 + (unsigned long long)n1 * (unsigned)(o2 - o1) +
+                  (unsigned long long)n2 * (unsigned)(o3 - o2) +
+                  (unsigned long long)(nc - n0 - n1 - n2) * (unsigned)(nn - o3);
+}
+
 template <int N0, int N1, int N2, int N3, bool TRI, bool MIXED, int PPT, int MODE, typename Lds>
 __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, PointSet<PPT, MODE>& P, int64_t e_begin,
                                                   int64_t e_end, unsigned long long& terms,
@@ -977,8 +996,14 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
         tf.nc[2] = TriOrbits<N2>::nc; tf.n21[2] = 3 * TriOrbits<N2>::n21;
         tf.nc[3] = TriOrbits<N3>::nc; tf.n21[3] = 3 * TriOrbits<N3>::n21;
     }
+    unsigned long long vmask[PPT];  // the lanes with a point, per point of the lane
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) vmask[k] = lane_mask(P.valid[k]);
     for (int64_t t0 = e_begin; t0 < e_end; t0 += TE) {
         const int te = (int)min((int64_t)TE, e_end - t0);
+        // the tile's pair counts (scalar, 32 bits: at most 64 PPT TE per tile): summed by the
+        // wavefront at each of its levels, and at the pairs' own levels (all, level 0, 1, 2)
+        unsigned w0 = 0, w1 = 0, w2 = 0, w3 = 0, nc = 0, n0 = 0, n1 = 0, n2 = 0;
         __syncthreads();
         // the 7 x 7 last level of the rectangles keeps its weights (rows form)
         const int nfold = !FOLD ? 0 : (tensor_group<TRI, N3>() > 0 ? o3 : nn);
@@ -990,30 +1015,42 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             double D2[PPT];
             Local<PPT, T> L;
             to_frame<FR, !TRI && !GRAD>(s, j, P.x, P.y, P.z, D2, L);
-            bool nr[PPT];
-            int lvl[PPT];
+            // the level each pair's distance ratio asks for, as wavefront masks straight from the
+            // comparisons: pairs for which level 0 suffices, then level 1, level 2, and every far
+            // pair (near pairs are listed by near_list_kernel and contribute nothing here); the
+            // wavefront's level and the term counts are then scalar work on the masks
+            const double lim0 = c0 * thr2, lim1 = c1 * thr2, lim2 = c2 * thr2;
+            bool far[PPT];
+            unsigned long long u0 = 0, u1 = 0, u2 = 0, u3 = 0;  // the lanes with a pair at each level
+            unsigned ec = 0;                                      // the element's far pairs
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                nr[k] = P.valid[k] && (D2[k] < thr2);  // listed by near_list_kernel
-                lvl[k] = D2[k] >= c0 * thr2 ? 0 : (D2[k] >= c1 * thr2 ? 1 : (D2[k] >= c2 * thr2 ? 2 : 3));
-                if (nr[k] || !P.valid[k]) lvl[k] = -1;  // contributes nothing
+                // masks of plain comparisons only (the backend turns a mask of a combined
+                // condition into a vector select and another comparison); the rest is scalar
+                far[k] = P.valid[k] && !(D2[k] < thr2);
+                const unsigned long long mf = vmask[k] & ~lane_mask(D2[k] < thr2);
+                const unsigned long long m0 = mf & lane_mask(D2[k] >= lim0);
+                const unsigned long long m1 = mf & lane_mask(D2[k] >= lim1) & ~m0;
+                const unsigned long long m2 = mf & lane_mask(D2[k] >= lim2) & ~(m0 | m1);
+                u0 |= m0; u1 |= m1; u2 |= m2; u3 |= mf & ~(m0 | m1 | m2);
+                ec += (unsigned)__popcll(mf);
+                n0 += (unsigned)__popcll(m0);
+                n1 += (unsigned)__popcll(m1);
+                n2 += (unsigned)__popcll(m2);
             }
-            // the finest level any lane of the wavefront needs
-            int mx = -1;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) mx = max(mx, lvl[k]);
-            const int wl = __ballot(mx >= 3) ? 3 : (__ballot(mx >= 2) ? 2 : (__ballot(mx >= 1) ? 1 : (__ballot(mx >= 0) ? 0 : -1)));
+            // the finest level any pair of the wavefront needs
+            const int wl = u3 ? 3 : (u2 ? 2 : (u1 ? 1 : (u0 ? 0 : -1)));
             if (wl < 0) continue;
+            nc += ec;
             T o[Sums<MODE>::kNode][PPT];
             const int b = j * nn;
-            int nw;
-            if (wl == 0) { element_sum<N0, 0, FOLD, TRI, PPT, MODE>(s, j, b, o1, L, o); nw = o1; }
-            else if (wl == 1) { element_sum<N1, 0, FOLD, TRI, PPT, MODE>(s, j, b + o1, o2 - o1, L, o); nw = o2 - o1; }
-            else if (wl == 2) { element_sum<N2, 0, FOLD, TRI, PPT, MODE>(s, j, b + o2, o3 - o2, L, o); nw = o3 - o2; }
+            if (wl == 0) { element_sum<N0, 0, FOLD, TRI, PPT, MODE>(s, j, b, o1, L, o); w0 += ec; }
+            else if (wl == 1) { element_sum<N1, 0, FOLD, TRI, PPT, MODE>(s, j, b + o1, o2 - o1, L, o); w1 += ec; }
+            else if (wl == 2) { element_sum<N2, 0, FOLD, TRI, PPT, MODE>(s, j, b + o2, o3 - o2, L, o); w2 += ec; }
             else {
                 constexpr int G3 = tensor_group<TRI, N3>();
                 element_sum<N3, G3, FOLD && (TRI || G3 == 0), TRI, PPT, MODE>(s, j, b + o3, nn - o3, L, o);
-                nw = nn - o3;
+                w3 += ec;
             }
             if constexpr (!TRI && !GRAD) {
                 // rows form for the rotation back; the 7 x 7 last level is in it already
@@ -1021,30 +1058,19 @@ __device__ __forceinline__ void far_eval_dr_range(const FarArgs& a, Lds& s, Poin
             }
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (lvl[k] >= 0) add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
-            // terms summed by the wavefront and the terms of the pairs' own levels (the
-            // per-pair choice), counted from ballots in scalar arithmetic
-            unsigned nc = 0, n0 = 0, n1 = 0, n2 = 0;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                nc += (unsigned)__popcll(__ballot(lvl[k] >= 0));
-                n0 += (unsigned)__popcll(__ballot(lvl[k] == 0));
-                n1 += (unsigned)__popcll(__ballot(lvl[k] == 1));
-                n2 += (unsigned)__popcll(__ballot(lvl[k] == 2));
-            }
-            terms += (unsigned long long)nc * (unsigned)nw;
-            terms_pair += (unsigned long long)n0 * (unsigned)o1 + (unsigned long long)n1 * (unsigned)(o2 - o1) +
-                          (unsigned long long)n2 * (unsigned)(o3 - o2) +
-                          (unsigned long long)(nc - n0 - n1 - n2) * (unsigned)(nn - o3);
+                if (far[k]) add_element<FR, PPT, MODE>(P, k, q, s, j, L, o);
         }
+        add_terms(w0, w1, w2, w3, nc, n0, n1, n2, o1, o2, o3, nn, terms, terms_pair);
     }
 }
 
 // DR == false: one rule per kind, NT / NR nodes.  DR == true: levels (T0..T3 / R0..R3).
 // GRAD: field gradient instead of potential and field.  Compiled node counts (NT, NR > 0)
 // are used only for rules whose weights are all positive (their nodes are folded).
+// The FP64 gradient with levels is held to three wavefronts per SIMD (167 registers, a few
+// bytes of spill): left alone the compiler takes 220 and runs two, 3.6 % slower.
 template <bool DR, int NT, int NR, int T1, int T2, int T3, int R1, int R2, int R3, bool MIXED, int PPT, bool GRAD>
-__global__ __launch_bounds__(kBlock) void far_eval_kernel(FarArgs a)
+__global__ __launch_bounds__(kBlock, (DR && GRAD && !MIXED) ? 3 : 1) void far_eval_kernel(FarArgs a)
 {
     constexpr int MODE = GRAD ? kFarGrad : kFarField;
     constexpr int NO = Sums<MODE>::kOut;
@@ -1712,7 +1738,7 @@ __device__ void heavy_pair(const NearArgs& a, unsigned long long w, uint64_t* fr
             near = visit_node(s, g, p1, p2, p3, thr2, h, nd);
             if (s.level > max_level) max_level = s.level;
         }
-        visits += (long long)__popcll(__ballot(valid));
+        visits += (long long)__popcll(lane_mask(valid));
         const bool desc = valid && near && s.level < a.max_depth;
         const bool leaf = valid && !desc;
         if (leaf) {
@@ -1721,13 +1747,13 @@ __device__ void heavy_pair(const NearArgs& a, unsigned long long w, uint64_t* fr
         }
         // descending children: the next level (index order); past kFront a lane walks its
         // child's subtree itself
-        const unsigned long long dm = __ballot(desc);
+        const unsigned long long dm = lane_mask(desc);
         const int pos = nN + (int)lanes_below(dm);
         const bool spill = desc && pos >= kFront;
         if (desc && !spill) nxt_f[pos] = pack_node(s);
         nN = min(kFront, nN + (int)__popcll(dm));
         // leaves: the queue (fewer than 64 wait when a chunk adds at most 64)
-        const unsigned long long lm = __ballot(leaf);
+        const unsigned long long lm = lane_mask(leaf);
         if (leaf) leafq[nq + (int)lanes_below(lm)] = pack_node(s);
         nq += (int)__popcll(lm);
         base += 64;
@@ -1798,7 +1824,7 @@ __global__ __launch_bounds__(kBlock) void near_kernel(NearArgs a)
 
     while (total > heavy) {
         // ---- refill from the window (a new window when it is used up)
-        const unsigned long long need = __ballot(!active);
+        const unsigned long long need = lane_mask(!active);
         if (need) {
             if (win >= win_end) {
                 const int first = __ffsll((long long)need) - 1;
