@@ -128,3 +128,40 @@ def test_past_the_depth_cap(capped):
     print(f"past the cap: phi {ep.max():.2e} E {ee.max():.2e}; cap hits {st['cap_hits']}")
     assert np.all(np.isfinite(phi)) and np.all(np.isfinite(E))
     assert ep.max() <= 1e-12 and np.all(ee <= tol)
+
+
+def test_wide_near_levels():
+    """Near threshold 10 and points 1e-4 .. 1e-2 L above one equilateral triangle and one
+    square: deep subdivisions whose levels hold more near nodes than a wavefront's level
+    store (128).  At level 4 every one of a triangle's 256 children lies within 10 child
+    sizes (10 L / 16 = 0.625 L) of a point above it (the farthest child centroid is under the
+    circumradius 0.577 L away), so the walk hands subtrees to single lanes there."""
+    rng = np.random.default_rng(31)
+    s = 0.8
+    tri = np.array([[0.0, 0.0, 0.0, s, 0.0, 0.0, 0.5 * s, 0.5 * np.sqrt(3.0) * s, 0.0]])
+    rect = np.array([[0.0, 0.0, 1.5, s, 0.0, 0.0, 0.0, s, 0.0]])
+    sigma = np.array([1.3, -0.7])
+    idx = np.repeat([0, 1], 40)
+    P, nrm, L = W.points_on_elements(tri, rect, idx, rng)
+    h = L * 10.0 ** rng.uniform(-4.0, -2.0, idx.size) * rng.choice([-1.0, 1.0], idx.size)
+    pts = P + h[:, None] * nrm
+    prm = oracle.params(33, 7, near_dr=10.0)
+    ref = oracle.evaluate(tri, rect, sigma, pts, prm, with_abs=True)
+    import torch
+
+    ctx = bemc.Context(0)
+    ctx.set_rules(33, 7, 10.0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(sigma)
+    tp = torch.tensor(np.ascontiguousarray(pts.T), device="cuda:0")
+    phi, E, rc = ctx.eval(tp, "fp64")
+    st = ctx.stats()
+    ctx.close()
+    # about 200 leaves per level over 8-15 levels for every pair
+    assert ref["stats"]["leaves"] > 1000 * ref["stats"]["near_pairs"]
+    assert rc == 0 and st["near_pairs"] == ref["stats"]["near_pairs"] and st["cap_hits"] == 0
+    assert abs(st["leaves"] - ref["stats"]["leaves"]) <= 1e-3 * ref["stats"]["leaves"]
+    ep, ee = errors(phi.cpu().numpy(), E.cpu().numpy().T, ref)
+    tol = np.maximum(1e-12, 2e-15 * L / np.abs(h))
+    print(f"wide levels: phi {ep.max():.2e} E {ee.max():.2e}; near {st['near_pairs']}, leaves {st['leaves']}")
+    assert ep.max() <= 1e-12 and np.all(ee <= tol)
