@@ -197,6 +197,32 @@ def test_other_near_thresholds(precision, near_dr, after_upload):
     assert ep.max() <= TOL[precision] and ee.max() <= TOL[precision]
 
 
+@pytest.mark.parametrize("max_depth", [0, 1, 3])
+def test_small_depth_caps(max_depth):
+    """Depth caps 0 (the rule on the whole element for every near pair), 1 and 3: both near
+    walks (a lane per pair, and a wavefront per pair for the points closest to an element)
+    stop there and apply the rule to the capped nodes, as the oracle does; leaves and capped
+    leaves match exactly."""
+    w = W.cylinder_workload(40, 30, 1200, n_points=1500, near_frac=0.3, seed=29)
+    ref = oracle.evaluate(w.tri, w.rect, w.sigma[0], w.points, oracle.params(33, 7, max_depth=max_depth),
+                          with_abs=True)
+    ctx = bemc.Context(0)
+    ctx.set_rules(33, 7, 3.0, max_depth)
+    ctx.upload_geometry(w.tri, w.rect)
+    ctx.upload_densities(w.sigma)
+    for prec in ("fp64", "mixed"):
+        phi, E, rc = run_gpu(ctx, w.points, prec)
+        st = ctx.stats()
+        assert rc == 0 and st["near_pairs"] == ref["stats"]["near_pairs"] > 0
+        assert st["max_depth"] == ref["stats"]["max_depth"] == max_depth
+        for k in ("leaves", "cap_hits"):
+            assert st[k] == ref["stats"][k], (k, st[k], ref["stats"][k])
+        ep, ee = nerr(phi, E, ref)
+        print(f"depth cap {max_depth} {prec}: phi {ep.max():.2e} E {ee.max():.2e}, cap hits {st['cap_hits']}")
+        assert ep.max() <= TOL[prec] and ee.max() <= TOL[prec]
+    ctx.close()
+
+
 @pytest.mark.parametrize("tri_rule,gl", [(4, 2), (7, 3), (12, 5), (19, 7), (33, 8)])
 def test_other_rules(tri_rule, gl):
     """Generic (run-time node count) kernels and every triangle table."""
