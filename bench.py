@@ -38,6 +38,7 @@ TRAFFIC_FILE = os.path.join(PROFILES, "hbm_counters_cylinder150k_nested200k.txt"
 VALU_FILE = os.path.join(PROFILES, "valu_counters_cylinder150k_nested200k.txt")
 TRACE_FILE = os.path.join(PROFILES, "kernel_trace_cylinder150k_nested200k.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1606_03743_amd", "csrc", "kernels.hip")
+PROBE_LIB = os.path.join(ROOT, "paper_1606_03743_amd", "libissue_probe.so")
 
 
 def log(msg):
@@ -85,6 +86,44 @@ def trace_avg_ms(prefix):
         if line.startswith(prefix):
             return float(line[86:].split()[1])
     return None
+
+
+def issue_rates():
+    """Issue rates measured on cuda:0 (wavefront instructions per second; csrc/issue_probe.hip),
+    or None without the probe library."""
+    if not os.path.exists(PROBE_LIB):
+        return None
+    import ctypes
+
+    import torch  # noqa: F401  (one HIP runtime per process: torch's)
+
+    lib = ctypes.CDLL(PROBE_LIB)
+    lib.issue_probe_rates.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    r = (ctypes.c_double * 6)()
+    if lib.issue_probe_rates(0, r) != 0:
+        return None
+    keys = ("fma_f64", "rsq_f64", "f64_one_rsq_in_nine", "fma_f32", "rsq_f32", "f32_one_rsq_in_nine")
+    return dict(zip(keys, [float(v) for v in r]))
+
+
+def issue_ceiling(rates, kernel, node_ints, far_ms):
+    """The node-interaction rate an FP64 kernel's instruction mix allows, from its committed VALU
+    counts per node interaction: the full-rate FP64 instructions at the measured FMA rate, each
+    reciprocal square root at its measured cost inside an FMA stream (9 / rate of the one-in-nine
+    stream - 8 / FMA rate).  None without the rates or with stale counters."""
+    f = profile_value(VALU_FILE, f"{kernel}_f64_lane_instructions_per_node_interaction")
+    tr = profile_value(VALU_FILE, f"{kernel}_trans_per_node_interaction")
+    if rates is None or f is None or tr is None:
+        return None
+    t_rsq = 9.0 / rates["f64_one_rsq_in_nine"] - 8.0 / rates["fma_f64"]
+    per_wave_interaction = (f - tr) / rates["fma_f64"] + tr * t_rsq
+    ceiling = 64.0 / per_wave_interaction
+    achieved = node_ints / (1e-3 * far_ms)
+    return {"node_interactions_per_s": ceiling, "achieved_node_interactions_per_s": achieved,
+            "frac": achieved / ceiling, "fp64_instructions_per_node_interaction": f,
+            "rsq_per_node_interaction": tr, "rates_wave_instructions_per_s": rates,
+            "note": "the rate the kernel's instructions allow at the issue rates measured on this device "
+                    "(probe kernels of independent chains): frac is the kernel's share of that ceiling"}
 
 
 def profiled(kernel, flops, far_ms, peak):
@@ -234,6 +273,8 @@ def main():
                       "near_kernel_ms": st["near_ms"], "G": G.cpu().numpy().T.copy()}
         log(f"gradient {prec} step done")
 
+    rates = issue_rates()
+    log(f"issue rates (wavefront instructions/s): {rates}")
     pairs = st64["pairs"]
     node_int = st64["node_interactions"]
     ms_step = 1e3 * dt64 / args.steps
@@ -269,6 +310,7 @@ def main():
                      "hbm_frac": None if traffic is None else traffic / far_avg_s / 1e9 / PEAK_HBM_GBPS,
                      "rocprof_avg_launch_ms": prof_ms,
                      "rocprof_frac": None if prof_ms is None else alg_flops / (1e-3 * prof_ms) / 1e12 / PEAK_FP64_TFLOPS,
+                     "issue_ceiling": issue_ceiling(rates, "far_fp64", node_int, 1e3 * far_avg_s),
                      "note": "achieved: algorithmic flops (20 per node interaction + 16 per pair) over the far "
                              "kernel's mean HIP-event time in this run; rocprof_frac: the same over the committed "
                              "kernel trace's average (profiling box)"},
@@ -312,6 +354,8 @@ def main():
                        "roofline": {"bound": "alu", "achieved": dr_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                     "frac": dr_ach / PEAK_FP64_TFLOPS,
                                     **profiled("far_dr_fp64", dr_flops, float(np.mean(fardr)), PEAK_FP64_TFLOPS),
+                                    "issue_ceiling": issue_ceiling(rates, "far_dr_fp64", stdr["node_interactions"],
+                                                                   float(np.mean(fardr))),
                                     "note": "20 flops per executed node interaction + 16 per pair"},
                        "mixed_value": pairs * side / dtdrm, "mixed_far_kernel_ms": float(np.mean(fardrm)),
                        "rules": "triangles 7/12/19/33 points for DR >= 100/25/10/3, rectangles Tables B2/B3/B4 "
@@ -411,6 +455,8 @@ def main():
                             "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                                          "frac": ach / peak,
                                          **profiled("colloc_" + prec, cflops, st["far_ms"], peak),
+                                         "issue_ceiling": None if prec != "fp64" else issue_ceiling(
+                                             rates, "colloc_fp64", st["node_interactions"], st["far_ms"]),
                                          "note": "11 flops per node interaction + 2 per pair and density"}}
         rows = np.random.default_rng(3).choice(wc.n_elements, 64, replace=False)
         cref = oracle.collocation(wc.tri, wc.rect, wc.sigma, rows=rows)

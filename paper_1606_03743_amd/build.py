@@ -18,6 +18,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbemc.so")
 SOURCES = ["kernels.hip", "order.hip", "near_order.hip", "noalloc.hip", "api.cpp", "server.cpp", "solver.cpp", "rules.cpp"]
+# measurement only (issue rates of the far kernels' instruction classes, read by the benchmark)
+PROBE_LIB = os.path.join(HERE, "libissue_probe.so")
+PROBE_SOURCE = "issue_probe.hip"
 ARCH = os.environ.get("BEMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -56,6 +59,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    # the issue-rate probe: a library of its own, so that the evaluation path does not carry it
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), "-x", "hip"] + common + ["-shared", "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"hipcc failed on {PROBE_SOURCE}:\n{msgs}")
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

@@ -109,3 +109,41 @@ def test_c_program_links_against_the_library(tmp_path, lib):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_issue_probe_library():
+    """The benchmark's issue-rate probe is a library of its own (not part of the boundary):
+    it loads without a GPU, exports its one entry point, rejects a null output, and libbemc.so
+    does not carry it."""
+    probe = os.path.join(ROOT, "paper_1606_03743_amd", "libissue_probe.so")
+    if not os.path.exists(probe):
+        from paper_1606_03743_amd import build
+
+        build.build()
+    out = subprocess.run(["nm", "-D", "--defined-only", probe], capture_output=True, text=True, check=True).stdout
+    assert re.search(r" T issue_probe_rates$", out, re.M)
+    lib = ctypes.CDLL(probe)
+    lib.issue_probe_rates.argtypes = [ctypes.c_int, ctypes.c_void_p]
+    assert lib.issue_probe_rates(0, None) == -1
+    main = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    assert "issue_probe_rates" not in main
+
+
+@pytest.mark.gpu
+def test_issue_probe_rates_on_device():
+    """The probe measures positive rates; the FP64 reciprocal square root issues slower than
+    the FP64 FMA, and the one-in-nine stream lies between the two."""
+    import torch
+
+    assert torch.cuda.is_available()
+    probe = os.path.join(ROOT, "paper_1606_03743_amd", "libissue_probe.so")
+    lib = ctypes.CDLL(probe)
+    lib.issue_probe_rates.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    r = (ctypes.c_double * 6)()
+    assert lib.issue_probe_rates(0, r) == 0
+    fma64, rsq64, mix64, fma32, rsq32, mix32 = list(r)
+    print(f"issue rates: fma64 {fma64:.3e} rsq64 {rsq64:.3e} mix64 {mix64:.3e} "
+          f"fma32 {fma32:.3e} rsq32 {rsq32:.3e} mix32 {mix32:.3e}")
+    assert all(v > 1e9 for v in r)
+    assert rsq64 < fma64 and rsq64 < mix64 <= 1.05 * fma64
+    assert rsq32 < fma32
