@@ -562,7 +562,10 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     Elements el = elements();
     if (colloc) { el.q = d_qc; el.n_rhs = n_rhs_colloc; }
     const double* lpts = colloc ? d_cen : pts;
-    HIP_TRY(launch_zero_counters(W.ctr, s));
+    // the counters and the near stage's order clears in one launch (a list regrowth below
+    // reallocates the latter, and the near stage then clears them itself)
+    HIP_TRY(clear_call(W.ctr, W.nw, npts, s));
+    bool order_cleared = true;
     HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
     const bool read_count = near_grow && !noalloc;
     if (read_count) {
@@ -594,6 +597,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
             int rc = ensure_near_capacity(found);
             if (rc) return rc;
             if ((rc = ensure_near_work(npts, near_rows))) return rc;
+            order_cleared = false;
             HIP_TRY(launch_reset_near_count(W.ctr, s));
             HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
         }
@@ -606,7 +610,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     na.near_list = W.near; na.slot = W.nw.slot; na.order = W.nw.order; na.opair = W.nw.opair;
     na.walk_end = near_walk_end(W.nw); na.heavy_end = near_heavy_end(W.nw); na.deep = 1;
     na.res = W.nw.res;
-    HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, s));
+    HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, order_cleared, s));
     HIP_TRY(launch_near(na, mode, s));
     if (colloc) {
         HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, s));

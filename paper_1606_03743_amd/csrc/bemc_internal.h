@@ -211,9 +211,13 @@ hipError_t near_work_alloc(NearWork& w, int64_t n, unsigned long long pairs, int
 void near_work_free(NearWork& w);
 // regroup the list (length read from ctr) into per-point segments sorted by element, and
 // order the list indices by estimated subdivision cost (w.order) for the near kernel;
-// pts [3][n] are the field points of the list (the centroids for collocation)
+// pts [3][n] are the field points of the list (the centroids for collocation); cleared: w's
+// per-point counts and cursors and its buckets are zero already (clear_call), else cleared here
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
-                      const double* pts, const Elements& el, const NearWork& w, hipStream_t s);
+                      const double* pts, const Elements& el, const NearWork& w, bool cleared, hipStream_t s);
+// an evaluation's first launch: zeroes the counters and w's per-point counts and cursors (n
+// points) and its buckets, so that near_order need not
+hipError_t clear_call(DevCounters* ctr, const NearWork& w, int64_t n, hipStream_t s);
 // the final rows of a field or gradient evaluation, in one pass per point: the far field
 // (n_split > 1: K times the chunk partial sums partial[n_split][prow][n]; else far[rows][n])
 // plus the point's near-pair records, stored at perm[p] (or p) of row 0 in d0 and of row

@@ -205,6 +205,23 @@ __global__ void clear_order_kernel(uint32_t* __restrict__ buckets, uint32_t* __r
         for (int i = threadIdx.x; i < 3 * kCostClasses; i += kBlock) buckets[i] = 0u;
 }
 
+// An evaluation's first launch: its device counters, and the clears of the near stage's order
+// (per-point counts and cursors, per-class buckets), which nothing touches before that stage.
+__global__ void clear_call_kernel(DevCounters* __restrict__ ctr, uint32_t* __restrict__ buckets,
+                                  uint32_t* __restrict__ count, uint32_t* __restrict__ cursor, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        count[i] = 0u;
+        cursor[i] = 0u;
+    }
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < 3 * kCostClasses; i += kBlock) buckets[i] = 0u;
+        unsigned long long* c = reinterpret_cast<unsigned long long*>(ctr);
+        for (int i = threadIdx.x; i < (int)(sizeof(DevCounters) / sizeof(unsigned long long)); i += kBlock) c[i] = 0ull;
+    }
+}
+
 // The class of every list index and the per-class counts (per-workgroup histograms in LDS,
 // one global atomic per class and workgroup); the near pairs of each point.
 __global__ void cost_count_kernel(const NearPair* __restrict__ list, const DevCounters* __restrict__ ctr,
@@ -306,7 +323,16 @@ unsigned grid_for(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
+
 }  // namespace
+
+hipError_t clear_call(DevCounters* ctr, const NearWork& w, int64_t n, hipStream_t s)
+{
+    static_assert(sizeof(DevCounters) % sizeof(unsigned long long) == 0, "counters are 64-bit words");
+    clear_call_kernel<<<grid_for(std::max<int64_t>(n, 1)), kBlock, 0, s>>>(ctr, w.buckets, w.count, w.cursor,
+                                                                           std::max<int64_t>(n, 0));
+    return hipGetLastError();
+}
 
 void near_work_free(NearWork& w)
 {
@@ -352,15 +378,15 @@ size_t near_scan_temp_bytes(int64_t n)
 }
 
 hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned long long cap, int64_t n,
-                      const double* pts, const Elements& el, const NearWork& w, hipStream_t s)
+                      const double* pts, const Elements& el, const NearWork& w, bool cleared, hipStream_t s)
 {
     static_assert(kBlock == kCostClasses, "one thread per cost class");
     if (n <= 0) {  // no pairs: the walk's share (near_walk_end) is empty
-        clear_order_kernel<<<1, kBlock, 0, s>>>(w.buckets, w.count, w.cursor, 0);
+        if (!cleared) clear_order_kernel<<<1, kBlock, 0, s>>>(w.buckets, w.count, w.cursor, 0);
         return hipGetLastError();
     }
     const unsigned lgrid = grid_for((int64_t)std::min<unsigned long long>(cap, 1ull << 40));
-    clear_order_kernel<<<grid_for(n), kBlock, 0, s>>>(w.buckets, w.count, w.cursor, n);
+    if (!cleared) clear_order_kernel<<<grid_for(n), kBlock, 0, s>>>(w.buckets, w.count, w.cursor, n);
     cost_count_kernel<<<lgrid, kBlock, 0, s>>>(list, ctr, cap, pts, n, el, w.cost, w.buckets, w.count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -363,7 +363,7 @@ bool Server::near_stage(Slot& s, std::string& err)
     na.visit_limit = 1ll << 22;
     // d_out = the far field (the element-chunk partial sums, or d_far with one chunk) + the near
     // field; both stay, so a repeated near stage starts from them again
-    hipError_t e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, s.stream);
+    hipError_t e = near_order(s.d_near, s.d_ctr, s.near_cap, n, s.d_pts, env_.el, s.nw, false, s.stream);
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess)
         e = near_finish(s.nw, n, kNearEval, 4, s.n_split > 1 ? s.d_partial : nullptr, s.n_split, 4, s.d_far, K,
