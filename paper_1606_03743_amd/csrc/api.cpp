@@ -166,6 +166,7 @@ int noalloc_set(int device, NoAllocSet** out)
 // small ring of them lets evaluations be in flight while the host goes on.
 struct CallRec {
     DevCounters* h_ctr = nullptr;   // counters at the end of the call (pinned)
+    DevCounters* d_ctr = nullptr;   // h_ctr's device address: the call's last kernel writes it
     DevCounters* h_list = nullptr;  // counters after the near-pair list pass (pinned)
     hipEvent_t ev_list = nullptr, ev_far0 = nullptr, ev_far1 = nullptr, ev_near1 = nullptr, ev_done = nullptr;
     bool pending = false;
@@ -490,7 +491,7 @@ int bemc_context::drain()
 //   near-pair list (near_list_kernel: classification with box culling, compaction);
 //   far field (near pairs excluded by the same test), element-chunk reduction;
 //   near-list regrouping, FP64 near field, ordered per-point sums, unordering;
-//   counters to pinned host memory.
+//   counters to pinned host memory (written by the last kernel).
 // Growing list (default): the host reads the list pass's pair count after the far field is
 // enqueued and, if the list was too short, grows it and repeats the list pass (never the
 // far field), then enqueues the near field and returns.  Fixed list, and the buffers of the
@@ -613,16 +614,18 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, order_cleared, s));
     HIP_TRY(launch_near(na, mode, s));
     if (colloc) {
-        HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, s));
+        HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, W.ctr, R.d_ctr, s));
     } else {
         // far field (chunk sums) + near sums, back to the caller's order, in one pass
         const int orows = grad ? 6 : (user_E ? 4 : 1);
         HIP_TRY(near_finish(W.nw, npts, mode, orows, n_split > 1 ? W.partial : nullptr, n_split, (int)rows,
                             W.ow.res, fa.K, ordered ? W.ow.perm : nullptr, user_phi, grad ? user_phi + n : user_E,
-                            s));
+                            W.ctr, R.d_ctr, s));
     }
     HIP_TRY(hipEventRecord(R.ev_near1, s));
-    HIP_TRY(hipMemcpyAsync(R.h_ctr, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    // the counters: written by that last kernel into the pinned record (one launch fewer per
+    // call), else copied here
+    if (!R.d_ctr) HIP_TRY(hipMemcpyAsync(R.h_ctr, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(R.ev_done, s));
     R.pending = true;
     R.mode = mode;
@@ -671,6 +674,8 @@ int bemc_create(int device, bemc_handle* out)
             bemc_destroy(h);
             return fail(BEMC_E_OUT_OF_MEMORY, "pinned counter buffers");
         }
+        // without a device address the host copies the counters itself
+        if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r.d_ctr), r.h_ctr, 0) != hipSuccess) r.d_ctr = nullptr;
         for (hipEvent_t* e : { &r.ev_list, &r.ev_far0, &r.ev_far1, &r.ev_near1, &r.ev_done })
             if (hipEventCreate(e) != hipSuccess) { bemc_destroy(h); return fail(BEMC_E_DEVICE, "hipEventCreate"); }
     }

@@ -222,9 +222,11 @@ hipError_t clear_call(DevCounters* ctr, const NearWork& w, int64_t n, hipStream_
 // (n_split > 1: K times the chunk partial sums partial[n_split][prow][n]; else far[rows][n])
 // plus the point's near-pair records, stored at perm[p] (or p) of row 0 in d0 and of row
 // r >= 1 in d1 + (r - 1) n
+// ctr_out (device address of pinned host memory, or null): the call's counters ctr are copied
+// there by the same launch, after every other kernel of the call
 hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const double* partial, int n_split,
                        int prow, const double* far, double K, const uint32_t* perm, double* d0, double* d1,
-                       hipStream_t s);
+                       const DevCounters* ctr, DevCounters* ctr_out, hipStream_t s);
 // entries of w.order that the subdivision walk takes (device pointer; set by near_order)
 inline const uint32_t* near_walk_end(const NearWork& w) { return w.buckets + kCostClasses + kOnElementClass; }
 // entries of w.order with deep subdivisions (all classes from kDeepClass up come first)
@@ -232,7 +234,8 @@ inline const uint32_t* near_heavy_end(const NearWork& w) { return w.buckets + kC
 // add each point's segment of per-pair result records to its outputs (collocation; field and
 // gradient evaluations use near_finish)
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s);
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, const DevCounters* ctr,
+                       DevCounters* ctr_out, hipStream_t s);
 constexpr unsigned long long kMaxNearPairs = 0xffffffffull;  // 32-bit segment offsets
 
 // Allocation-free evaluation (noalloc.hip): a static device array per GPU, carved into the

@@ -55,6 +55,18 @@ __global__ void rank_sort_kernel(const uint32_t* __restrict__ start, const uint3
     }
 }
 
+// The call's counters, copied by the first threads of the last kernel of an evaluation into
+// the host's pinned record of the call (out: its device address; null: the host copies them).
+__device__ __forceinline__ void copy_counters(const DevCounters* __restrict__ ctr, DevCounters* __restrict__ out)
+{
+    constexpr int kWords = (int)(sizeof(DevCounters) / sizeof(unsigned long long));
+    if (out && blockIdx.x == 0 && threadIdx.x < kWords) {
+        reinterpret_cast<unsigned long long*>(out)[threadIdx.x] =
+            reinterpret_cast<const unsigned long long*>(ctr)[threadIdx.x];
+        __threadfence_system();
+    }
+}
+
 // Adds each point's near-pair results, in element order, to its far-field result.
 // mode kNearEval: records (phi, Ex, Ey, Ez) (already scaled); kNearGrad: records of the six
 // gradient rows (scaled); kNearColloc: one unscaled value per pair, multiplied here by
@@ -63,8 +75,10 @@ __global__ void reduce_pairs_kernel(const uint32_t* __restrict__ start, const ui
                                     int64_t n, const NearPair* __restrict__ sorted, const double* __restrict__ res,
                                     int mode, double* __restrict__ phi,
                                     double* __restrict__ E, double* __restrict__ G, const double* __restrict__ q,
-                                    int64_t ne, int n_rhs, double K)
+                                    int64_t ne, int n_rhs, double K, const DevCounters* __restrict__ ctr,
+                                    DevCounters* __restrict__ ctr_out)
 {
+    copy_counters(ctr, ctr_out);
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t s = start[p], k = count[p];
@@ -96,9 +110,11 @@ __global__ void finish_points_kernel(const uint32_t* __restrict__ start, const u
                                      int64_t n, const double* __restrict__ res, int rec, int rows, int prow,
                                      const double* __restrict__ partial, int n_split, const double* __restrict__ far,
                                      double K, const uint32_t* __restrict__ perm, double* __restrict__ d0,
-                                     double* __restrict__ d1)
+                                     double* __restrict__ d1, const DevCounters* __restrict__ ctr,
+                                     DevCounters* __restrict__ ctr_out)
 {
 #pragma clang fp contract(off)
+    copy_counters(ctr, ctr_out);
     // one thread per (row, point)
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= (int64_t)rows * n) return;
@@ -404,23 +420,24 @@ hipError_t near_order(const NearPair* list, const DevCounters* ctr, unsigned lon
 
 hipError_t near_finish(const NearWork& w, int64_t n, int mode, int rows, const double* partial, int n_split,
                        int prow, const double* far, double K, const uint32_t* perm, double* d0, double* d1,
-                       hipStream_t s)
+                       const DevCounters* ctr, DevCounters* ctr_out, hipStream_t s)
 {
     if (n <= 0 || rows <= 0) return hipSuccess;
     if (mode == kNearColloc) return hipErrorInvalidValue;
     const int64_t threads = (int64_t)rows * n;
     if ((threads + kBlock - 1) / kBlock > 0x7fffffff) return hipErrorInvalidValue;
     finish_points_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        w.start, w.count, n, w.res, mode == kNearGrad ? 6 : 4, rows, prow, partial, n_split, far, K, perm, d0, d1);
+        w.start, w.count, n, w.res, mode == kNearGrad ? 6 : 4, rows, prow, partial, n_split, far, K, perm, d0, d1,
+        ctr, ctr_out);
     return hipGetLastError();
 }
 
 hipError_t near_reduce(const NearWork& w, int64_t n, int mode, double* phi, double* E,
-                       double* G, const double* q, int64_t ne, int n_rhs, double K, hipStream_t s)
+                       double* G, const double* q, int64_t ne, int n_rhs, double K, const DevCounters* ctr, DevCounters* ctr_out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     reduce_pairs_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K);
+        w.start, w.count, n, w.sorted, w.res, mode, phi, E, G, q, ne, n_rhs, K, ctr, ctr_out);
     return hipGetLastError();
 }
 

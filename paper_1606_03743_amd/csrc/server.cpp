@@ -367,7 +367,7 @@ bool Server::near_stage(Slot& s, std::string& err)
     if (e == hipSuccess) e = launch_near(na, kNearEval, s.stream);
     if (e == hipSuccess)
         e = near_finish(s.nw, n, kNearEval, 4, s.n_split > 1 ? s.d_partial : nullptr, s.n_split, 4, s.d_far, K,
-                        nullptr, s.d_out, s.d_out + n, s.stream);
+                        nullptr, s.d_out, s.d_out + n, s.d_ctr, nullptr, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)n * 4 * 8, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_ctr, s.d_ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
