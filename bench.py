@@ -439,7 +439,14 @@ def main():
         colloc = {}
         for prec in ("fp64", "mixed"):
             res = cctx.collocation(sig, prec)
+            # a product that forms its near stage (setting the rules again ends the reuse)
+            cctx.set_rules()
             torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = cctx.collocation(sig, prec, out=res)
+            torch.cuda.synchronize()
+            dt_first = time.perf_counter() - t0
+            # the next product reuses it (as every product of a solve after the first)
             t0 = time.perf_counter()
             res = cctx.collocation(sig, prec, out=res)
             torch.cuda.synchronize()
@@ -449,7 +456,12 @@ def main():
             cflops = COLLOC_FLOP_PER_NODE_INT * st["node_interactions"] + 2 * rhs * st["pairs"]
             peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
             ach = cflops / (1e-3 * st["far_ms"]) / 1e12
-            colloc[prec] = {"ms": 1e3 * dt, "pairs_per_s": st["pairs"] / dt, "near_pairs": st["near_pairs"],
+            colloc[prec] = {"ms": 1e3 * dt, "ms_forming_near_stage": 1e3 * dt_first,
+                            "timing_note": "ms: a product after another with the same geometry and rules, which "
+                                           "reuses its near-pair list and near records (every product of a "
+                                           "solve after the first); ms_forming_near_stage: a product that "
+                                           "lists, orders and walks the near pairs itself",
+                            "pairs_per_s": st["pairs"] / dt, "near_pairs": st["near_pairs"],
                             "far_kernel_ms": st["far_ms"], "near_kernel_ms": st["near_ms"],
                             "node_interactions": st["node_interactions"],
                             "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",

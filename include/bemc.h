@@ -226,7 +226,12 @@ int bemc_eval_gradient(bemc_handle h, const double* pts, int64_t n, int precisio
  * densities sigma[r][:], r < n_rhs (1..8), for every element i.  sigma and out are device
  * arrays [n_rhs][n_E].  The element's own contribution is its exact on-element integral;
  * neighbours below near_dr are subdivided in FP64.  precision as in bemc_eval (far pairs
- * only).  Independent of the densities of bemc_upload_densities.  Asynchronous like
+ * only).  Independent of the densities of bemc_upload_densities.  The near part depends
+ * on the geometry and the rules only (it is formed for unit densities): consecutive
+ * products on one context reuse the near-pair list and the near records of the first one,
+ * until the geometry, the rules or the near-pair capacity change or a field or gradient
+ * evaluation runs on the context; bemc_query_stats then repeats that product's near-field
+ * counts, and its near time covers only the sums with the new densities.  Asynchronous like
  * bemc_eval.  Errors: NO_GEOMETRY, INVALID_ARG, LIMIT, OUT_OF_MEMORY, DEVICE. */
 int bemc_collocation_matvec(bemc_handle h, const double* sigma, int n_rhs, int precision,
                             double* out, void* stream);

@@ -202,6 +202,13 @@ struct bemc_context {
     // evaluation buffers and the near-pair list policy
     EvalWork w{};
     bool near_grow = true;  // the list grows to each evaluation's near-pair count
+    // The collocation product's near stage depends on the geometry and the rules only (its
+    // records are unit-density potentials; the densities are applied when the sums are
+    // formed): after one product, the near-pair list, its order and those records stay in the
+    // work buffers, and the next product with the same geometry and rules reuses them.  Any
+    // change of geometry or rules, any reallocation of those buffers and any other evaluation
+    // on them ends this.
+    bool colloc_cached = false;
     int ensure_order(int64_t n);
     int ensure_near_capacity(unsigned long long need);
     int ensure_near_work(int64_t n, int rows);
@@ -340,6 +347,7 @@ void free_order(OrderWork& ow)
 
 void bemc_context::free_work()
 {
+    colloc_cached = false;
     free_order(w.ow);
     w.ow_cap = 0;
     dev_free(w.near);
@@ -381,6 +389,7 @@ int bemc_context::ensure_near_work(int64_t n, int rows)
     const unsigned long long pairs = std::max(w.near_cap, w.nw_pairs);
     const int nrw = std::max(rows, w.nw_rows);
     if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    colloc_cached = false;
     near_work_free(w.nw);
     w.nw_pts = 0;
     w.nw_pairs = 0;
@@ -400,6 +409,7 @@ int bemc_context::ensure_near_capacity(unsigned long long need)
     unsigned long long cap = std::max<unsigned long long>(need, 1ull << 20);
     cap = std::min(cap + cap / 4, kMaxNearPairs);
     if (drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    colloc_cached = false;
     dev_free(w.near);
     w.near_cap = 0;
     if (dev_alloc(&w.near, (size_t)cap) != hipSuccess) {
@@ -525,6 +535,10 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
         int rc = ensure_near_work(npts, near_rows);
         if (rc) return rc;
     }
+    // a field or gradient evaluation in these buffers overwrites the collocation near stage
+    const bool own_work = &W == &w;
+    if (!colloc && own_work) colloc_cached = false;
+    const bool reuse_near = colloc && own_work && colloc_cached;
     // element split: many more workgroups than resident slots, so that the dispatcher
     // balances the tail; the chunk partial sums are reduced in fixed order
     const int64_t blocks = (npts + 511) / 512;  // nominal 512 points per workgroup (256-768 in fact)
@@ -564,11 +578,14 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     if (colloc) { el.q = d_qc; el.n_rhs = n_rhs_colloc; }
     const double* lpts = colloc ? d_cen : pts;
     // the counters and the near stage's order clears in one launch (a list regrowth below
-    // reallocates the latter, and the near stage then clears them itself)
-    HIP_TRY(clear_call(W.ctr, W.nw, npts, s));
+    // reallocates the latter, and the near stage then clears them itself); a collocation
+    // product that reuses the near stage keeps the counters of the product that formed it
     bool order_cleared = true;
-    HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
-    const bool read_count = near_grow && !noalloc;
+    if (!reuse_near) {
+        HIP_TRY(clear_call(W.ctr, W.nw, npts, s));
+        HIP_TRY(launch_near_list(lpts, npts, el, W.near, W.near_cap, W.ctr, s));
+    }
+    const bool read_count = near_grow && !noalloc && !reuse_near;
     if (read_count) {
         HIP_TRY(hipMemcpyAsync(R.h_list, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(R.ev_list, s));
@@ -590,7 +607,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     // (field and gradient: the chunks are added with the near sums at the end)
     if (n_split > 1 && colloc) HIP_TRY(launch_reduce_chunks(W.partial, n_split, rows, npts, fa.K, phi, s));
 
-    if (near_grow && !noalloc) {
+    if (read_count) {
         // the far field runs meanwhile; the list pass finished long before it
         HIP_TRY(hipEventSynchronize(R.ev_list));
         const unsigned long long found = R.h_list->near_count;
@@ -611,8 +628,10 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     na.near_list = W.near; na.slot = W.nw.slot; na.order = W.nw.order; na.opair = W.nw.opair;
     na.walk_end = near_walk_end(W.nw); na.heavy_end = near_heavy_end(W.nw); na.deep = 1;
     na.res = W.nw.res;
-    HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, order_cleared, s));
-    HIP_TRY(launch_near(na, mode, s));
+    if (!reuse_near) {
+        HIP_TRY(near_order(W.near, W.ctr, W.near_cap, npts, lpts, el, W.nw, order_cleared, s));
+        HIP_TRY(launch_near(na, mode, s));
+    }
     if (colloc) {
         HIP_TRY(near_reduce(W.nw, npts, mode, phi, E, G, el.q, ne, n_rhs_colloc, fa.K, W.ctr, R.d_ctr, s));
     } else {
@@ -627,6 +646,7 @@ int bemc_context::run(int mode, const double* pts, int64_t n, int precision, int
     // call), else copied here
     if (!R.d_ctr) HIP_TRY(hipMemcpyAsync(R.h_ctr, W.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(R.ev_done, s));
+    if (colloc && own_work) colloc_cached = true;  // later products are ordered after this one
     R.pending = true;
     R.mode = mode;
     R.pairs = npts * ne;
@@ -718,6 +738,7 @@ int bemc_set_rules(bemc_handle h, int tri_rule, int rect_gl_n, double near_dr, i
 {
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
     if (h->server) return fail(BEMC_E_INVALID_ARG, "rules cannot change while serving");
+    h->colloc_cached = false;
     // the far-field sums expand r^2 about the element's centroid, whose rounding is bounded
     // for DR >= 2 (in FP32 by about 9 ulp of r^2)
     if (!(near_dr >= 2.0) || !std::isfinite(near_dr)) return fail(BEMC_E_INVALID_ARG, "near_dr must be >= 2");
@@ -758,6 +779,7 @@ int bemc_upload_geometry(bemc_handle h, const double* tri, int64_t n_tri, const 
 {
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
     if (h->server) return fail(BEMC_E_INVALID_ARG, "geometry cannot change while serving");
+    h->colloc_cached = false;
     if (n_tri < 0 || n_rect < 0) return fail(BEMC_E_INVALID_ARG, "negative element count");
     if ((n_tri > 0 && !tri) || (n_rect > 0 && !rect)) return fail(BEMC_E_INVALID_ARG, "null geometry pointer");
     const int64_t ne = n_tri + n_rect;
@@ -1019,6 +1041,7 @@ int bemc_set_dr_rules(bemc_handle h, int enable, const double* tri_dr, const dou
 {
     if (!h) return fail(BEMC_E_INVALID_ARG, "null handle");
     if (h->server) return fail(BEMC_E_INVALID_ARG, "rules cannot change while serving");
+    h->colloc_cached = false;
     double t[3] = { 100.0, 25.0, 10.0 }, r[3] = { 150.0, 40.0, 15.0 };
     if (tri_dr) std::copy(tri_dr, tri_dr + 3, t);
     if (rect_dr) std::copy(rect_dr, rect_dr + 3, r);
@@ -1043,6 +1066,7 @@ int bemc_set_near_capacity(bemc_handle h, int64_t pairs, int grow)
     if ((unsigned long long)pairs > kMaxNearPairs) return fail(BEMC_E_LIMIT, "capacity above 2^32 - 1 pairs");
     HIP_TRY(hipSetDevice(h->device));
     if (h->drain()) return fail(BEMC_E_DEVICE, "an earlier evaluation failed");
+    h->colloc_cached = false;
     dev_free(h->w.near);
     h->w.near_cap = 0;
     if (dev_alloc(&h->w.near, (size_t)pairs) != hipSuccess) {

@@ -388,6 +388,57 @@ def test_collocation_matvec(nested, precision):
     assert err.max() <= TOL[precision]
 
 
+def test_collocation_reuses_its_near_stage(nested):
+    """Consecutive products on one context reuse the first one's near-pair list and near
+    records (unit-density potentials): products with other densities match the oracle and a
+    fresh context bit for bit, also after a field evaluation in between (which ends the
+    reuse) and after a change of the near threshold (which forms the near stage anew)."""
+    torch = torch_mod()
+    tri, rect, sig, ref = nested
+    ne = sig.shape[1]
+    s8 = torch.tensor(sig, dtype=torch.float64, device="cuda:0")
+    s2 = torch.tensor(sig[[4, 1]] * 3.0, dtype=torch.float64, device="cuda:0")
+
+    def fresh(s, near_dr=3.0):
+        c = bemc.Context(0)
+        c.set_rules(33, 7, near_dr)
+        c.upload_geometry(tri, rect)
+        o = c.collocation(s, precision="fp64").cpu().numpy()
+        st = c.stats()
+        c.close()
+        return o, st
+
+    want8, st8 = fresh(s8)
+    want2, _ = fresh(s2)
+    ctx = bemc.Context(0)
+    ctx.upload_geometry(tri, rect)
+    ctx.upload_densities(sig[0])
+    first = ctx.collocation(s8, precision="fp64").cpu().numpy()
+    again = ctx.collocation(s2, precision="fp64").cpu().numpy()  # reuses the near stage
+    st = ctx.stats()
+    assert np.array_equal(first, want8) and np.array_equal(again, want2)
+    for k in ("near_pairs", "leaves", "on_surface"):
+        assert st[k] == st8[k], k
+    ref2 = oracle.collocation(tri, rect, sig[[4, 1]] * 3.0)
+    assert (np.abs(again - ref2["out"]) / ref2["abs"]).max() <= 1e-12
+    # a field evaluation overwrites the buffers; the next product forms its near stage again
+    pts = torch.tensor(np.ascontiguousarray(W.shell_points(300, 0.5, 3.0, np.random.default_rng(4)).T),
+                       device="cuda:0")
+    ctx.eval(pts, "fp64")
+    after_eval = ctx.collocation(s2, precision="fp64").cpu().numpy()
+    mixed = ctx.collocation(s8, precision="mixed").cpu().numpy()  # reuses it, mixed far field
+    assert np.array_equal(after_eval, want2)
+    assert (np.abs(mixed - ref["out"]) / ref["abs"]).max() <= 1e-6
+    # another near threshold: the near stage is formed anew, with more near pairs
+    ctx.set_rules(33, 7, 4.0)
+    wider = ctx.collocation(s8, precision="fp64").cpu().numpy()
+    st4 = ctx.stats()
+    ctx.close()
+    want4, st4_fresh = fresh(s8, 4.0)
+    assert np.array_equal(wider, want4) and st4["near_pairs"] == st4_fresh["near_pairs"] > st8["near_pairs"]
+    assert wider.shape == (8, ne)
+
+
 # ------------------------------------------------------------ full-size sampled ----
 def test_full_size_cylinder_sampled():
     """The benchmark workload at full size (150,000 elements, 1,000,000 points) in the
