@@ -694,8 +694,12 @@ int bemc_create(int device, bemc_handle* out)
             bemc_destroy(h);
             return fail(BEMC_E_OUT_OF_MEMORY, "pinned counter buffers");
         }
-        // without a device address the host copies the counters itself
-        if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r.d_ctr), r.h_ctr, 0) != hipSuccess) r.d_ctr = nullptr;
+        // without a device address the host copies the counters itself (and the failed call's
+        // error must not be reported by the next launch's hipGetLastError)
+        if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r.d_ctr), r.h_ctr, 0) != hipSuccess) {
+            r.d_ctr = nullptr;
+            (void)hipGetLastError();
+        }
         for (hipEvent_t* e : { &r.ev_list, &r.ev_far0, &r.ev_far1, &r.ev_near1, &r.ev_done })
             if (hipEventCreate(e) != hipSuccess) { bemc_destroy(h); return fail(BEMC_E_DEVICE, "hipEventCreate"); }
     }
